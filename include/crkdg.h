@@ -1,0 +1,177 @@
+/*
+ * crkdg.h -- C ABI of the MI355X (gfx950) compact Runge--Kutta discontinuous
+ * Galerkin (cRKDG) step library.
+ *
+ * Method: Chen, Sun and Xing, "The Runge--Kutta discontinuous Galerkin method
+ * with compact stencils for hyperbolic conservation laws" (arXiv 2307.06471).
+ * One time step (Section 2.2, equation (crkdg)):
+ *     u^(1) = u^n,
+ *     u^(i) = u^n - dt sum_{j<i} a_ij  loc(u^(j)),      i = 2..s  (inner stages)
+ *     u^{n+1} = u^n - dt sum_i b_i DG(u^(i))                    (final stage)
+ * where loc is the element-local projected derivative of equation (dxl) and
+ * DG the DG operator of equation (DG operator) with a Lax--Friedrichs (or, for
+ * linear advection, upwind) face flux.  Boundary data enter only the final
+ * stage (Section 3.4).  A limiter is applied once per step, after the final
+ * stage (Section 2.2, remark on limiters; Section 4.2).
+ *
+ * Conventions
+ *  - Ownership: all device memory (DOFs, workspace, flags, MLP parameters) is
+ *    allocated by the caller (for instance PyTorch) and passed as raw device
+ *    pointers; the library never allocates or frees device memory.  The
+ *    handle owns host metadata only.
+ *  - Streams: every call is ordered on the stream given to crkdg_bind.  Only
+ *    calls that return a value on the host (marked "syncs") wait for it.
+ *  - Canonical DOF layout (host exchange and the FP64 device layout):
+ *    u[comp][mode][cell], cell = j*nx + i (x fastest), tensor Legendre basis
+ *    phi_mode = P_m(xi) P_n(eta), mode = m + (k+1) n (1D: mode = m); mode 0 is
+ *    the cell average.  Components: advection 1; 1D Euler (rho, rho w, E);
+ *    2D Euler (rho, rho u, rho v, E), gamma from the mesh.
+ *  - Mixed-precision layout (CRKDG_FP32_MIXED): the DOF buffer holds the
+ *    cell averages avg[comp][cell] in FP64 followed by the higher modes
+ *    hi[comp][mode-1][cell] in FP32.  Conversion happens in set/get_state.
+ *  - Errors: every int-returning call returns CRKDG_OK (0) or a negative code;
+ *    crkdg_strerror maps it to text.  Kernel launch failures return
+ *    CRKDG_EHIP.  Invalid arguments never reach a kernel.
+ */
+#ifndef CRKDG_H
+#define CRKDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CRKDG_OK 0
+#define CRKDG_EINVAL (-1)        /* bad argument (k, tableau, dt, sizes, null) */
+#define CRKDG_EUNSUPPORTED (-2)  /* valid but not built (e.g. upwind flux for Euler) */
+#define CRKDG_ENONPHYSICAL (-3)  /* a cell average has rho <= 0 or p <= 0 or NaN */
+#define CRKDG_EHIP (-4)          /* HIP runtime or launch failure */
+#define CRKDG_EUNBOUND (-5)      /* state used before crkdg_bind */
+
+enum { CRKDG_EQ_ADVECTION = 0, CRKDG_EQ_EULER = 1 };
+enum { CRKDG_FLUX_UPWIND = 0, CRKDG_FLUX_LLF = 1 };
+enum { CRKDG_BC_PERIODIC = 0, CRKDG_BC_TRANSMISSIVE = 1, CRKDG_BC_DIRICHLET = 2 };
+enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1 };
+enum { CRKDG_OP_LOC = 0, CRKDG_OP_DG = 1 };
+
+/* initial conditions / exact solutions known to the library */
+enum {
+  CRKDG_IC_CONST = 0,       /* params: conserved state                                   */
+  CRKDG_IC_ADV_SIN = 1,     /* 1D sin(x - a t); 2D sin(pi(x - a t)) sin(pi(y - b t))       */
+  CRKDG_IC_EULER_WAVE = 2,  /* rho = 1 + 0.2 sin(pi(x + y - (u+v) t)); params: u, v, p      */
+  CRKDG_IC_VORTEX = 3,      /* isentropic vortex; params: eps, xc, yc, Lx, Ly (exact at t) */
+  CRKDG_IC_QUADRANT = 4,    /* params: xs, ys, then (rho,u,v,p) for NE, NW, SW, SE        */
+  CRKDG_IC_SHOCK = 5        /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
+                               aux: cell-centre field xi[ny][nx] (device, FP64)          */
+};
+
+typedef struct {
+  int dim;                  /* 1 or 2 */
+  int nx, ny;               /* cells; ny = 1 when dim == 1 */
+  double x0, x1, y0, y1;    /* domain */
+  int bc[4];                /* x-left, x-right, y-bottom, y-top: CRKDG_BC_* */
+  double bc_state[4][4];    /* conserved ghost state on Dirichlet sides */
+  int bc_exact;             /* > 0: Dirichlet data = exact solution with this CRKDG_IC_*
+                               id, evaluated at the stage time t^n + c_i dt */
+  int equation;             /* CRKDG_EQ_* */
+  double adv[2];            /* advection velocity */
+  double gamma;             /* ratio of specific heats (Euler) */
+  int precision;            /* CRKDG_FP64 | CRKDG_FP32_MIXED */
+} crkdg_mesh;
+
+typedef struct crkdg_state crkdg_state;
+
+/* Create a handle (host only; no device work).  k = 0..3 polynomial degree
+ * (Q^k on rectangles, P^k in 1D; Section 2.1).  flux: CRKDG_FLUX_*.
+ * rk_stages selects the paper's tableaus: 1 forward Euler, 2 scheme (eq:2),
+ * 3 scheme (eq:3), 4 classical RK4 (Section 2.2 and Section 4).
+ * Returns CRKDG_EINVAL for bad sizes/arguments, CRKDG_EUNSUPPORTED for an
+ * unsupported combination.  *out is set only on success. */
+int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out);
+
+/* Replace the tableau by an explicit one (Section 2.1, equation (butcher)):
+ * s <= 4 stages, A row-major s*s strictly lower triangular (a_ij = 0 for
+ * j >= i), b and c of length s; host arrays, copied.  sum(b) need not be 1. */
+int crkdg_set_tableau(crkdg_state* st, int s, const double* c, const double* A, const double* b);
+
+/* bytes of the DOF buffer and of the workspace for the chosen layout */
+size_t crkdg_state_bytes(const crkdg_state* st);
+size_t crkdg_workspace_bytes(const crkdg_state* st);
+
+/* Bind caller-owned device memory: dofs (crkdg_state_bytes, 256-byte aligned)
+ * holds u^n; work (crkdg_workspace_bytes, 256-byte aligned) holds the second
+ * state buffer, the stage states and reduction scratch.  stream is a
+ * hipStream_t (NULL = default stream).  The current state may afterwards
+ * live in either buffer (double buffering); crkdg_current_dofs tells which. */
+int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream);
+void* crkdg_current_dofs(const crkdg_state* st);
+
+/* host <-> device state in the canonical FP64 layout; set/get are
+ * stream-ordered; get_state syncs */
+int crkdg_set_state(crkdg_state* st, const double* host_dofs);
+int crkdg_get_state(const crkdg_state* st, double* host_dofs);
+/* time t^n used for time-dependent boundary data */
+int crkdg_set_time(crkdg_state* st, double t);
+double crkdg_get_time(const crkdg_state* st);
+
+/* L2 projection of an initial condition with (k+3) Gauss points per
+ * direction into the current state (device kernel; aux: device FP64 or NULL) */
+int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
+                  const double* aux_dev);
+
+/* One cRKDG step of size dt (> 0, finite), Section 2.2 equation (crkdg); no
+ * limiter.  Advances the internal time by dt. */
+int crkdg_step(crkdg_state* st, double dt);
+/* Same, with dt read from device memory (written by crkdg_compute_dt); no
+ * host synchronisation.  The internal time is not advanced. */
+int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
+
+/* dt = cfl / max_K [ (|u|+c)/dx + (|v|+c)/dy ] from the FP64 cell averages
+ * (advection: |a|/dx + |b|/dy), written to device memory (one double).
+ * Stream-ordered, no sync.  The paper gives CFL numbers only (Section 4);
+ * this wave-speed formula is the build's reading. */
+int crkdg_compute_dt(crkdg_state* st, double cfl, double* dt_dev);
+/* s_max of the formula above, returned on the host (syncs) */
+int crkdg_max_wavespeed(crkdg_state* st, double* s_max_host);
+
+/* TVB minmod limiter applied once after the final stage (Section 2.2 remark
+ * on limiters; Section 4.2): troubled-cell test in characteristic variables
+ * with constant M (threshold M h^2), limited P1 reconstruction of troubled
+ * cells with every other non-mean mode zeroed, cell averages unchanged, then
+ * an FP64 positivity check of rho and p at the operator's quadrature points
+ * (demotion to P1, then P0).  flags_dev (uint8 per cell, may be NULL):
+ * 0 untouched, 1 troubled, 2 demoted to P1, 3 demoted to P0.  If
+ * n_flagged_host is not NULL the call syncs and returns the count there.
+ * Returns CRKDG_ENONPHYSICAL (after syncing) only when n_flagged_host is
+ * given and a cell average is non-physical. */
+int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagged_host);
+
+/* L1, L2 (unnormalised integrals over the domain) and Linf errors of
+ * component comp against exact solution ic at time t, (k+3)^dim Gauss points
+ * per cell; out on host (syncs).  Deterministic two-pass reduction. */
+int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, double t,
+                int comp, double out_l1_l2_linf[3]);
+/* sum over cells of |K| * cell average of component comp (syncs) */
+int crkdg_total(crkdg_state* st, int comp, double* out_host);
+
+/* Operator-level entry points (materialised path; general tableaus):
+ * out = loc(in) or DG(in) at boundary-data time t_bc (device arrays in the
+ * state's layout, FP64 layout only). */
+int crkdg_apply_op(crkdg_state* st, int op, const void* in_dev, void* out_dev, double t_bc);
+/* RK stage combination out = base + sum_j coef_j X_j, j < n <= 4 (device
+ * arrays of crkdg_state_bytes each, FP64 layout only). */
+int crkdg_combine(crkdg_state* st, void* out_dev, const void* base_dev, int n,
+                  const double* coef, const void* const* X_dev);
+
+/* Host-only: the library's own n-point Gauss--Legendre rule (n = 1..6). */
+int crkdg_gauss_rule(int n, double* x, double* w);
+
+void crkdg_destroy(crkdg_state* st);
+const char* crkdg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

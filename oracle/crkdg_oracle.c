@@ -636,11 +636,18 @@ static double tvb_minmod(double a, double b, double c, double Mh2) {
   return minmod3(a, b, c);
 }
 
+/* distance of the modified-minmod decision from a tie: the TVB threshold,
+ * a sign change of a nonzero argument, or |a| against |b|, |c|.  An argument
+ * that is exactly zero is a difference of identical cell averages and stays
+ * exactly zero under any rounding of the characteristic projection, so it
+ * is not a tie. */
 static double margin_of(double a, double b, double c, double Mh2) {
   double r = fabs(fabs(a) - Mh2);
-  double t[5] = {fabs(a), fabs(b), fabs(c), fabs(fabs(a) - fabs(b)), fabs(fabs(a) - fabs(c))};
-  if (fabs(a) > Mh2)
-    for (int i = 0; i < 5; ++i) if (t[i] < r) r = t[i];
+  if (fabs(a) > Mh2) {
+    double t[5] = {fabs(a), fabs(b), fabs(c), fabs(fabs(a) - fabs(b)), fabs(fabs(a) - fabs(c))};
+    for (int i = 0; i < 5; ++i)
+      if (t[i] != 0.0 && t[i] < r) r = t[i];
+  }
   return r;
 }
 

@@ -1,0 +1,273 @@
+"""Thin ctypes binding of libcrkdg.so (include/crkdg.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  The functions
+keep the C names; `Solver` is a small convenience wrapper that owns the
+torch buffers of one handle.
+
+The library must have been built (paper_2307_06471_amd/build.py); there is
+no fallback: a missing library or a call without a HIP device raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libcrkdg.so")
+
+CRKDG_OK, CRKDG_EINVAL, CRKDG_EUNSUPPORTED, CRKDG_ENONPHYSICAL, CRKDG_EHIP, CRKDG_EUNBOUND = \
+    0, -1, -2, -3, -4, -5
+EQ_ADVECTION, EQ_EULER = 0, 1
+FLUX_UPWIND, FLUX_LLF = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
+FP64, FP32_MIXED = 0, 1
+OP_LOC, OP_DG = 0, 1
+IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
+
+
+class crkdg_mesh(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("bc", C.c_int * 4), ("bc_state", (C.c_double * 4) * 4), ("bc_exact", C.c_int),
+        ("equation", C.c_int), ("adv", C.c_double * 2), ("gamma", C.c_double),
+        ("precision", C.c_int),
+    ]
+
+
+class CrkdgError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+_LIB = None
+EXPORTS = {}
+
+
+def _sig():
+    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+    return {
+        "crkdg_create": (C.c_int, [C.POINTER(crkdg_mesh), C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+        "crkdg_set_tableau": (C.c_int, [vp, C.c_int, dp, dp, dp]),
+        "crkdg_state_bytes": (sz, [vp]),
+        "crkdg_workspace_bytes": (sz, [vp]),
+        "crkdg_bind": (C.c_int, [vp, vp, vp, vp]),
+        "crkdg_current_dofs": (vp, [vp]),
+        "crkdg_set_state": (C.c_int, [vp, dp]),
+        "crkdg_get_state": (C.c_int, [vp, dp]),
+        "crkdg_set_time": (C.c_int, [vp, C.c_double]),
+        "crkdg_get_time": (C.c_double, [vp]),
+        "crkdg_project": (C.c_int, [vp, C.c_int, dp, C.c_int, vp]),
+        "crkdg_step": (C.c_int, [vp, C.c_double]),
+        "crkdg_step_dev": (C.c_int, [vp, vp]),
+        "crkdg_compute_dt": (C.c_int, [vp, C.c_double, vp]),
+        "crkdg_max_wavespeed": (C.c_int, [vp, dp]),
+        "crkdg_limit": (C.c_int, [vp, C.c_double, vp, C.POINTER(C.c_int64)]),
+        "crkdg_error": (C.c_int, [vp, C.c_int, dp, C.c_int, C.c_double, C.c_int, dp]),
+        "crkdg_total": (C.c_int, [vp, C.c_int, dp]),
+        "crkdg_apply_op": (C.c_int, [vp, C.c_int, vp, vp, C.c_double]),
+        "crkdg_combine": (C.c_int, [vp, vp, vp, C.c_int, dp, C.POINTER(vp)]),
+        "crkdg_gauss_rule": (C.c_int, [C.c_int, dp, dp]),
+        "crkdg_destroy": (None, [vp]),
+        "crkdg_strerror": (C.c_char_p, [C.c_int]),
+    }
+
+
+def lib():
+    """Load libcrkdg.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run paper_2307_06471_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _sig().items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+            EXPORTS[name] = f
+        _LIB = L
+    return _LIB
+
+
+def strerror(code):
+    return lib().crkdg_strerror(code).decode()
+
+
+def _check(rc, what):
+    if rc != CRKDG_OK:
+        raise CrkdgError(rc, what)
+    return rc
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def crkdg_gauss_rule(n):
+    x, w = np.zeros(n), np.zeros(n)
+    _check(lib().crkdg_gauss_rule(n, _dp(x), _dp(w)), "crkdg_gauss_rule")
+    return x, w
+
+
+def make_mesh(dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(0, 0, 0, 0), bc_state=None,
+              bc_exact=0, equation=EQ_EULER, adv=(1.0, 0.0), gamma=1.4, precision=FP64):
+    m = crkdg_mesh()
+    m.dim, m.nx, m.ny = dim, nx, (ny if dim == 2 else 1)
+    m.x0, m.x1, m.y0, m.y1 = x0, x1, y0, y1
+    for i in range(4):
+        m.bc[i] = bc[i]
+    if bc_state is not None:
+        for s in range(4):
+            for c in range(len(bc_state[s])):
+                m.bc_state[s][c] = bc_state[s][c]
+    m.bc_exact = bc_exact
+    m.equation, m.gamma, m.precision = equation, gamma, precision
+    m.adv[0], m.adv[1] = adv
+    return m
+
+
+def crkdg_create(mesh, k, flux, rk_stages):
+    h = C.c_void_p()
+    _check(lib().crkdg_create(C.byref(mesh), k, flux, rk_stages, C.byref(h)), "crkdg_create")
+    return h
+
+
+class Solver:
+    """One cRKDG handle with its torch-owned device buffers."""
+
+    def __init__(self, mesh, k, flux, rk_stages, device="cuda", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the cRKDG library needs a HIP device")
+        self.torch = torch
+        self.mesh = mesh
+        self.k = k
+        self.dim = mesh.dim
+        self.ncomp = 1 if mesh.equation == EQ_ADVECTION else (4 if mesh.dim == 2 else 3)
+        self.nmodes = (k + 1) ** 2 if mesh.dim == 2 else k + 1
+        self.ncells = mesh.nx * (mesh.ny if mesh.dim == 2 else 1)
+        self.h = crkdg_create(mesh, k, flux, rk_stages)
+        L = lib()
+        self.state_bytes = L.crkdg_state_bytes(self.h)
+        self.work_bytes = L.crkdg_workspace_bytes(self.h)
+        self.dofs = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device=device)
+        self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        _check(L.crkdg_bind(self.h, self._aligned(self.dofs), self._aligned(self.work),
+                            C.c_void_p(self.stream.cuda_stream)), "crkdg_bind")
+
+    @staticmethod
+    def _aligned(t):
+        p = t.data_ptr()
+        return C.c_void_p((p + 255) // 256 * 256)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().crkdg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.ncomp, self.nmodes, self.ncells)
+
+    # -- the C entry points ---------------------------------------------
+    def crkdg_set_tableau(self, A, b, c):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        _check(lib().crkdg_set_tableau(self.h, len(b), _dp(c), _dp(A), _dp(b)), "crkdg_set_tableau")
+
+    def crkdg_set_state(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.size * 8 == self.state_bytes, (u.shape, self.state_bytes)
+        _check(lib().crkdg_set_state(self.h, _dp(u)), "crkdg_set_state")
+
+    def crkdg_get_state(self):
+        u = np.zeros(self.shape)
+        _check(lib().crkdg_get_state(self.h, _dp(u)), "crkdg_get_state")
+        return u
+
+    def crkdg_current_dofs(self):
+        return lib().crkdg_current_dofs(self.h)
+
+    def crkdg_set_time(self, t):
+        _check(lib().crkdg_set_time(self.h, t), "crkdg_set_time")
+
+    def crkdg_get_time(self):
+        return lib().crkdg_get_time(self.h)
+
+    def crkdg_project(self, ic, params=(), aux=None):
+        P = np.ascontiguousarray(params, dtype=np.float64) if len(params) else None
+        a = None if aux is None else C.c_void_p(aux.data_ptr())
+        _check(lib().crkdg_project(self.h, ic, _dp(P), 0 if P is None else P.size, a),
+               "crkdg_project")
+
+    def crkdg_step(self, dt):
+        _check(lib().crkdg_step(self.h, float(dt)), "crkdg_step")
+
+    def crkdg_step_dev(self, dt_tensor):
+        _check(lib().crkdg_step_dev(self.h, C.c_void_p(dt_tensor.data_ptr())), "crkdg_step_dev")
+
+    def crkdg_compute_dt(self, cfl, dt_tensor):
+        _check(lib().crkdg_compute_dt(self.h, float(cfl), C.c_void_p(dt_tensor.data_ptr())),
+               "crkdg_compute_dt")
+
+    def crkdg_max_wavespeed(self):
+        s = C.c_double()
+        _check(lib().crkdg_max_wavespeed(self.h, C.byref(s)), "crkdg_max_wavespeed")
+        return s.value
+
+    def crkdg_limit(self, M, flags=None, count=True):
+        n = C.c_int64(-1)
+        f = None if flags is None else C.c_void_p(flags.data_ptr())
+        rc = lib().crkdg_limit(self.h, float(M), f, C.byref(n) if count else None)
+        _check(rc, "crkdg_limit")
+        return n.value if count else None
+
+    def crkdg_error(self, ic, params=(), t=0.0, comp=0):
+        P = np.ascontiguousarray(params, dtype=np.float64) if len(params) else None
+        out = np.zeros(3)
+        _check(lib().crkdg_error(self.h, ic, _dp(P), 0 if P is None else P.size, float(t), comp,
+                                 _dp(out)), "crkdg_error")
+        return out
+
+    def crkdg_total(self, comp=0):
+        s = C.c_double()
+        _check(lib().crkdg_total(self.h, comp, C.byref(s)), "crkdg_total")
+        return s.value
+
+    def crkdg_apply_op(self, op, x, t_bc=0.0):
+        """x: torch float64 device tensor of the state's size; returns op(x)"""
+        out = self.torch.empty_like(x)
+        _check(lib().crkdg_apply_op(self.h, op, C.c_void_p(x.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), float(t_bc)), "crkdg_apply_op")
+        return out
+
+    def crkdg_combine(self, base, coefs, arrays):
+        out = self.torch.empty_like(arrays[0] if base is None else base)
+        n = len(arrays)
+        cf = np.ascontiguousarray(coefs, dtype=np.float64)
+        ptrs = (C.c_void_p * max(n, 1))(*[C.c_void_p(a.data_ptr()) for a in arrays])
+        _check(lib().crkdg_combine(self.h, C.c_void_p(out.data_ptr()),
+                                   None if base is None else C.c_void_p(base.data_ptr()), n,
+                                   _dp(cf), ptrs), "crkdg_combine")
+        return out
+
+    # -- helpers -------------------------------------------------------
+    def current_view(self):
+        """torch float64 view (ncomp, nmodes, ncells) of the current state"""
+        ptr = self.crkdg_current_dofs()
+        for buf in (self.dofs, self.work):
+            base = buf.data_ptr()
+            if base <= ptr < base + buf.numel():
+                off = ptr - base
+                n = self.ncomp * self.nmodes * self.ncells
+                return buf[off:off + 8 * n].view(self.torch.float64).view(self.shape)
+        raise RuntimeError("current state pointer outside the bound buffers")

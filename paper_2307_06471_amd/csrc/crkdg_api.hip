@@ -1,0 +1,459 @@
+// crkdg_api.hip -- host side of the cRKDG library: the C ABI declared in
+// include/crkdg.h.  Argument checking, tableau handling, buffer layout and
+// the launch sequence of one step (Section 2.2, equation (crkdg)).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "crkdg_internal.hpp"
+#include "dg_core.hpp"
+
+using namespace crk;
+
+struct crkdg_state {
+  crkdg_mesh mesh;
+  int k, flux, eq, nc, nb;
+  Geo geo;
+  PhysDev ph;
+  BCDev bc;
+  // tableau (Section 2.1, equation (butcher))
+  int s;
+  double A[MAXS][MAXS], b[MAXS], c[MAXS];
+  bool subdiag;  // a_ij = 0 unless j == i - 1: inner stages need one accumulator
+  // bound memory
+  bool bound;
+  char* dofs;
+  char* work;
+  hipStream_t stream;
+  int cur;  // 0: the current state is in dofs, 1: in the work buffer's first slot
+  double t;
+  size_t S;  // bytes of one state
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t SCRATCH = (size_t)RED_BLOCKS * 3 * sizeof(double) + 1024;
+
+size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+char* slot_ptr(const crkdg_state* st, int slot) {
+  // work layout: [state B][stage 1..3][L 0..2][scratch]
+  return st->work + (size_t)slot * round_up(st->S);
+}
+char* cur_ptr(const crkdg_state* st) { return st->cur ? slot_ptr(st, 0) : st->dofs; }
+char* nxt_ptr(const crkdg_state* st) { return st->cur ? st->dofs : slot_ptr(st, 0); }
+char* stage_ptr(const crkdg_state* st, int i) { return slot_ptr(st, i); }          // i = 1..3
+char* lbuf_ptr(const crkdg_state* st, int j) { return slot_ptr(st, MAXS + j); }    // j = 0..2
+char* scratch_ptr(const crkdg_state* st) { return slot_ptr(st, 2 * MAXS - 1); }
+
+void set_tableau_internal(crkdg_state* st, int s, const double* c, const double* A,
+                          const double* b) {
+  st->s = s;
+  memset(st->A, 0, sizeof st->A);
+  for (int i = 0; i < s; ++i) {
+    st->b[i] = b[i];
+    st->c[i] = c[i];
+    for (int j = 0; j < s; ++j) st->A[i][j] = A[i * s + j];
+  }
+  bool sub = true;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < i - 1; ++j)
+      if (st->A[i][j] != 0.0) sub = false;
+  st->subdiag = sub;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? CRKDG_OK : CRKDG_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* crkdg_strerror(int code) {
+  switch (code) {
+    case CRKDG_OK: return "ok";
+    case CRKDG_EINVAL: return "invalid argument";
+    case CRKDG_EUNSUPPORTED: return "unsupported configuration";
+    case CRKDG_ENONPHYSICAL: return "non-physical cell average (rho <= 0, p <= 0 or NaN)";
+    case CRKDG_EHIP: return "HIP runtime or kernel launch failure";
+    case CRKDG_EUNBOUND: return "state has no device memory bound";
+    default: return "unknown error";
+  }
+}
+
+int crkdg_gauss_rule(int n, double* x, double* w) {
+  if (n < 1 || n > 6 || !x || !w) return CRKDG_EINVAL;
+  for (int a = 0; a < n; ++a) {
+    x[a] = crk::gl_x(n, a);
+    w[a] = crk::gl_w(n, a);
+  }
+  return CRKDG_OK;
+}
+
+int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out) {
+  if (!mesh || !out) return CRKDG_EINVAL;
+  if (k < 0 || k > 3) return CRKDG_EINVAL;
+  if (mesh->dim != 1 && mesh->dim != 2) return CRKDG_EINVAL;
+  if (mesh->nx < 1 || mesh->ny < 1 || (mesh->dim == 1 && mesh->ny != 1)) return CRKDG_EINVAL;
+  if (!(mesh->x1 > mesh->x0) || (mesh->dim == 2 && !(mesh->y1 > mesh->y0))) return CRKDG_EINVAL;
+  if (rk_stages < 1 || rk_stages > 4) return CRKDG_EINVAL;
+  if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF) return CRKDG_EINVAL;
+  if (mesh->precision != CRKDG_FP64) return CRKDG_EUNSUPPORTED;
+  for (int sd = 0; sd < 4; ++sd)
+    if (mesh->bc[sd] < CRKDG_BC_PERIODIC || mesh->bc[sd] > CRKDG_BC_DIRICHLET) return CRKDG_EINVAL;
+  int eq;
+  if (mesh->equation == CRKDG_EQ_ADVECTION) {
+    eq = mesh->dim == 1 ? EQ_ADV1 : EQ_ADV2;
+  } else if (mesh->equation == CRKDG_EQ_EULER) {
+    if (mesh->dim != 2) return CRKDG_EUNSUPPORTED;
+    if (flux != CRKDG_FLUX_LLF) return CRKDG_EUNSUPPORTED;
+    if (!(mesh->gamma > 1.0)) return CRKDG_EINVAL;
+    eq = EQ_EULER2;
+  } else {
+    return CRKDG_EINVAL;
+  }
+  if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN) return CRKDG_EUNSUPPORTED;
+  crkdg_state* st = new (std::nothrow) crkdg_state();
+  if (!st) return CRKDG_EINVAL;
+  st->mesh = *mesh;
+  st->k = k;
+  st->flux = flux;
+  st->eq = eq;
+  st->nc = mesh->equation == CRKDG_EQ_ADVECTION ? 1 : 4;
+  st->nb = mesh->dim == 2 ? (k + 1) * (k + 1) : k + 1;
+  Geo& g = st->geo;
+  g.nx = mesh->nx;
+  g.ny = mesh->dim == 2 ? mesh->ny : 1;
+  g.N = (long long)g.nx * g.ny;
+  g.x0 = mesh->x0;
+  g.y0 = mesh->dim == 2 ? mesh->y0 : 0.0;
+  g.dx = (mesh->x1 - mesh->x0) / mesh->nx;
+  g.dy = mesh->dim == 2 ? (mesh->y1 - mesh->y0) / mesh->ny : 1.0;
+  g.inv_dx = 1.0 / g.dx;
+  g.inv_dy = 1.0 / g.dy;
+  st->ph.gamma = mesh->gamma;
+  st->ph.ax = mesh->adv[0];
+  st->ph.ay = mesh->adv[1];
+  st->ph.upwind = flux == CRKDG_FLUX_UPWIND;
+  for (int sd = 0; sd < 4; ++sd) {
+    st->bc.type[sd] = mesh->bc[sd];
+    for (int cc = 0; cc < 4; ++cc) st->bc.state[sd][cc] = mesh->bc_state[sd][cc];
+  }
+  if (mesh->dim == 1) st->bc.type[2] = st->bc.type[3] = CRKDG_BC_PERIODIC;
+  st->bc.exact = mesh->bc_exact;
+  memset(st->bc.params, 0, sizeof st->bc.params);
+  // tableaus named by the paper: forward Euler, (eq:2), (eq:3), classical RK4
+  static const double FE_A[1] = {0}, FE_b[1] = {1}, FE_c[1] = {0};
+  static const double E2_A[4] = {0, 0, 0.5, 0}, E2_b[2] = {0, 1}, E2_c[2] = {0, 0.5};
+  static const double E3_A[9] = {0, 0, 0, 1.0 / 3.0, 0, 0, 0, 2.0 / 3.0, 0},
+                      E3_b[3] = {0.25, 0, 0.75}, E3_c[3] = {0, 1.0 / 3.0, 2.0 / 3.0};
+  static const double R4_A[16] = {0, 0, 0, 0, 0.5, 0, 0, 0, 0, 0.5, 0, 0, 0, 0, 1, 0},
+                      R4_b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0},
+                      R4_c[4] = {0, 0.5, 0.5, 1};
+  switch (rk_stages) {
+    case 1: set_tableau_internal(st, 1, FE_c, FE_A, FE_b); break;
+    case 2: set_tableau_internal(st, 2, E2_c, E2_A, E2_b); break;
+    case 3: set_tableau_internal(st, 3, E3_c, E3_A, E3_b); break;
+    default: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
+  }
+  st->S = (size_t)st->nc * st->nb * g.N * sizeof(double);
+  st->bound = false;
+  st->cur = 0;
+  st->t = 0.0;
+  *out = st;
+  return CRKDG_OK;
+}
+
+int crkdg_set_tableau(crkdg_state* st, int s, const double* c, const double* A, const double* b) {
+  if (!st || !c || !A || !b || s < 1 || s > MAXS) return CRKDG_EINVAL;
+  for (int i = 0; i < s; ++i) {
+    if (!isfinite(b[i]) || !isfinite(c[i])) return CRKDG_EINVAL;
+    for (int j = 0; j < s; ++j) {
+      const double a = A[i * s + j];
+      if (!isfinite(a)) return CRKDG_EINVAL;
+      if (j >= i && a != 0.0) return CRKDG_EINVAL;  // explicit: strictly lower triangular
+    }
+  }
+  set_tableau_internal(st, s, c, A, b);
+  return CRKDG_OK;
+}
+
+size_t crkdg_state_bytes(const crkdg_state* st) { return st ? st->S : 0; }
+
+size_t crkdg_workspace_bytes(const crkdg_state* st) {
+  if (!st) return 0;
+  return (size_t)(2 * MAXS - 1) * round_up(st->S) + SCRATCH;
+}
+
+int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream) {
+  if (!st || !dofs_dev || !work_dev) return CRKDG_EINVAL;
+  if (((uintptr_t)dofs_dev % ALIGN) || ((uintptr_t)work_dev % ALIGN)) return CRKDG_EINVAL;
+  st->dofs = (char*)dofs_dev;
+  st->work = (char*)work_dev;
+  st->stream = (hipStream_t)stream;
+  st->bound = true;
+  st->cur = 0;
+  return CRKDG_OK;
+}
+
+void* crkdg_current_dofs(const crkdg_state* st) {
+  if (!st || !st->bound) return nullptr;
+  return cur_ptr(st);
+}
+
+int crkdg_set_state(crkdg_state* st, const double* host) {
+  if (!st || !host) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  hipError_t e = hipMemcpyAsync(cur_ptr(st), host, st->S, hipMemcpyHostToDevice, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_get_state(const crkdg_state* st, double* host) {
+  if (!st || !host) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  hipError_t e = hipMemcpyAsync(host, cur_ptr(st), st->S, hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_set_time(crkdg_state* st, double t) {
+  if (!st || !isfinite(t)) return CRKDG_EINVAL;
+  st->t = t;
+  return CRKDG_OK;
+}
+
+double crkdg_get_time(const crkdg_state* st) { return st ? st->t : NAN; }
+
+static int copy_params(crkdg_state* st, const double* params, int nparams, double* dst) {
+  memset(dst, 0, sizeof(double) * NPARAM);
+  if (nparams < 0 || nparams > NPARAM || (nparams > 0 && !params)) return CRKDG_EINVAL;
+  for (int e = 0; e < nparams; ++e) dst[e] = params[e];
+  (void)st;
+  return CRKDG_OK;
+}
+
+// small parameter blocks travel through the scratch area (stream-ordered)
+static int upload_params(crkdg_state* st, const double* P, double** dev) {
+  double* d = (double*)(scratch_ptr(st) + (size_t)RED_BLOCKS * 3 * sizeof(double));
+  hipError_t e = hipMemcpyAsync(d, P, sizeof(double) * NPARAM, hipMemcpyHostToDevice, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);  // P lives on the host stack
+  *dev = d;
+  return hip_rc(e);
+}
+
+int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
+                  const double* aux_dev) {
+  if (!st) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_SHOCK) return CRKDG_EINVAL;
+  if (ic == CRKDG_IC_SHOCK && !aux_dev) return CRKDG_EINVAL;
+  if ((ic == CRKDG_IC_EULER_WAVE || ic == CRKDG_IC_VORTEX || ic == CRKDG_IC_QUADRANT ||
+       ic == CRKDG_IC_SHOCK) && st->eq != EQ_EULER2)
+    return CRKDG_EINVAL;
+  double P[NPARAM];
+  int rc = copy_params(st, params, nparams, P);
+  if (rc) return rc;
+  double* Pd;
+  rc = upload_params(st, P, &Pd);
+  if (rc) return rc;
+  hipError_t e = launch_project(st->eq, st->k, st->ph, st->geo, ic, Pd, aux_dev, st->t,
+                                (double*)cur_ptr(st), st->stream);
+  return hip_rc(e);
+}
+
+// one step with dt from the host (dt_dev == NULL) or from device memory
+static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
+  const double* un = (const double*)cur_ptr(st);
+  double* unew = (double*)nxt_ptr(st);
+  hipError_t e = hipSuccess;
+  const int s = st->s;
+  FinalArgs fa{};
+  fa.base = un;
+  fa.out = unew;
+  fa.dt = dt;
+  fa.dt_ptr = dt_dev;
+  const double* stages[MAXS];
+  stages[0] = un;
+  if (s > 1 && st->subdiag) {
+    // all inner stages in one element-local pass
+    InnerArgs ia{};
+    ia.un = un;
+    ia.s = s;
+    ia.dt = dt;
+    ia.dt_ptr = dt_dev;
+    ia.store_mask = 0;
+    for (int i = 1; i < s; ++i) {
+      ia.a_sub[i] = st->A[i][i - 1];
+      ia.stage[i] = (double*)stage_ptr(st, i);
+      stages[i] = ia.stage[i];
+      if (st->b[i] != 0.0) ia.store_mask |= 1 << i;
+    }
+    // a stage with b_i == 0 is still needed by later stages only through the
+    // register chain, so it is not stored
+    e = launch_inner(st->eq, st->k, st->ph, st->geo, ia, st->stream);
+  } else if (s > 1) {
+    // general tableau: materialise L_j = loc(u^(j)) and combine
+    const long long n = (long long)(st->S / sizeof(double));
+    for (int i = 1; i < s && e == hipSuccess; ++i) {
+      double* Lj = (double*)lbuf_ptr(st, i - 1);
+      e = launch_loc(st->eq, st->k, st->ph, st->geo, stages[i - 1], Lj, st->stream);
+      if (e != hipSuccess) break;
+      double coef[MAXS];
+      const double* X[MAXS];
+      int nx = 0;
+      for (int j = 0; j < i; ++j) {
+        if (st->A[i][j] == 0.0) continue;
+        coef[nx] = dt_dev ? -st->A[i][j] : -dt * st->A[i][j];
+        X[nx] = (const double*)lbuf_ptr(st, j);
+        ++nx;
+      }
+      double* ui = (double*)stage_ptr(st, i);
+      e = launch_combine(n, ui, un, nx, coef, X, dt_dev, st->stream);
+      stages[i] = ui;
+    }
+  }
+  if (e != hipSuccess) return CRKDG_EHIP;
+  int ns = 0;
+  for (int i = 0; i < s; ++i) {
+    if (st->b[i] == 0.0) continue;
+    fa.st[ns] = stages[i];
+    fa.w[ns] = st->b[i];
+    fa.tst[ns] = st->t + st->c[i] * (dt_dev ? 0.0 : dt);
+    ++ns;
+  }
+  fa.ns = ns;
+  e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+  if (e != hipSuccess) return CRKDG_EHIP;
+  st->cur ^= 1;
+  return CRKDG_OK;
+}
+
+int crkdg_step(crkdg_state* st, double dt) {
+  if (!st) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (!isfinite(dt) || !(dt > 0.0)) return CRKDG_EINVAL;
+  int rc = step_impl(st, dt, nullptr);
+  if (rc == CRKDG_OK) st->t += dt;
+  return rc;
+}
+
+int crkdg_step_dev(crkdg_state* st, const double* dt_dev) {
+  if (!st || !dt_dev) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (st->bc.exact > 0) return CRKDG_EUNSUPPORTED;  // stage times need dt on the host
+  return step_impl(st, 0.0, dt_dev);
+}
+
+int crkdg_compute_dt(crkdg_state* st, double cfl, double* dt_dev) {
+  if (!st || !dt_dev || !isfinite(cfl) || !(cfl > 0.0)) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  double* partial = (double*)scratch_ptr(st);
+  hipError_t e = launch_wavespeed(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st),
+                                  partial, RED_BLOCKS, cfl, nullptr, dt_dev, st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
+  if (!st || !smax) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  double* partial = (double*)scratch_ptr(st);
+  double* res = partial + RED_BLOCKS * 2;
+  hipError_t e = launch_wavespeed(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st),
+                                  partial, RED_BLOCKS, 1.0, res, nullptr, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(smax, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagged) {
+  if (!st || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  unsigned long long* counters =
+      n_flagged ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
+  hipError_t e = launch_limit(st->eq, st->k, st->ph, st->geo, st->bc, M, (double*)cur_ptr(st),
+                              flags_dev, counters, st->stream);
+  if (e != hipSuccess) return CRKDG_EHIP;
+  if (n_flagged) {
+    unsigned long long h[2] = {0, 0};
+    e = hipMemcpyAsync(h, counters, sizeof h, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    if (e != hipSuccess) return CRKDG_EHIP;
+    *n_flagged = (int64_t)h[0];
+    if (h[1]) return CRKDG_ENONPHYSICAL;
+  }
+  return CRKDG_OK;
+}
+
+int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, double t, int comp,
+                double out[3]) {
+  if (!st || !out || comp < 0 || comp >= st->nc) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_QUADRANT) return CRKDG_EINVAL;
+  double P[NPARAM];
+  int rc = copy_params(st, params, nparams, P);
+  if (rc) return rc;
+  double* Pd;
+  rc = upload_params(st, P, &Pd);
+  if (rc) return rc;
+  double* partial = (double*)scratch_ptr(st);
+  double* res = (double*)(scratch_ptr(st) + SCRATCH - 256);
+  hipError_t e = launch_error(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st), ic, Pd,
+                              nullptr, t, comp, partial, RED_BLOCKS, res, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_total(crkdg_state* st, int comp, double* out) {
+  if (!st || !out || comp < 0 || comp >= st->nc) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  double* partial = (double*)scratch_ptr(st);
+  double* res = (double*)(scratch_ptr(st) + SCRATCH - 256);
+  hipError_t e = launch_total(st->eq, st->k, st->geo, (const double*)cur_ptr(st), comp, partial,
+                              RED_BLOCKS, res, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
+int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_bc) {
+  if (!st || !in || !out || (op != CRKDG_OP_LOC && op != CRKDG_OP_DG)) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (in == out) return CRKDG_EINVAL;
+  hipError_t e;
+  if (op == CRKDG_OP_LOC) {
+    e = launch_loc(st->eq, st->k, st->ph, st->geo, (const double*)in, (double*)out, st->stream);
+  } else {
+    // out = 0 - (-1) * DG(in)
+    FinalArgs fa{};
+    fa.base = nullptr;
+    fa.out = (double*)out;
+    fa.ns = 1;
+    fa.st[0] = (const double*)in;
+    fa.w[0] = 1.0;
+    fa.tst[0] = t_bc;
+    fa.dt = -1.0;
+    e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+  }
+  return hip_rc(e);
+}
+
+int crkdg_combine(crkdg_state* st, void* out, const void* base, int n, const double* coef,
+                  const void* const* X) {
+  if (!st || !out || n < 0 || n > MAXS || (n > 0 && (!coef || !X))) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  for (int j = 0; j < n; ++j)
+    if (!X[j] || !isfinite(coef[j])) return CRKDG_EINVAL;
+  const long long len = (long long)(st->S / sizeof(double));
+  const double* Xd[MAXS];
+  for (int j = 0; j < n; ++j) Xd[j] = (const double*)X[j];
+  return hip_rc(launch_combine(len, (double*)out, (const double*)base, n, coef, Xd, nullptr,
+                               st->stream));
+}
+
+void crkdg_destroy(crkdg_state* st) { delete st; }
+
+}  // extern "C"

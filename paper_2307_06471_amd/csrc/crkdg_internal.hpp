@@ -1,0 +1,83 @@
+// crkdg_internal.hpp -- types shared by the host API and the kernel launchers
+// of the cRKDG library (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/crkdg.h"
+
+namespace crk {
+
+constexpr int MAXS = 4;        // stages of the largest tableau
+constexpr int NPARAM = 24;     // initial-condition parameters passed to kernels
+
+struct Geo {
+  int nx, ny;
+  long long N;
+  double x0, y0, dx, dy, inv_dx, inv_dy;
+};
+
+struct BCDev {
+  int type[4];           // x-left, x-right, y-bottom, y-top
+  double state[4][4];    // Dirichlet conserved states
+  int exact;             // > 0: time-dependent Dirichlet data from this IC id
+  double params[NPARAM]; // its parameters
+};
+
+struct PhysDev {
+  double gamma, ax, ay;
+  int upwind;
+};
+
+// one equation/dimension/degree selection
+enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2 };
+
+struct InnerArgs {
+  const double* un;
+  double* stage[MAXS];   // stage[i] receives u^(i+1) (i >= 1) when bit i of store_mask is set
+  int s;
+  int store_mask;
+  double a_sub[MAXS];    // a_{i, i-1}
+  double dt;
+  const double* dt_ptr;  // if set, dt = *dt_ptr
+};
+
+struct FinalArgs {
+  const double* base;    // u^n (NULL: zero)
+  double* out;
+  int ns;
+  const double* st[MAXS];
+  double w[MAXS];        // b_i
+  double tst[MAXS];      // boundary-data time of each stage
+  double dt;
+  const double* dt_ptr;
+};
+
+// launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error
+hipError_t launch_inner(int eq, int k, const PhysDev& ph, const Geo& g, const InnerArgs& a,
+                        hipStream_t s);
+hipError_t launch_final(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
+                        const FinalArgs& a, hipStream_t s);
+hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
+                      double* out, hipStream_t s);
+hipError_t launch_combine(long long n, double* out, const double* base, int nx,
+                          const double* coef, const double* const* X, const double* dt_ptr,
+                          hipStream_t s);
+hipError_t launch_wavespeed(int eq, int k, const PhysDev& ph, const Geo& g, const double* u,
+                            double* partial, int nblocks, double cfl, double* smax_out,
+                            double* dt_out, hipStream_t s);
+hipError_t launch_error(int eq, int k, const PhysDev& ph, const Geo& g, const double* u, int ic,
+                        const double* params, const double* aux, double t, int comp,
+                        double* partial, int nblocks, double* out3, hipStream_t s);
+hipError_t launch_total(int eq, int k, const Geo& g, const double* u, int comp, double* partial,
+                        int nblocks, double* out, hipStream_t s);
+hipError_t launch_project(int eq, int k, const PhysDev& ph, const Geo& g, int ic,
+                          const double* params, const double* aux, double t, double* u,
+                          hipStream_t s);
+hipError_t launch_limit(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
+                        double M, double* u, uint8_t* flags, unsigned long long* counters,
+                        hipStream_t s);
+
+constexpr int RED_BLOCKS = 1024;  // blocks of the first reduction pass
+
+}  // namespace crk

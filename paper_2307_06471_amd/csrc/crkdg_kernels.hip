@@ -1,0 +1,1160 @@
+// crkdg_kernels.hip -- HIP kernels of the cRKDG step for gfx950 (FP64 path).
+//
+//   k_inner    all inner stages of one step, element local (Section 2.2,
+//              equation (crkdg), first line): one lane per cell, the whole
+//              stage chain in registers, no neighbour data, no boundary data.
+//   k_final2   final stage (equation (crkdg), second line): a 64x4 tile of
+//              cells per workgroup; stage traces are exchanged through LDS,
+//              every face flux is computed once per tile in canonical (+x/+y)
+//              orientation and the stage-weighted sum G = sum_i b_i F^(i)
+//              (equation (g)) is lifted into both neighbours with opposite
+//              signs, so the update is conservative (equation (avg)).
+//   k_final1   the same for 1D meshes.
+//   k_loc      one application of the local operator (materialised path).
+//   k_combine  RK stage combination, out = base + sum_j coef_j X_j (streaming).
+//   k_wave*    dt selection from the cell averages (max reduction).
+//   k_error*   L1/L2/Linf errors, deterministic two-pass reduction.
+//   k_project  L2 projection of an initial condition, (k+3)-point rule.
+//   k_limit    TVB minmod troubled-cell test and limited P1 reconstruction,
+//              in place (only a cell's own non-mean modes change).
+#include <math.h>
+
+#include "crkdg_internal.hpp"
+#include "dg_core.hpp"
+
+namespace crk {
+
+using R = double;
+
+// ---------------------------------------------------------------------------
+// state access in the canonical layout u[comp][mode][cell]
+// ---------------------------------------------------------------------------
+template <int NC, int NB>
+__device__ __forceinline__ void load_state(const double* __restrict__ p, long long N, long long cell,
+                                           R (&u)[NC][NB]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) u[c][b] = p[(long long)(c * NB + b) * N + cell];
+}
+template <int NC, int NB>
+__device__ __forceinline__ void store_state(double* __restrict__ p, long long N, long long cell,
+                                            const R (&u)[NC][NB]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) p[(long long)(c * NB + b) * N + cell] = u[c][b];
+}
+
+template <class EQ>
+__device__ __forceinline__ EQ make_eq(const PhysDev& ph);
+template <>
+__device__ __forceinline__ Euler2<R> make_eq<Euler2<R>>(const PhysDev& ph) {
+  Euler2<R> e;
+  e.gam = ph.gamma;
+  e.gm1 = ph.gamma - 1.0;
+  return e;
+}
+template <>
+__device__ __forceinline__ Adv<R, 1> make_eq<Adv<R, 1>>(const PhysDev& ph) {
+  Adv<R, 1> e;
+  e.ax = ph.ax;
+  e.ay = 0.0;
+  e.upwind = ph.upwind;
+  return e;
+}
+template <>
+__device__ __forceinline__ Adv<R, 2> make_eq<Adv<R, 2>>(const PhysDev& ph) {
+  Adv<R, 2> e;
+  e.ax = ph.ax;
+  e.ay = ph.ay;
+  e.upwind = ph.upwind;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// exact solutions / initial data (device side; used by projection, error
+// norms and time-dependent Dirichlet data)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void prim2cons(int dim, double gamma, double rho, double u, double v,
+                                          double p, double* q) {
+  if (dim == 1) {
+    q[0] = rho;
+    q[1] = rho * u;
+    q[2] = p / (gamma - 1.0) + 0.5 * rho * u * u;
+  } else {
+    q[0] = rho;
+    q[1] = rho * u;
+    q[2] = rho * v;
+    q[3] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+  }
+}
+
+__device__ __forceinline__ double periodic_offset(double d, double L) {
+  // representative of d modulo L in [-L/2, L/2)
+  double r = d - L * floor(d / L + 0.5);
+  return r;
+}
+
+template <class EQ>
+__device__ void exact_state(int ic, const double* P, const double* aux, const Geo& g,
+                            const PhysDev& ph, double x, double y, double t, double* q) {
+  constexpr int dim = EQ::DIM;
+  switch (ic) {
+    case CRKDG_IC_CONST:
+      for (int c = 0; c < EQ::NC; ++c) q[c] = P[c];
+      return;
+    case CRKDG_IC_ADV_SIN:
+      if (dim == 1)
+        q[0] = sin(x - ph.ax * t);
+      else
+        q[0] = sin(M_PI * (x - ph.ax * t)) * sin(M_PI * (y - ph.ay * t));
+      return;
+    case CRKDG_IC_EULER_WAVE: {
+      const double u = P[0], v = P[1], p = P[2];
+      const double rho = dim == 1 ? 1.0 + 0.2 * sin(M_PI * (x - u * t))
+                                  : 1.0 + 0.2 * sin(M_PI * (x + y - (u + v) * t));
+      prim2cons(dim, ph.gamma, rho, u, v, p, q);
+      return;
+    }
+    case CRKDG_IC_VORTEX: {
+      const double eps = P[0], gm = ph.gamma;
+      const double xr = periodic_offset(x - P[1] - t, P[3]);
+      const double yr = periodic_offset(y - P[2] - t, P[4]);
+      const double r2 = xr * xr + yr * yr;
+      const double amp = eps / (2.0 * M_PI) * exp(0.5 * (1.0 - r2));
+      const double T = 1.0 - (gm - 1.0) * eps * eps / (8.0 * gm * M_PI * M_PI) * exp(1.0 - r2);
+      const double rho = pow(T, 1.0 / (gm - 1.0));
+      prim2cons(dim, gm, rho, 1.0 - amp * yr, 1.0 + amp * xr, rho * T, q);
+      return;
+    }
+    case CRKDG_IC_QUADRANT: {
+      const bool east = x >= P[0], north = y >= P[1];
+      const int quad = east ? (north ? 0 : 3) : (north ? 1 : 2);  // NE NW SW SE
+      const double* s = P + 2 + 4 * quad;
+      prim2cons(dim, ph.gamma, s[0], s[1], s[2], s[3], q);
+      return;
+    }
+    case CRKDG_IC_SHOCK: {
+      const double cth = cos(P[0]), sth = sin(P[0]);
+      if (cth * (x - P[4]) + sth * (y - P[5]) < 0.0) {
+        prim2cons(dim, ph.gamma, P[1], P[2] * cth, P[2] * sth, P[3], q);
+        return;
+      }
+      // bilinear interpolation of the cell-centre field, periodic wrap
+      const double fx = (x - g.x0) / g.dx - 0.5, fy = (y - g.y0) / g.dy - 0.5;
+      const double bx = floor(fx), by = floor(fy);
+      const double wx = fx - bx, wy = fy - by;
+      int i0 = (int)bx % g.nx; if (i0 < 0) i0 += g.nx;
+      int j0 = (int)by % g.ny; if (j0 < 0) j0 += g.ny;
+      const int i1 = i0 + 1 == g.nx ? 0 : i0 + 1, j1 = j0 + 1 == g.ny ? 0 : j0 + 1;
+      const double a00 = aux[(long long)j0 * g.nx + i0], a10 = aux[(long long)j0 * g.nx + i1];
+      const double a01 = aux[(long long)j1 * g.nx + i0], a11 = aux[(long long)j1 * g.nx + i1];
+      const double xi = (1.0 - wy) * ((1.0 - wx) * a00 + wx * a10) + wy * ((1.0 - wx) * a01 + wx * a11);
+      double rho = 1.0 + P[7] * xi;
+      if (rho < P[6]) rho = P[6];
+      prim2cons(dim, ph.gamma, rho, 0.0, 0.0, 1.0, q);
+      return;
+    }
+    default:
+      for (int c = 0; c < EQ::NC; ++c) q[c] = __builtin_nan("");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K1: inner stages (local operator only)
+// ---------------------------------------------------------------------------
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_inner(PhysDev ph, Geo g, InnerArgs a) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= g.N) return;
+  const EQ eq = make_eq<EQ>(ph);
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
+  R u[NC][NB];
+  load_state<NC, NB>(a.un, g.N, cell, u);
+#pragma unroll 1
+  for (int i = 1; i < a.s; ++i) {
+    R acc[NC][NB];
+    load_state<NC, NB>(a.un, g.N, cell, acc);
+    loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[i]), R(g.inv_dx), R(g.inv_dy), acc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
+    if ((a.store_mask >> i) & 1) store_state<NC, NB>(a.stage[i], g.N, cell, u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour traces and boundary ghosts for the final stage
+// ---------------------------------------------------------------------------
+// side: 0 left (want the neighbour's xi=+1 trace), 1 right (its xi=-1 trace),
+//       2 bottom (its eta=+1 trace), 3 top (its eta=-1 trace).
+// own: this cell's trace on the shared face (used by the transmissive rule).
+template <class EQ, int K, int SIDE>
+__device__ __forceinline__ void neighbour_trace(const EQ& eq, const PhysDev& ph, const Geo& g,
+                                                const BCDev& bc, const double* __restrict__ S,
+                                                int i, int j, double tb,
+                                                const R (&own)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1],
+                                                R (&out)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1]) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, NP = EQ::DIM == 2 ? K + 1 : 1;
+  int ni = i + (SIDE == 0 ? -1 : SIDE == 1 ? 1 : 0);
+  int nj = j + (SIDE == 2 ? -1 : SIDE == 3 ? 1 : 0);
+  const bool outside = ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny;
+  if (outside) {
+    const int type = bc.type[SIDE];
+    if (type == CRKDG_BC_TRANSMISSIVE) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) out[c][p] = own[c][p];
+      return;
+    }
+    if (type == CRKDG_BC_DIRICHLET) {
+      constexpr GTab<K + 1> T = Tab<K + 1>::t;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        double q[4];
+        if (bc.exact > 0) {
+          const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+          double x, y;
+          if (SIDE < 2) {
+            x = xc + (SIDE == 0 ? -0.5 : 0.5) * g.dx;
+            y = EQ::DIM == 2 ? yc + 0.5 * g.dy * T.X[p] : 0.0;
+          } else {
+            x = xc + 0.5 * g.dx * T.X[p];
+            y = yc + (SIDE == 2 ? -0.5 : 0.5) * g.dy;
+          }
+          exact_state<EQ>(bc.exact, bc.params, nullptr, g, ph, x, y, tb, q);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) q[c] = bc.state[SIDE][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c][p] = q[c];
+      }
+      return;
+    }
+    if (ni < 0) ni += g.nx;
+    if (ni >= g.nx) ni -= g.nx;
+    if (nj < 0) nj += g.ny;
+    if (nj >= g.ny) nj -= g.ny;
+  }
+  R U[NC][NB];
+  load_state<NC, NB>(S, g.N, (long long)nj * g.nx + ni, U);
+  if constexpr (SIDE == 0) trace_x<+1, EQ, K, R>(U, out);
+  if constexpr (SIDE == 1) trace_x<-1, EQ, K, R>(U, out);
+  if constexpr (SIDE == 2) trace_y<+1, EQ, K, R>(U, out);
+  if constexpr (SIDE == 3) trace_y<-1, EQ, K, R>(U, out);
+}
+
+// ---------------------------------------------------------------------------
+// K2 (2D): final stage on a 64x4 tile
+// ---------------------------------------------------------------------------
+constexpr int BX = 64, BY = 4;
+
+template <class EQ, int K>
+__global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, FinalArgs a) {
+  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q;
+  __shared__ R sR[NV][BY][BX + 1];   // [.][ty][tx+1]: right-face traces; [.][ty][0]: halo
+  __shared__ R sT[NV][BY + 1][BX];   // [.][ty+1][tx]: top-face traces;   [.][0][tx]: halo
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty;
+  const bool active = i < g.nx && j < g.ny;
+  const long long cell = (long long)j * g.nx + i;
+  const bool last_col = active && (tx == BX - 1 || i == g.nx - 1);
+  const bool last_row = active && (ty == BY - 1 || j == g.ny - 1);
+  const EQ eq = make_eq<EQ>(ph);
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
+
+  R acc[NC][NB];
+  R GL[NC][Q], GB[NC][Q], GR[NC][Q], GT[NC][Q];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) GL[c][p] = GB[c][p] = GR[c][p] = GT[c][p] = 0.0;
+  }
+  if (active && a.base) load_state<NC, NB>(a.base, g.N, cell, acc);
+
+#pragma unroll 1
+  for (int s = 0; s < a.ns; ++s) {
+    const double* __restrict__ S = a.st[s];
+    const R w = a.w[s];
+    R tL[NC][Q], tB[NC][Q], tRn[NC][Q], tTn[NC][Q];
+    if (active) {
+      R U[NC][NB];
+      load_state<NC, NB>(S, g.N, cell, U);
+      const R vs = R(0.5) * dt * w;
+      volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
+      R tR[NC][Q], tT[NC][Q];
+      trace_x<+1, EQ, K, R>(U, tR);
+      trace_x<-1, EQ, K, R>(U, tL);
+      trace_y<+1, EQ, K, R>(U, tT);
+      trace_y<-1, EQ, K, R>(U, tB);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          sR[c * Q + p][ty][tx + 1] = tR[c][p];
+          sT[c * Q + p][ty + 1][tx] = tT[c][p];
+        }
+      if (tx == 0) {
+        R h[NC][Q];
+        neighbour_trace<EQ, K, 0>(eq, ph, g, bc, S, i, j, a.tst[s], tL, h);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) sR[c * Q + p][ty][0] = h[c][p];
+      }
+      if (ty == 0) {
+        R h[NC][Q];
+        neighbour_trace<EQ, K, 2>(eq, ph, g, bc, S, i, j, a.tst[s], tB, h);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) sT[c * Q + p][0][tx] = h[c][p];
+      }
+      if (last_col) neighbour_trace<EQ, K, 1>(eq, ph, g, bc, S, i, j, a.tst[s], tR, tRn);
+      if (last_row) neighbour_trace<EQ, K, 3>(eq, ph, g, bc, S, i, j, a.tst[s], tT, tTn);
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        R qa[NC], qb[NC], F[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = sR[c * Q + p][ty][tx];
+          qb[c] = tL[c][p];
+        }
+        eq.template num_flux<0>(qa, qb, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) GL[c][p] = GL[c][p] + w * F[c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = sT[c * Q + p][ty][tx];
+          qb[c] = tB[c][p];
+        }
+        eq.template num_flux<1>(qa, qb, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) GB[c][p] = GB[c][p] + w * F[c];
+      }
+      if (last_col) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          R qa[NC], qb[NC], F[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            qa[c] = sR[c * Q + p][ty][tx + 1];
+            qb[c] = tRn[c][p];
+          }
+          eq.template num_flux<0>(qa, qb, F);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) GR[c][p] = GR[c][p] + w * F[c];
+        }
+      }
+      if (last_row) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          R qa[NC], qb[NC], F[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            qa[c] = sT[c * Q + p][ty + 1][tx];
+            qb[c] = tTn[c][p];
+          }
+          eq.template num_flux<1>(qa, qb, F);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) GT[c][p] = GT[c][p] + w * F[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // share the combined fluxes: a cell's right face is its right neighbour's left face
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        sR[c * Q + p][ty][tx] = GL[c][p];
+        sT[c * Q + p][ty][tx] = GB[c][p];
+      }
+  }
+  __syncthreads();
+  if (!active) return;
+  if (!last_col) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int p = 0; p < Q; ++p) GR[c][p] = sR[c * Q + p][ty][tx + 1];
+  }
+  if (!last_row) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int p = 0; p < Q; ++p) GT[c][p] = sT[c * Q + p][ty + 1][tx];
+  }
+  const R ls = R(-0.5) * dt;
+  lift_x<EQ, K, R>(GR, GL, ls * R(g.inv_dx), acc);
+  lift_y<EQ, K, R>(GT, GB, ls * R(g.inv_dy), acc);
+  store_state<NC, NB>(a.out, g.N, cell, acc);
+}
+
+// ---------------------------------------------------------------------------
+// K2 (1D): final stage on a row of 256 cells
+// ---------------------------------------------------------------------------
+constexpr int B1 = 256;
+
+template <class EQ, int K>
+__global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, FinalArgs a) {
+  constexpr int NC = EQ::NC, NB = K + 1;
+  __shared__ R sR[NC][B1 + 1];
+  const int tx = threadIdx.x;
+  const int i = blockIdx.x * B1 + tx;
+  const bool active = i < g.nx;
+  const bool last_col = active && (tx == B1 - 1 || i == g.nx - 1);
+  const EQ eq = make_eq<EQ>(ph);
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
+  R acc[NC][NB], GL[NC][1], GR[NC][1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
+    GL[c][0] = GR[c][0] = 0.0;
+  }
+  if (active && a.base) load_state<NC, NB>(a.base, g.N, i, acc);
+#pragma unroll 1
+  for (int s = 0; s < a.ns; ++s) {
+    const double* __restrict__ S = a.st[s];
+    const R w = a.w[s];
+    R tL[NC][1], tR[NC][1], tRn[NC][1];
+    if (active) {
+      R U[NC][NB];
+      load_state<NC, NB>(S, g.N, i, U);
+      volume_acc<EQ, K, R>(eq, U, dt * w * R(g.inv_dx), R(0), acc);
+      trace_x<+1, EQ, K, R>(U, tR);
+      trace_x<-1, EQ, K, R>(U, tL);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sR[c][tx + 1] = tR[c][0];
+      if (tx == 0) {
+        R h[NC][1];
+        neighbour_trace<EQ, K, 0>(eq, ph, g, bc, S, i, 0, a.tst[s], tL, h);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sR[c][0] = h[c][0];
+      }
+      if (last_col) neighbour_trace<EQ, K, 1>(eq, ph, g, bc, S, i, 0, a.tst[s], tR, tRn);
+    }
+    __syncthreads();
+    if (active) {
+      R qa[NC], qb[NC], F[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        qa[c] = sR[c][tx];
+        qb[c] = tL[c][0];
+      }
+      eq.template num_flux<0>(qa, qb, F);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) GL[c][0] = GL[c][0] + w * F[c];
+      if (last_col) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = tR[c][0];
+          qb[c] = tRn[c][0];
+        }
+        eq.template num_flux<0>(qa, qb, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) GR[c][0] = GR[c][0] + w * F[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sR[c][tx] = GL[c][0];
+  }
+  __syncthreads();
+  if (!active) return;
+  if (!last_col) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) GR[c][0] = sR[c][tx + 1];
+  }
+  lift_x<EQ, K, R>(GR, GL, R(-dt) * R(g.inv_dx), acc);
+  store_state<NC, NB>(a.out, g.N, i, acc);
+}
+
+// ---------------------------------------------------------------------------
+// local operator applied once: out = loc(in)
+// ---------------------------------------------------------------------------
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_loc(PhysDev ph, Geo g, const double* __restrict__ in,
+                                             double* __restrict__ out) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= g.N) return;
+  const EQ eq = make_eq<EQ>(ph);
+  R u[NC][NB], acc[NC][NB];
+  load_state<NC, NB>(in, g.N, cell, u);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
+  loc_acc<EQ, K, R>(eq, u, R(1), R(g.inv_dx), R(g.inv_dy), acc);
+  store_state<NC, NB>(out, g.N, cell, acc);
+}
+
+// ---------------------------------------------------------------------------
+// RK stage combination: out = base + sum_j (coef_j * dtscale) X_j
+// ---------------------------------------------------------------------------
+struct CombineArgs {
+  double* out;
+  const double* base;
+  const double* X[MAXS];
+  double coef[MAXS];
+  int n;
+  const double* dt_ptr;  // if set, every coefficient is multiplied by *dt_ptr
+};
+
+__global__ __launch_bounds__(256) void k_combine(long long n, CombineArgs a) {
+  // n doubles; pairs are processed as double2 (16-byte accesses), the odd
+  // tail element by the first thread
+  const double scale = a.dt_ptr ? *a.dt_ptr : 1.0;
+  double cf[MAXS];
+#pragma unroll
+  for (int j = 0; j < MAXS; ++j) cf[j] = a.coef[j] * scale;
+  const long long n2 = n / 2;
+  const double2* __restrict__ base = reinterpret_cast<const double2*>(a.base);
+  double2* __restrict__ out = reinterpret_cast<double2*>(a.out);
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n2;
+       e += (long long)gridDim.x * 256) {
+    double2 v = base ? base[e] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < MAXS; ++j) {
+      if (j < a.n) {
+        const double2 x = reinterpret_cast<const double2*>(a.X[j])[e];
+        v.x = v.x + cf[j] * x.x;
+        v.y = v.y + cf[j] * x.y;
+      }
+    }
+    out[e] = v;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const long long e = n - 1;
+    double v = a.base ? a.base[e] : 0.0;
+    for (int j = 0; j < a.n; ++j) v = v + cf[j] * a.X[j][e];
+    a.out[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = (w > v || w != w) ? w : v;  // propagate NaN
+  }
+  return v;
+}
+
+// deterministic block sum: fixed tree in LDS
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] = sh[t] + sh[t + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      const double w = sh[t + o];
+      if (w > sh[t] || w != w) sh[t] = w;
+    }
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <class EQ>
+__device__ __forceinline__ double cell_speed(const PhysDev& ph, const Geo& g, const double* q) {
+  if constexpr (EQ::EULER) {
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, v = q[2] * ir;
+    const double p = (ph.gamma - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+    const double c = sqrt(ph.gamma * p * ir);
+    return (fabs(u) + c) * g.inv_dx + (fabs(v) + c) * g.inv_dy;
+  } else {
+    return fabs(ph.ax) * g.inv_dx + (EQ::DIM == 2 ? fabs(ph.ay) * g.inv_dy : 0.0);
+  }
+}
+
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_wave_partial(PhysDev ph, Geo g, const double* __restrict__ u,
+                                                      double* __restrict__ partial) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (long long cell = (long long)blockIdx.x * 256 + threadIdx.x; cell < g.N;
+       cell += (long long)gridDim.x * 256) {
+    double q[4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = u[(long long)(c * NB) * g.N + cell];
+    const double s = cell_speed<EQ>(ph, g, q);
+    if (s > m || s != s) m = s;
+  }
+  m = block_max<256>(m, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_wave_final(const double* __restrict__ partial, int n, double cfl,
+                                                    double* smax_out, double* dt_out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const double w = partial[e];
+    if (w > m || w != w) m = w;
+  }
+  m = block_max<256>(m, sh);
+  if (threadIdx.x == 0) {
+    if (smax_out) *smax_out = m;
+    if (dt_out) *dt_out = cfl / m;
+  }
+}
+
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const double* __restrict__ u,
+                                                       int ic, const double* __restrict__ params,
+                                                       const double* __restrict__ aux, double t,
+                                                       int comp, double* __restrict__ partial) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, Q = K + 1, QE = K + 3;
+  constexpr int DIM = EQ::DIM;
+  constexpr GTab<QE> E = Tab<QE>::t;
+  __shared__ double sh[256];
+  double P[NPARAM];
+  for (int e = 0; e < NPARAM; ++e) P[e] = params[e];
+  double l1 = 0.0, l2 = 0.0, li = 0.0;
+  const double wscale = DIM == 2 ? 0.25 * g.dx * g.dy : 0.5 * g.dx;
+  for (long long cell = (long long)blockIdx.x * 256 + threadIdx.x; cell < g.N;
+       cell += (long long)gridDim.x * 256) {
+    const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+    const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+    double U[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) U[b] = u[(long long)(comp * NB + b) * g.N + cell];
+#pragma unroll
+    for (int a = 0; a < QE; ++a)
+#pragma unroll
+      for (int bq = 0; bq < (DIM == 2 ? QE : 1); ++bq) {
+        const double xi = E.X[a], eta = DIM == 2 ? E.X[bq] : 0.0;
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int m = b % Q, n = b / Q;
+          v += U[b] * leg(m, xi) * (DIM == 2 ? leg(n, eta) : 1.0);
+        }
+        double q[4];
+        exact_state<EQ>(ic, P, aux, g, ph, xc + 0.5 * g.dx * xi, yc + 0.5 * g.dy * eta, t, q);
+        const double e = fabs(v - q[comp]);
+        const double wq = wscale * E.W[a] * (DIM == 2 ? E.W[bq] : 1.0);
+        l1 += wq * e;
+        l2 += wq * e * e;
+        if (e > li || e != e) li = e;
+      }
+  }
+  l1 = block_sum<256>(l1, sh);
+  l2 = block_sum<256>(l2, sh);
+  li = block_max<256>(li, sh);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = l1;
+    partial[3 * blockIdx.x + 1] = l2;
+    partial[3 * blockIdx.x + 2] = li;
+  }
+}
+
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_total_partial(Geo g, const double* __restrict__ u, int comp,
+                                                       double* __restrict__ partial) {
+  constexpr int NB = Sizes<K, EQ::DIM>::NB;
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (long long cell = (long long)blockIdx.x * 256 + threadIdx.x; cell < g.N;
+       cell += (long long)gridDim.x * 256)
+    s += u[(long long)(comp * NB) * g.N + cell];
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// sums (stride 3 groups: l1, l2 summed, linf max) in a fixed order
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int n, int width,
+                                                   double scale, double* out) {
+  __shared__ double sh[256];
+  for (int q = 0; q < width; ++q) {
+    double s = 0.0;
+    const bool is_max = width == 3 && q == 2;
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const double w = partial[width * e + q];
+      if (is_max) {
+        if (w > s || w != w) s = w;
+      } else {
+        s += w;
+      }
+    }
+    s = is_max ? block_max<256>(s, sh) : block_sum<256>(s, sh);
+    if (threadIdx.x == 0) {
+      if (width == 3 && q == 1) s = sqrt(s);
+      out[q] = (width == 1) ? s * scale : s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2 projection of an initial condition with a (k+3)-point rule
+// ---------------------------------------------------------------------------
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_project(PhysDev ph, Geo g, int ic,
+                                                 const double* __restrict__ params,
+                                                 const double* __restrict__ aux, double t,
+                                                 double* __restrict__ u) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, Q = K + 1, QE = K + 3;
+  constexpr int DIM = EQ::DIM;
+  constexpr GTab<QE> E = Tab<QE>::t;
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= g.N) return;
+  double P[NPARAM];
+  for (int e = 0; e < NPARAM; ++e) P[e] = params[e];
+  const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+  const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+  double acc[NC][NB];
+  for (int c = 0; c < NC; ++c)
+    for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
+  for (int a = 0; a < QE; ++a)
+    for (int bq = 0; bq < (DIM == 2 ? QE : 1); ++bq) {
+      const double xi = E.X[a], eta = DIM == 2 ? E.X[bq] : 0.0;
+      const double wq = E.W[a] * (DIM == 2 ? E.W[bq] : 1.0);
+      double q[4];
+      exact_state<EQ>(ic, P, aux, g, ph, xc + 0.5 * g.dx * xi, yc + 0.5 * g.dy * eta, t, q);
+      for (int b = 0; b < NB; ++b) {
+        const int m = b % Q, n = b / Q;
+        const double ph_ = leg(m, xi) * (DIM == 2 ? leg(n, eta) : 1.0);
+        for (int c = 0; c < NC; ++c) acc[c][b] += wq * q[c] * ph_;
+      }
+    }
+  for (int c = 0; c < NC; ++c)
+    for (int b = 0; b < NB; ++b) {
+      const int m = b % Q, n = b / Q;
+      const double norm = DIM == 2 ? (2 * m + 1) * (2 * n + 1) / 4.0 : (2 * m + 1) / 2.0;
+      u[(long long)(c * NB + b) * g.N + cell] = acc[c][b] * norm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TVB minmod limiter, once per step after the final stage (in place)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double minmod3(double a, double b, double c) {
+  const bool pos = a > 0.0 && b > 0.0 && c > 0.0;
+  const bool neg = a < 0.0 && b < 0.0 && c < 0.0;
+  if (!(pos || neg)) return 0.0;
+  double m = fabs(a);
+  if (fabs(b) < m) m = fabs(b);
+  if (fabs(c) < m) m = fabs(c);
+  return pos ? m : -m;
+}
+__device__ __forceinline__ double tvb(double a, double b, double c, double Mh2) {
+  return fabs(a) <= Mh2 ? a : minmod3(a, b, c);
+}
+
+// left/right eigenvectors of the 2D Euler flux Jacobian in direction d at q
+// (L rows, R columns, row-major 4x4)
+__device__ void euler_eigvec(double gamma, const double* q, int d, double* L, double* Rm) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double q2 = u * u + v * v;
+  const double p = (gamma - 1.0) * (q[3] - 0.5 * q[0] * q2);
+  const double c = sqrt(gamma * p * ir);
+  const double H = (q[3] + p) * ir;
+  const double b1 = (gamma - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  const double un = d == 0 ? u : v, ut = d == 0 ? v : u;
+  // in the rotated frame (normal, tangential); map back to (x, y) columns
+  const int in = d == 0 ? 1 : 2, it = d == 0 ? 2 : 1;
+  double Rl[4][4] = {};
+  // columns: un - c, entropy, shear, un + c
+  Rl[0][0] = 1.0; Rl[in][0] = un - c; Rl[it][0] = ut; Rl[3][0] = H - un * c;
+  Rl[0][1] = 1.0; Rl[in][1] = un;     Rl[it][1] = ut; Rl[3][1] = 0.5 * q2;
+  Rl[0][2] = 0.0; Rl[in][2] = 0.0;    Rl[it][2] = 1.0; Rl[3][2] = ut;
+  Rl[0][3] = 1.0; Rl[in][3] = un + c; Rl[it][3] = ut; Rl[3][3] = H + un * c;
+  double Ll[4][4] = {};
+  Ll[0][0] = 0.5 * (b2 + un / c); Ll[0][in] = -0.5 * (b1 * un + 1.0 / c); Ll[0][it] = -0.5 * b1 * ut; Ll[0][3] = 0.5 * b1;
+  Ll[1][0] = 1.0 - b2;            Ll[1][in] = b1 * un;                  Ll[1][it] = b1 * ut;        Ll[1][3] = -b1;
+  Ll[2][0] = -ut;                 Ll[2][in] = 0.0;                      Ll[2][it] = 1.0;            Ll[2][3] = 0.0;
+  Ll[3][0] = 0.5 * (b2 - un / c); Ll[3][in] = -0.5 * (b1 * un - 1.0 / c); Ll[3][it] = -0.5 * b1 * ut; Ll[3][3] = 0.5 * b1;
+  for (int r = 0; r < 4; ++r)
+    for (int s = 0; s < 4; ++s) {
+      L[r * 4 + s] = Ll[r][s];
+      Rm[r * 4 + s] = Rl[r][s];
+    }
+}
+
+template <class EQ, int K>
+__device__ bool physical_points(const PhysDev& ph, const double (&U)[EQ::NC][Sizes<K, EQ::DIM>::NB]) {
+  if constexpr (!EQ::EULER) {
+    return true;
+  } else {
+    constexpr int Q = K + 1, NB = Q * Q;
+    constexpr GTab<Q> T = Tab<Q>::t;
+    auto ok = [&](double xi, double eta) {
+      double q[4];
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+        for (int b = 0; b < NB; ++b) s += U[c][b] * leg(b % Q, xi) * leg(b / Q, eta);
+        q[c] = s;
+      }
+      const double p = (ph.gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+      return q[0] > 0.0 && p > 0.0;
+    };
+    for (int a = 0; a < Q; ++a) {
+      for (int b = 0; b < Q; ++b)
+        if (!ok(T.X[a], T.X[b])) return false;
+      if (!ok(-1.0, T.X[a]) || !ok(1.0, T.X[a]) || !ok(T.X[a], -1.0) || !ok(T.X[a], 1.0))
+        return false;
+    }
+    return true;
+  }
+}
+
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, double M,
+                                               double* __restrict__ u, uint8_t* __restrict__ flags,
+                                               unsigned long long* __restrict__ counters) {
+  constexpr int NC = EQ::NC, DIM = EQ::DIM, Q = K + 1, NB = Sizes<K, DIM>::NB;
+  __shared__ unsigned int cnt[2];
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  uint8_t flag = 0;
+  bool bad = false;
+  if (cell < g.N) {
+    const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+    double U[NC][NB];
+    load_state<NC, NB>(u, g.N, cell, U);
+    double avg[NC];
+    for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
+    if constexpr (EQ::EULER) {
+      const double p = (ph.gamma - 1.0) * (avg[3] - 0.5 * (avg[1] * avg[1] + avg[2] * avg[2]) / avg[0]);
+      bad = !(avg[0] > 0.0) || !(p > 0.0);
+    }
+    // neighbour averages in direction d, side s (ghost rule of the boundary)
+    auto nbr_avg = [&](int d, int s, double* qa) {
+      int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
+      const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
+      if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
+        const int type = bc.type[side];
+        if (type == CRKDG_BC_TRANSMISSIVE) {
+          for (int c = 0; c < NC; ++c) qa[c] = avg[c];
+          return;
+        }
+        if (type == CRKDG_BC_DIRICHLET) {
+          for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
+          return;
+        }
+        ni = (ni + g.nx) % g.nx;
+        nj = (nj + g.ny) % g.ny;
+      }
+      for (int c = 0; c < NC; ++c) qa[c] = u[(long long)(c * NB) * g.N + (long long)nj * g.nx + ni];
+    };
+    auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
+    double dp[2][NC], dm[2][NC];
+    bool troubled = false;
+    if (K >= 1 && !bad) {
+      for (int d = 0; d < DIM; ++d) {
+        const double h = d == 0 ? g.dx : g.dy;
+        const double Mh2 = M * h * h;
+        double qn[NC], a[NC], at[NC];
+        nbr_avg(d, +1, qn);
+        for (int c = 0; c < NC; ++c) dp[d][c] = qn[c] - avg[c];
+        nbr_avg(d, -1, qn);
+        for (int c = 0; c < NC; ++c) dm[d][c] = avg[c] - qn[c];
+        for (int c = 0; c < NC; ++c) {
+          a[c] = 0.0;
+          at[c] = 0.0;
+          for (int deg = 1; deg <= K; ++deg) {
+            const double v = U[c][mode_of(d, deg)];
+            a[c] += v;
+            at[c] += (deg % 2) ? v : -v;
+          }
+        }
+        double ca[NC], cat[NC], cp[NC], cm[NC];
+        if constexpr (EQ::EULER) {
+          double L[16], Rm[16];
+          euler_eigvec(ph.gamma, avg, d, L, Rm);
+          for (int r = 0; r < NC; ++r) {
+            ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
+            for (int c = 0; c < NC; ++c) {
+              ca[r] += L[r * 4 + c] * a[c];
+              cat[r] += L[r * 4 + c] * at[c];
+              cp[r] += L[r * 4 + c] * dp[d][c];
+              cm[r] += L[r * 4 + c] * dm[d][c];
+            }
+          }
+        } else {
+          for (int c = 0; c < NC; ++c) {
+            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
+          }
+        }
+        for (int r = 0; r < NC; ++r)
+          if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r])
+            troubled = true;
+      }
+    }
+    auto reconstruct = [&](double (&V)[NC][NB]) {
+      double ns[2][NC];
+      for (int d = 0; d < DIM; ++d) {
+        const double h = d == 0 ? g.dx : g.dy;
+        const double Mh2 = M * h * h;
+        const int sm = mode_of(d, 1);
+        double sl[NC], pp[NC], mm[NC];
+        double qn[NC];
+        nbr_avg(d, +1, qn);
+        for (int c = 0; c < NC; ++c) pp[c] = qn[c] - avg[c];
+        nbr_avg(d, -1, qn);
+        for (int c = 0; c < NC; ++c) mm[c] = avg[c] - qn[c];
+        for (int c = 0; c < NC; ++c) sl[c] = U[c][sm];
+        if constexpr (EQ::EULER) {
+          double L[16], Rm[16], lim[NC];
+          euler_eigvec(ph.gamma, avg, d, L, Rm);
+          for (int r = 0; r < NC; ++r) {
+            double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int c = 0; c < NC; ++c) {
+              s1 += L[r * 4 + c] * sl[c];
+              s2 += L[r * 4 + c] * pp[c];
+              s3 += L[r * 4 + c] * mm[c];
+            }
+            lim[r] = tvb(s1, s2, s3, Mh2);
+          }
+          for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+            for (int r = 0; r < NC; ++r) s += Rm[c * 4 + r] * lim[r];
+            ns[d][c] = s;
+          }
+        } else {
+          for (int c = 0; c < NC; ++c) ns[d][c] = tvb(sl[c], pp[c], mm[c], Mh2);
+        }
+      }
+      for (int c = 0; c < NC; ++c) {
+        for (int b = 1; b < NB; ++b) V[c][b] = 0.0;
+        for (int d = 0; d < DIM; ++d) V[c][mode_of(d, 1)] = ns[d][c];
+      }
+    };
+    bool changed = false;
+    if (troubled) {
+      reconstruct(U);
+      flag = 1;
+      changed = true;
+    }
+    if constexpr (EQ::EULER) {
+      if (!bad && K >= 1 && !physical_points<EQ, K>(ph, U)) {
+        if (!troubled) reconstruct(U);
+        flag = 2;
+        changed = true;
+        if (!physical_points<EQ, K>(ph, U)) {
+          for (int c = 0; c < NC; ++c)
+            for (int b = 1; b < NB; ++b) U[c][b] = 0.0;
+          flag = 3;
+        }
+      }
+    }
+    if (changed)
+      for (int c = 0; c < NC; ++c)
+        for (int b = 1; b < NB; ++b) u[(long long)(c * NB + b) * g.N + cell] = U[c][b];
+    if (flags) flags[cell] = flag;
+  }
+  if (counters) {
+    if (flag) atomicAdd(&cnt[0], 1u);
+    if (bad) atomicAdd(&cnt[1], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (cnt[0]) atomicAdd(&counters[0], (unsigned long long)cnt[0]);
+      if (cnt[1]) atomicAdd(&counters[1], (unsigned long long)cnt[1]);
+    }
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <template <class, int> class F, class... A>
+hipError_t dispatch(int eq, int k, A&&... args) {
+  switch (eq * 4 + k) {
+    case EQ_ADV1 * 4 + 0: return F<Adv<R, 1>, 0>::run(args...);
+    case EQ_ADV1 * 4 + 1: return F<Adv<R, 1>, 1>::run(args...);
+    case EQ_ADV1 * 4 + 2: return F<Adv<R, 1>, 2>::run(args...);
+    case EQ_ADV1 * 4 + 3: return F<Adv<R, 1>, 3>::run(args...);
+    case EQ_ADV2 * 4 + 0: return F<Adv<R, 2>, 0>::run(args...);
+    case EQ_ADV2 * 4 + 1: return F<Adv<R, 2>, 1>::run(args...);
+    case EQ_ADV2 * 4 + 2: return F<Adv<R, 2>, 2>::run(args...);
+    case EQ_ADV2 * 4 + 3: return F<Adv<R, 2>, 3>::run(args...);
+    case EQ_EULER2 * 4 + 0: return F<Euler2<R>, 0>::run(args...);
+    case EQ_EULER2 * 4 + 1: return F<Euler2<R>, 1>::run(args...);
+    case EQ_EULER2 * 4 + 2: return F<Euler2<R>, 2>::run(args...);
+    case EQ_EULER2 * 4 + 3: return F<Euler2<R>, 3>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <class EQ, int K>
+struct RunInner {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const InnerArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_inner<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, a);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunFinal {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const FinalArgs& a,
+                        hipStream_t s) {
+    if constexpr (EQ::DIM == 2) {
+      dim3 grid(nblk(g.nx, BX), nblk(g.ny, BY));
+      hipLaunchKernelGGL((k_final2<EQ, K>), grid, dim3(BX, BY), 0, s, ph, g, bc, a);
+    } else {
+      hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
+    }
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunLoc {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const double* in, double* out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_loc<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, in, out);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunWave {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const double* u, double* partial,
+                        int nb, double cfl, double* smax, double* dt, hipStream_t s) {
+    hipLaunchKernelGGL((k_wave_partial<EQ, K>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
+    hipLaunchKernelGGL(k_wave_final, dim3(1), dim3(256), 0, s, partial, nb, cfl, smax, dt);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunError {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const double* u, int ic,
+                        const double* params, const double* aux, double t, int comp,
+                        double* partial, int nb, double* out3, hipStream_t s) {
+    hipLaunchKernelGGL((k_error_partial<EQ, K>), dim3(nb), dim3(256), 0, s, ph, g, u, ic, params,
+                       aux, t, comp, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, 3, 1.0, out3);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunTotal {
+  static hipError_t run(const Geo& g, const double* u, int comp, double* partial, int nb,
+                        double* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_total_partial<EQ, K>), dim3(nb), dim3(256), 0, s, g, u, comp, partial);
+    const double area = g.dx * (EQ::DIM == 2 ? g.dy : 1.0);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, 1, area, out);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunProject {
+  static hipError_t run(const PhysDev& ph, const Geo& g, int ic, const double* params,
+                        const double* aux, double t, double* u, hipStream_t s) {
+    hipLaunchKernelGGL((k_project<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, ic, params,
+                       aux, t, u);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
+struct RunLimit {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, double M, double* u,
+                        uint8_t* flags, unsigned long long* counters, hipStream_t s) {
+    if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 2);
+    hipLaunchKernelGGL((k_limit<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M, u,
+                       flags, counters);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_inner(int eq, int k, const PhysDev& ph, const Geo& g, const InnerArgs& a,
+                        hipStream_t s) {
+  return dispatch<RunInner>(eq, k, ph, g, a, s);
+}
+hipError_t launch_final(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
+                        const FinalArgs& a, hipStream_t s) {
+  return dispatch<RunFinal>(eq, k, ph, g, bc, a, s);
+}
+hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
+                      double* out, hipStream_t s) {
+  return dispatch<RunLoc>(eq, k, ph, g, in, out, s);
+}
+hipError_t launch_combine(long long n, double* out, const double* base, int nx,
+                          const double* coef, const double* const* X, const double* dt_ptr,
+                          hipStream_t s) {
+  CombineArgs a{};
+  a.out = out;
+  a.base = base;
+  a.n = nx;
+  a.dt_ptr = dt_ptr;
+  for (int j = 0; j < nx && j < MAXS; ++j) {
+    a.X[j] = X[j];
+    a.coef[j] = coef[j];
+  }
+  unsigned blocks = nblk(n / 2, 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, s, n, a);
+  return hipGetLastError();
+}
+hipError_t launch_wavespeed(int eq, int k, const PhysDev& ph, const Geo& g, const double* u,
+                            double* partial, int nb, double cfl, double* smax, double* dt,
+                            hipStream_t s) {
+  return dispatch<RunWave>(eq, k, ph, g, u, partial, nb, cfl, smax, dt, s);
+}
+hipError_t launch_error(int eq, int k, const PhysDev& ph, const Geo& g, const double* u, int ic,
+                        const double* params, const double* aux, double t, int comp,
+                        double* partial, int nb, double* out3, hipStream_t s) {
+  return dispatch<RunError>(eq, k, ph, g, u, ic, params, aux, t, comp, partial, nb, out3, s);
+}
+hipError_t launch_total(int eq, int k, const Geo& g, const double* u, int comp, double* partial,
+                        int nb, double* out, hipStream_t s) {
+  return dispatch<RunTotal>(eq, k, g, u, comp, partial, nb, out, s);
+}
+hipError_t launch_project(int eq, int k, const PhysDev& ph, const Geo& g, int ic,
+                          const double* params, const double* aux, double t, double* u,
+                          hipStream_t s) {
+  return dispatch<RunProject>(eq, k, ph, g, ic, params, aux, t, u, s);
+}
+hipError_t launch_limit(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
+                        double M, double* u, uint8_t* flags, unsigned long long* counters,
+                        hipStream_t s) {
+  return dispatch<RunLimit>(eq, k, ph, g, bc, M, u, flags, counters, s);
+}
+
+}  // namespace crk

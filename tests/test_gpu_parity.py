@@ -1,0 +1,268 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Sizes span several 64x4 tiles and ragged tails.  Tolerance for the FP64
+path: 1e-12 relative to the largest magnitude of the compared quantity
+(the stated FP64 tolerance of the build); the two sides differ only in
+rounding order (the GPU contracts a*b+c into FMAs, the oracle does not).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2307_06471_amd import workloads as W
+from tests.helpers import BC, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2307_06471_amd import crkdg
+    return crkdg
+
+
+def meshes(K, dim, nx, ny, equation, bc=(0, 0, 0, 0), bc_state=None, adv=(0.8, -0.6),
+           box=(0.0, 1.0, 0.0, 1.0), bc_exact=0, flux="llf"):
+    eqo = O.EQ_EULER if equation == "euler" else O.EQ_ADVECTION
+    om = O.Mesh(dim, nx, ny, x0=box[0], x1=box[1], y0=box[2], y1=box[3], bc=bc,
+                bc_state=bc_state, bc_exact=bc_exact, equation=eqo, adv=adv,
+                flux=O.FLUX_LLF if flux == "llf" else O.FLUX_UPWIND)
+    lm = K.make_mesh(dim, nx, ny, x0=box[0], x1=box[1], y0=box[2], y1=box[3], bc=bc,
+                     bc_state=bc_state, bc_exact=bc_exact,
+                     equation=K.EQ_EULER if equation == "euler" else K.EQ_ADVECTION, adv=adv)
+    return om, lm
+
+
+def random_state(equation, shape, seed):
+    rng = np.random.default_rng(seed)
+    if equation == "euler":
+        return W.random_euler_modes(rng, shape[1], shape[2])
+    return rng.standard_normal(shape)
+
+
+def solver(K, lm, k, flux, stages=3):
+    return K.Solver(lm, k, K.FLUX_LLF if flux == "llf" else K.FLUX_UPWIND, stages)
+
+
+OP_CASES = [
+    # dim, equation, nx, ny, bc, flux
+    (2, "euler", 70, 9, (0, 0, 0, 0), "llf"),
+    (2, "euler", 67, 5, (1, 1, 1, 1), "llf"),
+    (2, "euler", 64, 4, (2, 1, 1, 2), "llf"),
+    (2, "advection", 65, 6, (0, 0, 0, 0), "upwind"),
+    (2, "advection", 33, 11, (1, 1, 0, 0), "llf"),
+    (1, "advection", 300, 1, (0, 0, 0, 0), "upwind"),
+    (1, "advection", 257, 1, (1, 1, 0, 0), "llf"),
+]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("case", OP_CASES, ids=lambda c: f"{c[0]}d-{c[1]}-{c[2]}x{c[3]}-bc{c[4]}")
+def test_operators(K, case, k):
+    import torch
+    dim, eq, nx, ny, bc, flux = case
+    bcs = [[1.1, 0.2, -0.1, 2.7]] * 4 if eq == "euler" else [[0.3]] * 4
+    om, lm = meshes(K, dim, nx, ny, eq, bc=bc, bc_state=bcs, flux=flux)
+    s = solver(K, lm, k, flux)
+    u = random_state(eq, om.shape(k), 11 * k + nx)
+    x = torch.from_numpy(u.copy()).cuda()
+    for op, oop in ((K.OP_LOC, O.OP_LOC), (K.OP_DG, O.OP_DG)):
+        got = s.crkdg_apply_op(op, x).cpu().numpy()
+        ref = O.apply(om, k, oop, u)
+        assert rel_err(got, ref) < TOL, (op, rel_err(got, ref))
+
+
+def test_combine(K):
+    import torch
+    om, lm = meshes(K, 2, 37, 5, "euler")
+    s = solver(K, lm, 2, "llf")
+    rng = np.random.default_rng(0)
+    arrs = [rng.standard_normal(om.shape(2)) for _ in range(4)]
+    coefs = [0.3, -1.25, 2.0, 1e-3]
+    t = [torch.from_numpy(a).cuda() for a in arrs]
+    out = s.crkdg_combine(t[0], coefs[:3], t[1:]).cpu().numpy()
+    ref = arrs[0] + coefs[0] * arrs[1] + coefs[1] * arrs[2] + coefs[2] * arrs[3]
+    assert rel_err(out, ref) < 1e-15
+    out = s.crkdg_combine(None, coefs, t).cpu().numpy()
+    ref = sum(c * a for c, a in zip(coefs, arrs))
+    assert rel_err(out, ref) < 1e-15
+
+
+TABS = ["fe", "eq2", "eq3", "rk4", "ssp3"]
+
+
+@pytest.mark.parametrize("tab", TABS)
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_one_step_euler(K, tab, k):
+    om, lm = meshes(K, 2, 70, 9, "euler", box=(0.0, 2.0, 0.0, 1.0))
+    s = solver(K, lm, k, "llf")
+    A, b, c = (np.array(v, float) for v in W.TABLEAU[tab])
+    s.crkdg_set_tableau(A, b, c)
+    u = random_state("euler", om.shape(k), 5 + k)
+    s.crkdg_set_state(u)
+    dt = 2e-3
+    s.crkdg_step(dt)
+    got = s.crkdg_get_state()
+    ref = O.step_crkdg(om, k, (A, b, c), 0.0, dt, u)
+    assert rel_err(got, ref) < TOL
+
+
+@pytest.mark.parametrize("tab", TABS)
+@pytest.mark.parametrize("dim", [1, 2])
+def test_one_step_advection(K, tab, dim):
+    k = 2
+    om, lm = meshes(K, dim, 70 if dim == 2 else 300, 9, "advection", flux="upwind")
+    s = solver(K, lm, k, "upwind")
+    A, b, c = (np.array(v, float) for v in W.TABLEAU[tab])
+    s.crkdg_set_tableau(A, b, c)
+    u = random_state("advection", om.shape(k), 3)
+    s.crkdg_set_state(u)
+    s.crkdg_step(1e-3)
+    ref = O.step_crkdg(om, k, (A, b, c), 0.0, 1e-3, u)
+    assert rel_err(s.crkdg_get_state(), ref) < TOL
+
+
+def test_c1_full_run(K):
+    """1D advection workload: 640 steps, SSP-RK3 Butcher tableau, periodic"""
+    cfg = W.config("c1")
+    om, lm = meshes(K, 1, cfg["nx"], 1, "advection", box=cfg["box"], adv=(1.0, 0.0), flux="upwind")
+    s = solver(K, lm, 2, "upwind")
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["ssp3"])
+    s.crkdg_set_tableau(A, b, c)
+    s.crkdg_project(K.IC_ADV_SIN)
+    u0 = O.project(om, 2, O.IC_ADV_SIN)
+    assert rel_err(s.crkdg_get_state(), u0) < 1e-14
+    h = (cfg["box"][1] - cfg["box"][0]) / cfg["nx"]
+    dt = cfg["dt_over_h"] * h
+    u = u0.copy()
+    for n in range(cfg["steps"]):
+        s.crkdg_step(dt)
+        u = O.step_crkdg(om, 2, (A, b, c), n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+    e_gpu = s.crkdg_error(K.IC_ADV_SIN, (), t=cfg["steps"] * dt)
+    e_or = O.errors(om, 2, u, O.IC_ADV_SIN, t=cfg["steps"] * dt)
+    assert rel_err(e_gpu, e_or) < 1e-10
+
+
+def test_small_vortex_run_and_conservation(K):
+    cfg = W.config("c2", scale=8)  # 32 x 32
+    om, lm = meshes(K, 2, cfg["nx"], cfg["ny"], "euler", box=cfg["box"])
+    s = solver(K, lm, 2, "llf")
+    s.crkdg_project(K.IC_VORTEX, cfg["ic_params"])
+    u = O.project(om, 2, O.IC_VORTEX, cfg["ic_params"])
+    assert rel_err(s.crkdg_get_state(), u) < 1e-13
+    smax = s.crkdg_max_wavespeed()
+    assert abs(smax - O.max_wavespeed(om, 2, u)) < 1e-14 * smax
+    dt = cfg["cfl"] / smax
+    m0 = [s.crkdg_total(c) for c in range(4)]
+    for c in range(4):
+        assert abs(m0[c] - O.total_mass(om, 2, u, c)) < 1e-13 * max(1, abs(m0[c]))
+    A, b, cc = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    for n in range(40):
+        s.crkdg_step(dt)
+        u = O.step_crkdg(om, 2, (A, b, cc), n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+    for c in range(4):
+        assert abs(s.crkdg_total(c) - m0[c]) < 1e-13 * max(1, abs(m0[c]))
+    e = s.crkdg_error(K.IC_VORTEX, cfg["ic_params"], t=40 * dt)
+    eo = O.errors(om, 2, u, O.IC_VORTEX, cfg["ic_params"], t=40 * dt)
+    assert rel_err(e, eo) < 1e-10
+
+
+def test_bitwise_determinism(K):
+    cfg = W.config("c2", scale=8)
+    om, lm = meshes(K, 2, cfg["nx"], cfg["ny"], "euler", box=cfg["box"])
+    outs = []
+    for _ in range(2):
+        s = solver(K, lm, 2, "llf")
+        s.crkdg_project(K.IC_VORTEX, cfg["ic_params"])
+        for _ in range(10):
+            s.crkdg_step(0.01)
+        outs.append(s.crkdg_get_state())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("ic", ["const", "adv1", "adv2", "wave", "vortex", "quadrant", "shock"])
+def test_projection(K, ic):
+    k = 2
+    if ic in ("adv1",):
+        om, lm = meshes(K, 1, 100, 1, "advection", box=(0.0, 2 * np.pi, 0, 1), adv=(1.0, 0.0))
+        p, oid, lid, aux = [], O.IC_ADV_SIN, K.IC_ADV_SIN, None
+    elif ic == "adv2":
+        om, lm = meshes(K, 2, 40, 30, "advection", box=(-1.0, 1.0, -1.0, 1.0), adv=(1.0, 1.0))
+        p, oid, lid, aux = [], O.IC_ADV_SIN, K.IC_ADV_SIN, None
+    else:
+        box = (0.0, 4.0, 0.0, 1.0) if ic == "shock" else (0.0, 2.0, 0.0, 2.0)
+        om, lm = meshes(K, 2, 130, 33, "euler", box=box)
+        aux = None
+        if ic == "const":
+            p, oid, lid = [1.0, 0.3, -0.2, 2.5], O.IC_CONST, K.IC_CONST
+        elif ic == "wave":
+            p, oid, lid = [0.7, 0.3, 1.0], O.IC_EULER_WAVE, K.IC_EULER_WAVE
+        elif ic == "vortex":
+            p, oid, lid = [5.0, 1.0, 1.0, 2.0, 2.0], O.IC_VORTEX, K.IC_VORTEX
+        elif ic == "quadrant":
+            p, oid, lid = W.quadrant_params(3, split=(1.03, 0.97)), O.IC_QUADRANT, K.IC_QUADRANT
+        else:
+            p, aux = W.shock_problem(2000, 130, 33)
+            oid, lid = O.IC_SHOCK, K.IC_SHOCK
+    s = solver(K, lm, k, "llf" if ic not in ("adv1", "adv2") else "upwind")
+    if aux is not None:
+        import torch
+        s.crkdg_project(lid, p, aux=torch.from_numpy(aux).cuda())
+    else:
+        s.crkdg_project(lid, p)
+    ref = O.project(om, k, oid, p if p else None, aux)
+    assert rel_err(s.crkdg_get_state(), ref) < 1e-13
+
+
+def test_inflow_boundary_stage_times(K):
+    """1D advection with inflow data sin(-t) on the left, evaluated at the
+    final-stage times (Section 3.4); 100 steps of scheme (eq:3)"""
+    N, k = 80, 2
+    L = 4 * np.pi
+    om, lm = meshes(K, 1, N, 1, "advection", box=(0.0, L, 0, 1), adv=(1.0, 0.0), bc=(2, 1, 0, 0),
+                    bc_exact=O.IC_ADV_SIN, flux="upwind")
+    s = solver(K, lm, k, "upwind", stages=3)
+    s.crkdg_project(K.IC_ADV_SIN)
+    u = O.project(om, k, O.IC_ADV_SIN)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    dt = 0.16 * L / N
+    for n in range(100):
+        s.crkdg_step(dt)
+        u = O.step_crkdg(om, k, (A, b, c), n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter(K, k):
+    """one limiter application on a projected quadrant state with jumps that
+    cut cells; flags compared where the decision margin exceeds 1e-9"""
+    import torch
+    om, lm = meshes(K, 2, 70, 37, "euler", bc=(1, 1, 1, 1))
+    p = W.quadrant_params(7, split=(0.503, 0.497))
+    s = solver(K, lm, k, "llf")
+    s.crkdg_project(K.IC_QUADRANT, p)
+    u = O.project(om, k, O.IC_QUADRANT, p)
+    # smooth perturbation so that many cells sit near the thresholds
+    rng = np.random.default_rng(k)
+    u[:, 1:] += 5e-5 * rng.standard_normal(u[:, 1:].shape)  # around M h^2 = 1e-4
+    s.crkdg_set_state(u)
+    flags = torch.zeros(om.ncells, dtype=torch.uint8, device="cuda")
+    n_gpu = s.crkdg_limit(0.5, flags)
+    lim_o, fl_o, n_o = O.limit_tvb(om, k, 0.5, u)
+    _, margin, _ = O.tvb_flags(om, k, 0.5, u)
+    fg = flags.cpu().numpy()
+    safe = margin > 1e-9
+    assert safe.mean() > 0.9
+    assert np.array_equal(fg[safe] != 0, fl_o[safe] != 0)
+    agree = (fg == fl_o)
+    got = s.crkdg_get_state()
+    assert rel_err(got[:, :, agree], lim_o[:, :, agree]) < 1e-13
+    assert np.array_equal(got[:, 0], u[:, 0])  # means untouched
+    assert abs(n_gpu - n_o) <= (~safe).sum()
