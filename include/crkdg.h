@@ -165,6 +165,15 @@ int crkdg_apply_op(crkdg_state* st, int op, const void* in_dev, void* out_dev, d
 int crkdg_combine(crkdg_state* st, void* out_dev, const void* base_dev, int n,
                   const double* coef, const void* const* X_dev);
 
+/* Measurement: record a HIP event pair on the bound stream around every
+ * kernel launch (at most max_launches) until crkdg_profile_end, which syncs
+ * and returns the summed milliseconds and launch counts per kernel class:
+ * 0 inner stages, 1 final stage, 2 local operator, 3 stage combination,
+ * 4 dt reduction, 5 limiter, 6 other.  Host-side events only; no device
+ * memory is allocated. */
+int crkdg_profile_begin(crkdg_state* st, int max_launches);
+int crkdg_profile_end(crkdg_state* st, double ms[8], int64_t counts[8]);
+
 /* Host-only: the library's own n-point Gauss--Legendre rule (n = 1..6). */
 int crkdg_gauss_rule(int n, double* x, double* w);
 

@@ -70,6 +70,8 @@ def _sig():
         "crkdg_apply_op": (C.c_int, [vp, C.c_int, vp, vp, C.c_double]),
         "crkdg_combine": (C.c_int, [vp, vp, vp, C.c_int, dp, C.POINTER(vp)]),
         "crkdg_gauss_rule": (C.c_int, [C.c_int, dp, dp]),
+        "crkdg_profile_begin": (C.c_int, [vp, C.c_int]),
+        "crkdg_profile_end": (C.c_int, [vp, dp, C.POINTER(C.c_int64)]),
         "crkdg_destroy": (None, [vp]),
         "crkdg_strerror": (C.c_char_p, [C.c_int]),
     }
@@ -259,6 +261,20 @@ class Solver:
                                    None if base is None else C.c_void_p(base.data_ptr()), n,
                                    _dp(cf), ptrs), "crkdg_combine")
         return out
+
+    KERNEL_CLASSES = ("inner", "final", "loc", "combine", "dt", "limit", "other", "spare")
+
+    def crkdg_profile_begin(self, max_launches):
+        _check(lib().crkdg_profile_begin(self.h, int(max_launches)), "crkdg_profile_begin")
+
+    def crkdg_profile_end(self):
+        ms = np.zeros(8)
+        cnt = np.zeros(8, dtype=np.int64)
+        _check(lib().crkdg_profile_end(self.h, _dp(ms),
+                                       cnt.ctypes.data_as(C.POINTER(C.c_int64))),
+               "crkdg_profile_end")
+        return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(self.KERNEL_CLASSES)
+                if cnt[i]}
 
     # -- helpers -------------------------------------------------------
     def current_view(self):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "crkdg_internal.hpp"
 #include "dg_core.hpp"
@@ -30,6 +31,12 @@ struct crkdg_state {
   int cur;  // 0: the current state is in dofs, 1: in the work buffer's first slot
   double t;
   size_t S;  // bytes of one state
+  // per-launch timing (measurement only)
+  bool prof;
+  int prof_max;
+  std::vector<hipEvent_t> ev;   // 2 per launch
+  std::vector<int> ev_cls;
+  int prof_n;
 };
 
 namespace {
@@ -66,6 +73,24 @@ void set_tableau_internal(crkdg_state* st, int s, const double* c, const double*
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? CRKDG_OK : CRKDG_EHIP; }
+
+enum { KC_INNER = 0, KC_FINAL = 1, KC_LOC = 2, KC_COMBINE = 3, KC_DT = 4, KC_LIMIT = 5, KC_OTHER = 6 };
+
+// event pair around one launch when profiling is on
+struct ProfScope {
+  crkdg_state* st;
+  int idx;
+  ProfScope(crkdg_state* s, int cls) : st(s), idx(-1) {
+    if (st->prof && st->prof_n < st->prof_max) {
+      idx = st->prof_n++;
+      st->ev_cls[idx] = cls;
+      (void)hipEventRecord(st->ev[2 * idx], st->stream);
+    }
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(st->ev[2 * idx + 1], st->stream);
+  }
+};
 
 }  // namespace
 
@@ -293,13 +318,17 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
     }
     // a stage with b_i == 0 is still needed by later stages only through the
     // register chain, so it is not stored
+    ProfScope ps(st, KC_INNER);
     e = launch_inner(st->eq, st->k, st->ph, st->geo, ia, st->stream);
   } else if (s > 1) {
     // general tableau: materialise L_j = loc(u^(j)) and combine
     const long long n = (long long)(st->S / sizeof(double));
     for (int i = 1; i < s && e == hipSuccess; ++i) {
       double* Lj = (double*)lbuf_ptr(st, i - 1);
-      e = launch_loc(st->eq, st->k, st->ph, st->geo, stages[i - 1], Lj, st->stream);
+      {
+        ProfScope ps(st, KC_LOC);
+        e = launch_loc(st->eq, st->k, st->ph, st->geo, stages[i - 1], Lj, st->stream);
+      }
       if (e != hipSuccess) break;
       double coef[MAXS];
       const double* X[MAXS];
@@ -311,6 +340,7 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
         ++nx;
       }
       double* ui = (double*)stage_ptr(st, i);
+      ProfScope ps(st, KC_COMBINE);
       e = launch_combine(n, ui, un, nx, coef, X, dt_dev, st->stream);
       stages[i] = ui;
     }
@@ -325,7 +355,10 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
     ++ns;
   }
   fa.ns = ns;
-  e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+  {
+    ProfScope ps(st, KC_FINAL);
+    e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+  }
   if (e != hipSuccess) return CRKDG_EHIP;
   st->cur ^= 1;
   return CRKDG_OK;
@@ -351,6 +384,7 @@ int crkdg_compute_dt(crkdg_state* st, double cfl, double* dt_dev) {
   if (!st || !dt_dev || !isfinite(cfl) || !(cfl > 0.0)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   double* partial = (double*)scratch_ptr(st);
+  ProfScope ps(st, KC_DT);
   hipError_t e = launch_wavespeed(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st),
                                   partial, RED_BLOCKS, cfl, nullptr, dt_dev, st->stream);
   return hip_rc(e);
@@ -373,8 +407,12 @@ int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagge
   if (!st->bound) return CRKDG_EUNBOUND;
   unsigned long long* counters =
       n_flagged ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
-  hipError_t e = launch_limit(st->eq, st->k, st->ph, st->geo, st->bc, M, (double*)cur_ptr(st),
-                              flags_dev, counters, st->stream);
+  hipError_t e;
+  {
+    ProfScope ps(st, KC_LIMIT);
+    e = launch_limit(st->eq, st->k, st->ph, st->geo, st->bc, M, (double*)cur_ptr(st), flags_dev,
+                     counters, st->stream);
+  }
   if (e != hipSuccess) return CRKDG_EHIP;
   if (n_flagged) {
     unsigned long long h[2] = {0, 0};
@@ -454,6 +492,47 @@ int crkdg_combine(crkdg_state* st, void* out, const void* base, int n, const dou
                                st->stream));
 }
 
-void crkdg_destroy(crkdg_state* st) { delete st; }
+int crkdg_profile_begin(crkdg_state* st, int max_launches) {
+  if (!st || max_launches < 1 || max_launches > (1 << 20)) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if ((int)st->ev.size() < 2 * max_launches) {
+    const size_t old = st->ev.size();
+    st->ev.resize(2 * (size_t)max_launches);
+    for (size_t e = old; e < st->ev.size(); ++e)
+      if (hipEventCreate(&st->ev[e]) != hipSuccess) {
+        st->ev.resize(e);
+        return CRKDG_EHIP;
+      }
+  }
+  st->ev_cls.assign(max_launches, 0);
+  st->prof_max = max_launches;
+  st->prof_n = 0;
+  st->prof = true;
+  return CRKDG_OK;
+}
+
+int crkdg_profile_end(crkdg_state* st, double ms[8], int64_t counts[8]) {
+  if (!st || !ms || !counts) return CRKDG_EINVAL;
+  for (int c = 0; c < 8; ++c) {
+    ms[c] = 0.0;
+    counts[c] = 0;
+  }
+  if (!st->prof) return CRKDG_EINVAL;
+  st->prof = false;
+  if (hipStreamSynchronize(st->stream) != hipSuccess) return CRKDG_EHIP;
+  for (int i = 0; i < st->prof_n; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, st->ev[2 * i], st->ev[2 * i + 1]) != hipSuccess) return CRKDG_EHIP;
+    ms[st->ev_cls[i]] += t;
+    counts[st->ev_cls[i]] += 1;
+  }
+  return CRKDG_OK;
+}
+
+void crkdg_destroy(crkdg_state* st) {
+  if (!st) return;
+  for (hipEvent_t e : st->ev) (void)hipEventDestroy(e);
+  delete st;
+}
 
 }  // extern "C"
