@@ -30,7 +30,10 @@ struct crkdg_state {
   hipStream_t stream;
   int cur;  // 0: the current state is in dofs, 1: in the work buffer's first slot
   double t;
-  size_t S;  // bytes of one state
+  size_t S;       // bytes of one state (device layout lay)
+  size_t S_stage; // bytes of one stored stage state (layout lay_stage)
+  int lay, lay_stage;
+  bool mixed;
   // per-launch timing (measurement only)
   bool prof;
   int prof_max;
@@ -46,9 +49,12 @@ constexpr size_t SCRATCH = (size_t)RED_BLOCKS * 3 * sizeof(double) + 1024;
 
 size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+size_t slot_bytes(const crkdg_state* st) {
+  return round_up(st->S > st->S_stage ? st->S : st->S_stage);
+}
 char* slot_ptr(const crkdg_state* st, int slot) {
   // work layout: [state B][stage 1..3][L 0..2][scratch]
-  return st->work + (size_t)slot * round_up(st->S);
+  return st->work + (size_t)slot * slot_bytes(st);
 }
 char* cur_ptr(const crkdg_state* st) { return st->cur ? slot_ptr(st, 0) : st->dofs; }
 char* nxt_ptr(const crkdg_state* st) { return st->cur ? st->dofs : slot_ptr(st, 0); }
@@ -125,7 +131,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   if (!(mesh->x1 > mesh->x0) || (mesh->dim == 2 && !(mesh->y1 > mesh->y0))) return CRKDG_EINVAL;
   if (rk_stages < 1 || rk_stages > 4) return CRKDG_EINVAL;
   if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF) return CRKDG_EINVAL;
-  if (mesh->precision != CRKDG_FP64) return CRKDG_EUNSUPPORTED;
+  if (mesh->precision != CRKDG_FP64 && mesh->precision != CRKDG_FP32_MIXED) return CRKDG_EINVAL;
   for (int sd = 0; sd < 4; ++sd)
     if (mesh->bc[sd] < CRKDG_BC_PERIODIC || mesh->bc[sd] > CRKDG_BC_DIRICHLET) return CRKDG_EINVAL;
   int eq;
@@ -140,6 +146,8 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     return CRKDG_EINVAL;
   }
   if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN) return CRKDG_EUNSUPPORTED;
+  // the FP32-bulk form is built for 2D Euler, k = 1..3
+  if (mesh->precision == CRKDG_FP32_MIXED && (eq != EQ_EULER2 || k < 1)) return CRKDG_EUNSUPPORTED;
   crkdg_state* st = new (std::nothrow) crkdg_state();
   if (!st) return CRKDG_EINVAL;
   st->mesh = *mesh;
@@ -183,7 +191,18 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     case 3: set_tableau_internal(st, 3, E3_c, E3_A, E3_b); break;
     default: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
   }
-  st->S = (size_t)st->nc * st->nb * g.N * sizeof(double);
+  st->mixed = mesh->precision == CRKDG_FP32_MIXED;
+  if (st->mixed) {
+    st->lay = LMIX;
+    st->lay_stage = LMIX;
+    st->S = (size_t)st->nc * g.N * sizeof(double) + (size_t)st->nc * (st->nb - 1) * g.N * sizeof(float);
+    st->S_stage = st->S;
+  } else {
+    st->lay = L64;
+    st->lay_stage = L64;
+    st->S = (size_t)st->nc * st->nb * g.N * sizeof(double);
+    st->S_stage = st->S;
+  }
   st->bound = false;
   st->cur = 0;
   st->t = 0.0;
@@ -209,7 +228,7 @@ size_t crkdg_state_bytes(const crkdg_state* st) { return st ? st->S : 0; }
 
 size_t crkdg_workspace_bytes(const crkdg_state* st) {
   if (!st) return 0;
-  return (size_t)(2 * MAXS - 1) * round_up(st->S) + SCRATCH;
+  return (size_t)(2 * MAXS - 1) * slot_bytes(st) + SCRATCH;
 }
 
 int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream) {
@@ -228,19 +247,65 @@ void* crkdg_current_dofs(const crkdg_state* st) {
   return cur_ptr(st);
 }
 
+// host conversion between the canonical FP64 layout and the device layout
+static void to_device_layout(const crkdg_state* st, const double* in, char* out) {
+  const long long N = st->geo.N;
+  const int nc = st->nc, nb = st->nb;
+  double* avg = (double*)out;
+  float* hi = (float*)(out + (size_t)nc * N * sizeof(double));
+  for (int c = 0; c < nc; ++c) {
+    for (long long e = 0; e < N; ++e) avg[c * N + e] = in[(long long)(c * nb) * N + e];
+    for (int b = 1; b < nb; ++b)
+      for (long long e = 0; e < N; ++e)
+        hi[(long long)(c * (nb - 1) + b - 1) * N + e] = (float)in[(long long)(c * nb + b) * N + e];
+  }
+}
+static void from_device_layout(const crkdg_state* st, const char* in, double* out) {
+  const long long N = st->geo.N;
+  const int nc = st->nc, nb = st->nb;
+  const double* avg = (const double*)in;
+  const float* hi = (const float*)(in + (size_t)nc * N * sizeof(double));
+  for (int c = 0; c < nc; ++c) {
+    for (long long e = 0; e < N; ++e) out[(long long)(c * nb) * N + e] = avg[c * N + e];
+    for (int b = 1; b < nb; ++b)
+      for (long long e = 0; e < N; ++e)
+        out[(long long)(c * nb + b) * N + e] = (double)hi[(long long)(c * (nb - 1) + b - 1) * N + e];
+  }
+}
+
 int crkdg_set_state(crkdg_state* st, const double* host) {
   if (!st || !host) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  hipError_t e = hipMemcpyAsync(cur_ptr(st), host, st->S, hipMemcpyHostToDevice, st->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  hipError_t e;
+  if (!st->mixed) {
+    e = hipMemcpyAsync(cur_ptr(st), host, st->S, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  } else {
+    char* tmp = (char*)malloc(st->S);
+    if (!tmp) return CRKDG_EINVAL;
+    to_device_layout(st, host, tmp);
+    e = hipMemcpyAsync(cur_ptr(st), tmp, st->S, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    free(tmp);
+  }
   return hip_rc(e);
 }
 
 int crkdg_get_state(const crkdg_state* st, double* host) {
   if (!st || !host) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  hipError_t e = hipMemcpyAsync(host, cur_ptr(st), st->S, hipMemcpyDeviceToHost, st->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  hipError_t e;
+  if (!st->mixed) {
+    e = hipMemcpyAsync(host, cur_ptr(st), st->S, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  } else {
+    char* tmp = (char*)malloc(st->S);
+    if (!tmp) return CRKDG_EINVAL;
+    e = hipMemcpyAsync(tmp, cur_ptr(st), st->S, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    if (e == hipSuccess) from_device_layout(st, tmp, host);
+    free(tmp);
+  }
   return hip_rc(e);
 }
 
@@ -284,50 +349,57 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
   double* Pd;
   rc = upload_params(st, P, &Pd);
   if (rc) return rc;
-  hipError_t e = launch_project(st->eq, st->k, st->ph, st->geo, ic, Pd, aux_dev, st->t,
-                                (double*)cur_ptr(st), st->stream);
+  hipError_t e = launch_project(st->eq, st->k, st->lay, st->ph, st->geo, ic, Pd, aux_dev, st->t,
+                                cur_ptr(st), st->stream);
   return hip_rc(e);
 }
 
 // one step with dt from the host (dt_dev == NULL) or from device memory
 static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
-  const double* un = (const double*)cur_ptr(st);
-  double* unew = (double*)nxt_ptr(st);
+  const void* un = cur_ptr(st);
+  void* unew = nxt_ptr(st);
   hipError_t e = hipSuccess;
   const int s = st->s;
   FinalArgs fa{};
   fa.base = un;
+  fa.lay_base = st->lay;
   fa.out = unew;
   fa.dt = dt;
   fa.dt_ptr = dt_dev;
-  const double* stages[MAXS];
+  const void* stages[MAXS];
+  int lays[MAXS];
   stages[0] = un;
+  lays[0] = st->lay;
   if (s > 1 && st->subdiag) {
     // all inner stages in one element-local pass
     InnerArgs ia{};
     ia.un = un;
+    ia.lay_in = st->lay;
+    ia.lay_stage = st->lay_stage;
     ia.s = s;
     ia.dt = dt;
     ia.dt_ptr = dt_dev;
     ia.store_mask = 0;
     for (int i = 1; i < s; ++i) {
       ia.a_sub[i] = st->A[i][i - 1];
-      ia.stage[i] = (double*)stage_ptr(st, i);
+      ia.stage[i] = stage_ptr(st, i);
       stages[i] = ia.stage[i];
+      lays[i] = st->lay_stage;
       if (st->b[i] != 0.0) ia.store_mask |= 1 << i;
     }
     // a stage with b_i == 0 is still needed by later stages only through the
     // register chain, so it is not stored
     ProfScope ps(st, KC_INNER);
-    e = launch_inner(st->eq, st->k, st->ph, st->geo, ia, st->stream);
+    e = launch_inner(st->eq, st->k, st->mixed, st->ph, st->geo, ia, st->stream);
   } else if (s > 1) {
+    if (st->mixed) return CRKDG_EUNSUPPORTED;  // materialised path: FP64 layout only
     // general tableau: materialise L_j = loc(u^(j)) and combine
     const long long n = (long long)(st->S / sizeof(double));
     for (int i = 1; i < s && e == hipSuccess; ++i) {
       double* Lj = (double*)lbuf_ptr(st, i - 1);
       {
         ProfScope ps(st, KC_LOC);
-        e = launch_loc(st->eq, st->k, st->ph, st->geo, stages[i - 1], Lj, st->stream);
+        e = launch_loc(st->eq, st->k, st->ph, st->geo, (const double*)stages[i - 1], Lj, st->stream);
       }
       if (e != hipSuccess) break;
       double coef[MAXS];
@@ -341,8 +413,9 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
       }
       double* ui = (double*)stage_ptr(st, i);
       ProfScope ps(st, KC_COMBINE);
-      e = launch_combine(n, ui, un, nx, coef, X, dt_dev, st->stream);
+      e = launch_combine(n, ui, (const double*)un, nx, coef, X, dt_dev, st->stream);
       stages[i] = ui;
+      lays[i] = L64;
     }
   }
   if (e != hipSuccess) return CRKDG_EHIP;
@@ -350,6 +423,7 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
   for (int i = 0; i < s; ++i) {
     if (st->b[i] == 0.0) continue;
     fa.st[ns] = stages[i];
+    fa.lay[ns] = lays[i];
     fa.w[ns] = st->b[i];
     fa.tst[ns] = st->t + st->c[i] * (dt_dev ? 0.0 : dt);
     ++ns;
@@ -357,7 +431,7 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
   fa.ns = ns;
   {
     ProfScope ps(st, KC_FINAL);
-    e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+    e = launch_final(st->eq, st->k, st->mixed, st->ph, st->geo, st->bc, fa, st->stream);
   }
   if (e != hipSuccess) return CRKDG_EHIP;
   st->cur ^= 1;
@@ -385,8 +459,8 @@ int crkdg_compute_dt(crkdg_state* st, double cfl, double* dt_dev) {
   if (!st->bound) return CRKDG_EUNBOUND;
   double* partial = (double*)scratch_ptr(st);
   ProfScope ps(st, KC_DT);
-  hipError_t e = launch_wavespeed(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st),
-                                  partial, RED_BLOCKS, cfl, nullptr, dt_dev, st->stream);
+  hipError_t e = launch_wavespeed(st->eq, st->k, st->lay, st->ph, st->geo, cur_ptr(st), partial,
+                                  RED_BLOCKS, cfl, nullptr, dt_dev, st->stream);
   return hip_rc(e);
 }
 
@@ -395,8 +469,8 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
   if (!st->bound) return CRKDG_EUNBOUND;
   double* partial = (double*)scratch_ptr(st);
   double* res = partial + RED_BLOCKS * 2;
-  hipError_t e = launch_wavespeed(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st),
-                                  partial, RED_BLOCKS, 1.0, res, nullptr, st->stream);
+  hipError_t e = launch_wavespeed(st->eq, st->k, st->lay, st->ph, st->geo, cur_ptr(st), partial,
+                                  RED_BLOCKS, 1.0, res, nullptr, st->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(smax, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
   return hip_rc(e);
@@ -410,7 +484,7 @@ int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagge
   hipError_t e;
   {
     ProfScope ps(st, KC_LIMIT);
-    e = launch_limit(st->eq, st->k, st->ph, st->geo, st->bc, M, (double*)cur_ptr(st), flags_dev,
+    e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, cur_ptr(st), flags_dev,
                      counters, st->stream);
   }
   if (e != hipSuccess) return CRKDG_EHIP;
@@ -438,7 +512,7 @@ int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, doub
   if (rc) return rc;
   double* partial = (double*)scratch_ptr(st);
   double* res = (double*)(scratch_ptr(st) + SCRATCH - 256);
-  hipError_t e = launch_error(st->eq, st->k, st->ph, st->geo, (const double*)cur_ptr(st), ic, Pd,
+  hipError_t e = launch_error(st->eq, st->k, st->lay, st->ph, st->geo, cur_ptr(st), ic, Pd,
                               nullptr, t, comp, partial, RED_BLOCKS, res, st->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
@@ -450,7 +524,7 @@ int crkdg_total(crkdg_state* st, int comp, double* out) {
   if (!st->bound) return CRKDG_EUNBOUND;
   double* partial = (double*)scratch_ptr(st);
   double* res = (double*)(scratch_ptr(st) + SCRATCH - 256);
-  hipError_t e = launch_total(st->eq, st->k, st->geo, (const double*)cur_ptr(st), comp, partial,
+  hipError_t e = launch_total(st->eq, st->k, st->lay, st->geo, cur_ptr(st), comp, partial,
                               RED_BLOCKS, res, st->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
@@ -461,6 +535,7 @@ int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_
   if (!st || !in || !out || (op != CRKDG_OP_LOC && op != CRKDG_OP_DG)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   if (in == out) return CRKDG_EINVAL;
+  if (st->mixed) return CRKDG_EUNSUPPORTED;
   hipError_t e;
   if (op == CRKDG_OP_LOC) {
     e = launch_loc(st->eq, st->k, st->ph, st->geo, (const double*)in, (double*)out, st->stream);
@@ -468,13 +543,15 @@ int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_
     // out = 0 - (-1) * DG(in)
     FinalArgs fa{};
     fa.base = nullptr;
-    fa.out = (double*)out;
+    fa.lay_base = L64;
+    fa.out = out;
     fa.ns = 1;
-    fa.st[0] = (const double*)in;
+    fa.st[0] = in;
+    fa.lay[0] = L64;
     fa.w[0] = 1.0;
     fa.tst[0] = t_bc;
     fa.dt = -1.0;
-    e = launch_final(st->eq, st->k, st->ph, st->geo, st->bc, fa, st->stream);
+    e = launch_final(st->eq, st->k, false, st->ph, st->geo, st->bc, fa, st->stream);
   }
   return hip_rc(e);
 }
@@ -483,6 +560,7 @@ int crkdg_combine(crkdg_state* st, void* out, const void* base, int n, const dou
                   const void* const* X) {
   if (!st || !out || n < 0 || n > MAXS || (n > 0 && (!coef || !X))) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
+  if (st->mixed) return CRKDG_EUNSUPPORTED;
   for (int j = 0; j < n; ++j)
     if (!X[j] || !isfinite(coef[j])) return CRKDG_EINVAL;
   const long long len = (long long)(st->S / sizeof(double));

@@ -11,6 +11,12 @@ namespace crk {
 constexpr int MAXS = 4;        // stages of the largest tableau
 constexpr int NPARAM = 24;     // initial-condition parameters passed to kernels
 
+// device layouts of a state
+//  L64:  double u[comp][mode][cell]                      (canonical)
+//  LMIX: double avg[comp][cell], then float hi[comp][mode-1][cell]
+//  L32:  float u[comp][mode][cell]                       (FP32 stage states)
+enum Layout { L64 = 0, LMIX = 1, L32 = 2 };
+
 struct Geo {
   int nx, ny;
   long long N;
@@ -33,8 +39,10 @@ struct PhysDev {
 enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2 };
 
 struct InnerArgs {
-  const double* un;
-  double* stage[MAXS];   // stage[i] receives u^(i+1) (i >= 1) when bit i of store_mask is set
+  const void* un;
+  int lay_in;            // layout of u^n
+  void* stage[MAXS];     // stage[i] receives u^(i+1) (i >= 1) when bit i of store_mask is set
+  int lay_stage;         // layout of the stored stage states
   int s;
   int store_mask;
   double a_sub[MAXS];    // a_{i, i-1}
@@ -43,40 +51,43 @@ struct InnerArgs {
 };
 
 struct FinalArgs {
-  const double* base;    // u^n (NULL: zero)
-  double* out;
+  const void* base;      // u^n (NULL: zero), layout lay_base
+  int lay_base;
+  void* out;             // u^{n+1}, layout lay_base
   int ns;
-  const double* st[MAXS];
+  const void* st[MAXS];
+  int lay[MAXS];         // layout of each final-stage state
   double w[MAXS];        // b_i
   double tst[MAXS];      // boundary-data time of each stage
   double dt;
   const double* dt_ptr;
 };
 
-// launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error
-hipError_t launch_inner(int eq, int k, const PhysDev& ph, const Geo& g, const InnerArgs& a,
-                        hipStream_t s);
-hipError_t launch_final(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
-                        const FinalArgs& a, hipStream_t s);
+// launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error.
+// mixed: compute type float (FP32 bulk) instead of double.
+hipError_t launch_inner(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+                        const InnerArgs& a, hipStream_t s);
+hipError_t launch_final(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, const FinalArgs& a, hipStream_t s);
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s);
 hipError_t launch_combine(long long n, double* out, const double* base, int nx,
                           const double* coef, const double* const* X, const double* dt_ptr,
                           hipStream_t s);
-hipError_t launch_wavespeed(int eq, int k, const PhysDev& ph, const Geo& g, const double* u,
-                            double* partial, int nblocks, double cfl, double* smax_out,
-                            double* dt_out, hipStream_t s);
-hipError_t launch_error(int eq, int k, const PhysDev& ph, const Geo& g, const double* u, int ic,
-                        const double* params, const double* aux, double t, int comp,
+hipError_t launch_wavespeed(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
+                            const void* u, double* partial, int nblocks, double cfl,
+                            double* smax_out, double* dt_out, hipStream_t s);
+hipError_t launch_error(int eq, int k, int lay, const PhysDev& ph, const Geo& g, const void* u,
+                        int ic, const double* params, const double* aux, double t, int comp,
                         double* partial, int nblocks, double* out3, hipStream_t s);
-hipError_t launch_total(int eq, int k, const Geo& g, const double* u, int comp, double* partial,
-                        int nblocks, double* out, hipStream_t s);
-hipError_t launch_project(int eq, int k, const PhysDev& ph, const Geo& g, int ic,
-                          const double* params, const double* aux, double t, double* u,
+hipError_t launch_total(int eq, int k, int lay, const Geo& g, const void* u, int comp,
+                        double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& g, int ic,
+                          const double* params, const double* aux, double t, void* u,
                           hipStream_t s);
-hipError_t launch_limit(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
-                        double M, double* u, uint8_t* flags, unsigned long long* counters,
-                        hipStream_t s);
+hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, double M, void* u, uint8_t* flags,
+                        unsigned long long* counters, hipStream_t s);
 
 constexpr int RED_BLOCKS = 1024;  // blocks of the first reduction pass
 

@@ -1,4 +1,4 @@
-// crkdg_kernels.hip -- HIP kernels of the cRKDG step for gfx950 (FP64 path).
+// crkdg_kernels.hip -- HIP kernels of the cRKDG step for gfx950.
 //
 //   k_inner    all inner stages of one step, element local (Section 2.2,
 //              equation (crkdg), first line): one lane per cell, the whole
@@ -7,69 +7,142 @@
 //              cells per workgroup; stage traces are exchanged through LDS,
 //              every face flux is computed once per tile in canonical (+x/+y)
 //              orientation and the stage-weighted sum G = sum_i b_i F^(i)
-//              (equation (g)) is lifted into both neighbours with opposite
-//              signs, so the update is conservative (equation (avg)).
+//              (equation (g)) is accumulated in FP64 and lifted into both
+//              neighbours with opposite signs, so the cell-average update
+//              (equation (avg)) is conservative and done in FP64.
 //   k_final1   the same for 1D meshes.
 //   k_loc      one application of the local operator (materialised path).
 //   k_combine  RK stage combination, out = base + sum_j coef_j X_j (streaming).
 //   k_wave*    dt selection from the cell averages (max reduction).
 //   k_error*   L1/L2/Linf errors, deterministic two-pass reduction.
 //   k_project  L2 projection of an initial condition, (k+3)-point rule.
-//   k_limit    TVB minmod troubled-cell test and limited P1 reconstruction,
-//              in place (only a cell's own non-mean modes change).
+//   k_limit    TVB minmod troubled-cell test and limited P1 reconstruction
+//              in FP64, in place (only a cell's own non-mean modes change).
+//
+// Precision: the step kernels are templated on the compute type R.  R =
+// double is the plain FP64 method; R = float is the FP32-bulk form, in which
+// the cell averages stay FP64 in memory and in the final update, the stage
+// states of the inner stages are FP32, and the face-flux sums G are FP64.
 #include <math.h>
 
 #include "crkdg_internal.hpp"
 #include "dg_core.hpp"
 
+#ifndef INNER_OCC_F32
+#define INNER_OCC_F32 2
+#endif
+#ifndef INNER_OCC_F64
+#define INNER_OCC_F64 1
+#endif
+#ifndef FINAL_OCC_F32
+#define FINAL_OCC_F32 2
+#endif
+#ifndef FINAL_OCC_F64
+#define FINAL_OCC_F64 1
+#endif
+
 namespace crk {
 
-using R = double;
+// ---------------------------------------------------------------------------
+// state access (layouts in crkdg_internal.hpp)
+// ---------------------------------------------------------------------------
+template <class T, int NC, int NB, int LAY>
+__device__ __forceinline__ void load_state(const void* __restrict__ p, long long N, long long cell,
+                                           T (&u)[NC][NB]) {
+  if constexpr (LAY == L64) {
+    const double* q = (const double*)p;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = (T)q[(long long)(c * NB + b) * N + cell];
+  } else if constexpr (LAY == LMIX) {
+    const double* a = (const double*)p;
+    const float* h = (const float*)(a + (long long)NC * N);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u[c][0] = (T)a[(long long)c * N + cell];
+#pragma unroll
+      for (int b = 1; b < NB; ++b) u[c][b] = (T)h[(long long)(c * (NB - 1) + b - 1) * N + cell];
+    }
+  } else {
+    const float* q = (const float*)p;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = (T)q[(long long)(c * NB + b) * N + cell];
+  }
+}
 
-// ---------------------------------------------------------------------------
-// state access in the canonical layout u[comp][mode][cell]
-// ---------------------------------------------------------------------------
-template <int NC, int NB>
-__device__ __forceinline__ void load_state(const double* __restrict__ p, long long N, long long cell,
-                                           R (&u)[NC][NB]) {
+// store; the averages come from a0 (FP64) when given, else from u
+template <class T, int NC, int NB, int LAY>
+__device__ __forceinline__ void store_state(void* __restrict__ p, long long N, long long cell,
+                                            const T (&u)[NC][NB], const double* a0 = nullptr) {
+  if constexpr (LAY == L64) {
+    double* q = (double*)p;
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      q[(long long)(c * NB) * N + cell] = a0 ? a0[c] : (double)u[c][0];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) u[c][b] = p[(long long)(c * NB + b) * N + cell];
+      for (int b = 1; b < NB; ++b) q[(long long)(c * NB + b) * N + cell] = (double)u[c][b];
+    }
+  } else if constexpr (LAY == LMIX) {
+    double* a = (double*)p;
+    float* h = (float*)(a + (long long)NC * N);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      a[(long long)c * N + cell] = a0 ? a0[c] : (double)u[c][0];
+#pragma unroll
+      for (int b = 1; b < NB; ++b) h[(long long)(c * (NB - 1) + b - 1) * N + cell] = (float)u[c][b];
+    }
+  } else {
+    float* q = (float*)p;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) q[(long long)(c * NB + b) * N + cell] = (float)u[c][b];
+  }
 }
-template <int NC, int NB>
-__device__ __forceinline__ void store_state(double* __restrict__ p, long long N, long long cell,
-                                            const R (&u)[NC][NB]) {
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) p[(long long)(c * NB + b) * N + cell] = u[c][b];
+
+// cell average of component c (mode 0), as double
+template <int NC, int NB, int LAY>
+__device__ __forceinline__ double load_avg(const void* __restrict__ p, long long N, int c,
+                                           long long cell) {
+  if constexpr (LAY == L64) return ((const double*)p)[(long long)(c * NB) * N + cell];
+  else if constexpr (LAY == LMIX) return ((const double*)p)[(long long)c * N + cell];
+  else return (double)((const float*)p)[(long long)(c * NB) * N + cell];
 }
+
+// the step kernels' layout follows the compute type: FP64 layout for the
+// FP64 method, mixed layout (FP64 averages, FP32 higher modes) for FP32 bulk
+template <class EQ>
+struct StepLayout {
+  static constexpr int value = sizeof(typename EQ::Real) == 4 ? LMIX : L64;
+};
 
 template <class EQ>
-__device__ __forceinline__ EQ make_eq(const PhysDev& ph);
-template <>
-__device__ __forceinline__ Euler2<R> make_eq<Euler2<R>>(const PhysDev& ph) {
-  Euler2<R> e;
-  e.gam = ph.gamma;
-  e.gm1 = ph.gamma - 1.0;
-  return e;
-}
-template <>
-__device__ __forceinline__ Adv<R, 1> make_eq<Adv<R, 1>>(const PhysDev& ph) {
-  Adv<R, 1> e;
-  e.ax = ph.ax;
-  e.ay = 0.0;
-  e.upwind = ph.upwind;
-  return e;
-}
-template <>
-__device__ __forceinline__ Adv<R, 2> make_eq<Adv<R, 2>>(const PhysDev& ph) {
-  Adv<R, 2> e;
-  e.ax = ph.ax;
-  e.ay = ph.ay;
-  e.upwind = ph.upwind;
-  return e;
+struct MakeEq;
+template <class R>
+struct MakeEq<Euler2<R>> {
+  __device__ static Euler2<R> make(const PhysDev& ph) {
+    Euler2<R> e;
+    e.gam = (R)ph.gamma;
+    e.gm1 = (R)(ph.gamma - 1.0);
+    return e;
+  }
+};
+template <class R, int D>
+struct MakeEq<Adv<R, D>> {
+  __device__ static Adv<R, D> make(const PhysDev& ph) {
+    Adv<R, D> e;
+    e.ax = (R)ph.ax;
+    e.ay = D == 2 ? (R)ph.ay : R(0);
+    e.upwind = ph.upwind;
+    return e;
+  }
+};
+template <class EQ>
+__device__ __forceinline__ EQ make_eq(const PhysDev& ph) {
+  return MakeEq<EQ>::make(ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,25 +237,34 @@ __device__ void exact_state(int ic, const double* P, const double* aux, const Ge
 // ---------------------------------------------------------------------------
 // K1: inner stages (local operator only)
 // ---------------------------------------------------------------------------
+// occupancy targets (waves per SIMD) for the register-resident step kernels
 template <class EQ, int K>
-__global__ __launch_bounds__(256) void k_inner(PhysDev ph, Geo g, InnerArgs a) {
-  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
+struct Occ {
+  static constexpr bool F32 = sizeof(typename EQ::Real) == 4;
+  static constexpr int inner = F32 ? INNER_OCC_F32 : INNER_OCC_F64;
+  static constexpr int final_ = F32 ? FINAL_OCC_F32 : FINAL_OCC_F64;
+};
+
+template <class EQ, int K>
+__global__ __launch_bounds__(256, (Occ<EQ, K>::inner)) void k_inner(PhysDev ph, Geo g, InnerArgs a) {
+  using R = typename EQ::Real;
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, LAY = StepLayout<EQ>::value;
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   if (cell >= g.N) return;
   const EQ eq = make_eq<EQ>(ph);
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
   R u[NC][NB];
-  load_state<NC, NB>(a.un, g.N, cell, u);
+  load_state<R, NC, NB, LAY>(a.un, g.N, cell, u);
 #pragma unroll 1
   for (int i = 1; i < a.s; ++i) {
     R acc[NC][NB];
-    load_state<NC, NB>(a.un, g.N, cell, acc);
+    load_state<R, NC, NB, LAY>(a.un, g.N, cell, acc);
     loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[i]), R(g.inv_dx), R(g.inv_dy), acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
-    if ((a.store_mask >> i) & 1) store_state<NC, NB>(a.stage[i], g.N, cell, u);
+    if ((a.store_mask >> i) & 1) store_state<R, NC, NB, LAY>(a.stage[i], g.N, cell, u);
   }
 }
 
@@ -193,11 +275,12 @@ __global__ __launch_bounds__(256) void k_inner(PhysDev ph, Geo g, InnerArgs a) {
 //       2 bottom (its eta=+1 trace), 3 top (its eta=-1 trace).
 // own: this cell's trace on the shared face (used by the transmissive rule).
 template <class EQ, int K, int SIDE>
-__device__ __forceinline__ void neighbour_trace(const EQ& eq, const PhysDev& ph, const Geo& g,
-                                                const BCDev& bc, const double* __restrict__ S,
-                                                int i, int j, double tb,
-                                                const R (&own)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1],
-                                                R (&out)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1]) {
+__device__ __forceinline__ void neighbour_trace(const Geo& g, const PhysDev& ph, const BCDev& bc,
+                                                const void* __restrict__ S, int i, int j,
+                                                double tb,
+                                                const typename EQ::Real (&own)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1],
+                                                typename EQ::Real (&out)[EQ::NC][EQ::DIM == 2 ? K + 1 : 1]) {
+  using R = typename EQ::Real;
   constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, NP = EQ::DIM == 2 ? K + 1 : 1;
   int ni = i + (SIDE == 0 ? -1 : SIDE == 1 ? 1 : 0);
   int nj = j + (SIDE == 2 ? -1 : SIDE == 3 ? 1 : 0);
@@ -216,23 +299,28 @@ __device__ __forceinline__ void neighbour_trace(const EQ& eq, const PhysDev& ph,
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         double q[4];
-        if (bc.exact > 0) {
-          const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-          double x, y;
-          if (SIDE < 2) {
-            x = xc + (SIDE == 0 ? -0.5 : 0.5) * g.dx;
-            y = EQ::DIM == 2 ? yc + 0.5 * g.dy * T.X[p] : 0.0;
-          } else {
-            x = xc + 0.5 * g.dx * T.X[p];
-            y = yc + (SIDE == 2 ? -0.5 : 0.5) * g.dy;
-          }
-          exact_state<EQ>(bc.exact, bc.params, nullptr, g, ph, x, y, tb, q);
-        } else {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) q[c] = bc.state[SIDE][c];
+        for (int c = 0; c < NC; ++c) q[c] = bc.state[SIDE][c];
+        if constexpr (!EQ::EULER) {
+          // time-dependent inflow data (advection only): the exact solution
+          // sin(x - a t) (1D) / sin(pi(x - a t)) sin(pi(y - b t)) (2D) at the
+          // stage time
+          if (bc.exact == CRKDG_IC_ADV_SIN) {
+            const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
+            double x, y;
+            if (SIDE < 2) {
+              x = xc + (SIDE == 0 ? -0.5 : 0.5) * g.dx;
+              y = EQ::DIM == 2 ? yc + 0.5 * g.dy * T.X[p] : 0.0;
+            } else {
+              x = xc + 0.5 * g.dx * T.X[p];
+              y = yc + (SIDE == 2 ? -0.5 : 0.5) * g.dy;
+            }
+            q[0] = EQ::DIM == 1 ? sin(x - ph.ax * tb)
+                                : sin(M_PI * (x - ph.ax * tb)) * sin(M_PI * (y - ph.ay * tb));
+          }
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[c][p] = q[c];
+        for (int c = 0; c < NC; ++c) out[c][p] = (R)q[c];
       }
       return;
     }
@@ -242,7 +330,7 @@ __device__ __forceinline__ void neighbour_trace(const EQ& eq, const PhysDev& ph,
     if (nj >= g.ny) nj -= g.ny;
   }
   R U[NC][NB];
-  load_state<NC, NB>(S, g.N, (long long)nj * g.nx + ni, U);
+  load_state<R, NC, NB, StepLayout<EQ>::value>(S, g.N, (long long)nj * g.nx + ni, U);
   if constexpr (SIDE == 0) trace_x<+1, EQ, K, R>(U, out);
   if constexpr (SIDE == 1) trace_x<-1, EQ, K, R>(U, out);
   if constexpr (SIDE == 2) trace_y<+1, EQ, K, R>(U, out);
@@ -254,11 +342,38 @@ __device__ __forceinline__ void neighbour_trace(const EQ& eq, const PhysDev& ph,
 // ---------------------------------------------------------------------------
 constexpr int BX = 64, BY = 4;
 
+template <class R, int NV>
+struct FinalSmem {
+  // traces of the current stage (R): right-face traces [v][ty][tx+1] with the
+  // left halo in column 0; top-face traces [v][ty+1][tx] with the bottom halo
+  // in row 0; the right/top neighbours' traces for the tile's edge faces
+  static constexpr int NR = NV * BY * (BX + 1), NT = NV * (BY + 1) * BX;
+  static constexpr int NLH = NV * BY, NBH = NV * BX;
+  static constexpr size_t TRACE_BYTES = sizeof(R) * (NR + NT + NLH + NBH);
+  // after the stage loop the same bytes hold every cell's left/bottom G (FP64)
+  static constexpr size_t GEX_BYTES = sizeof(double) * (2 * NV * BY * BX);
+  static constexpr size_t UNION_BYTES = TRACE_BYTES > GEX_BYTES ? TRACE_BYTES : GEX_BYTES;
+  // edge-face G of the tile's last column / row (FP64), alive over all stages
+  static constexpr size_t EDGE_BYTES = sizeof(double) * (NV * BY + NV * BX);
+  static constexpr size_t BYTES = UNION_BYTES + EDGE_BYTES;
+};
+
 template <class EQ, int K>
-__global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, FinalArgs a) {
-  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q;
-  __shared__ R sR[NV][BY][BX + 1];   // [.][ty][tx+1]: right-face traces; [.][ty][0]: halo
-  __shared__ R sT[NV][BY + 1][BX];   // [.][ty+1][tx]: top-face traces;   [.][0][tx]: halo
+__global__ __launch_bounds__(BX* BY, (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
+                                                                      FinalArgs a) {
+  using R = typename EQ::Real;
+  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q, LAY = StepLayout<EQ>::value;
+  using SM = FinalSmem<R, NV>;
+  __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
+  R(*sR)[BY][BX + 1] = reinterpret_cast<R(*)[BY][BX + 1]>(smem);
+  R(*sT)[BY + 1][BX] = reinterpret_cast<R(*)[BY + 1][BX]>(smem + sizeof(R) * SM::NR);
+  R(*sLh)[BY] = reinterpret_cast<R(*)[BY]>(smem + sizeof(R) * (SM::NR + SM::NT));
+  R(*sBh)[BX] = reinterpret_cast<R(*)[BX]>(smem + sizeof(R) * (SM::NR + SM::NT + SM::NLH));
+  double(*gx)[BY][BX] = reinterpret_cast<double(*)[BY][BX]>(smem);
+  double(*gy)[BY][BX] = reinterpret_cast<double(*)[BY][BX]>(smem + sizeof(double) * NV * BY * BX);
+  double(*gR)[BY] = reinterpret_cast<double(*)[BY]>(smem + SM::UNION_BYTES);
+  double(*gT)[BX] = reinterpret_cast<double(*)[BX]>(smem + SM::UNION_BYTES + sizeof(double) * NV * BY);
+
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty;
   const bool active = i < g.nx && j < g.ny;
@@ -269,41 +384,54 @@ __global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, 
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
 
   R acc[NC][NB];
-  R GL[NC][Q], GB[NC][Q], GR[NC][Q], GT[NC][Q];
+  double a0[NC];         // cell averages, FP64
+  double GL[NC][Q], GB[NC][Q];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
+    for (int b = 0; b < NB; ++b) acc[c][b] = R(0);
+    a0[c] = 0.0;
 #pragma unroll
-    for (int p = 0; p < Q; ++p) GL[c][p] = GB[c][p] = GR[c][p] = GT[c][p] = 0.0;
+    for (int p = 0; p < Q; ++p) GL[c][p] = GB[c][p] = 0.0;
   }
-  if (active && a.base) load_state<NC, NB>(a.base, g.N, cell, acc);
+  if (active && a.base) {
+    load_state<R, NC, NB, LAY>(a.base, g.N, cell, acc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a0[c] = load_avg<NC, NB, LAY>(a.base, g.N, c, cell);
+  }
+  if (last_col)
+    for (int v = 0; v < NV; ++v) gR[v][ty] = 0.0;
+  if (last_row)
+    for (int v = 0; v < NV; ++v) gT[v][tx] = 0.0;
 
 #pragma unroll 1
   for (int s = 0; s < a.ns; ++s) {
-    const double* __restrict__ S = a.st[s];
-    const R w = a.w[s];
-    R tL[NC][Q], tB[NC][Q], tRn[NC][Q], tTn[NC][Q];
+    const void* __restrict__ S = a.st[s];
+    const double w = a.w[s];
+    R tL[NC][Q], tB[NC][Q];
     if (active) {
-      R U[NC][NB];
-      load_state<NC, NB>(S, g.N, cell, U);
-      const R vs = R(0.5) * dt * w;
-      volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
-      R tR[NC][Q], tT[NC][Q];
-      trace_x<+1, EQ, K, R>(U, tR);
-      trace_x<-1, EQ, K, R>(U, tL);
-      trace_y<+1, EQ, K, R>(U, tT);
-      trace_y<-1, EQ, K, R>(U, tB);
+      {
+        R U[NC][NB];
+        load_state<R, NC, NB, LAY>(S, g.N, cell, U);
+        const R vs = R(0.5 * dt * w);
+        volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
+        R t[NC][Q];
+        trace_x<+1, EQ, K, R>(U, t);
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          sR[c * Q + p][ty][tx + 1] = tR[c][p];
-          sT[c * Q + p][ty + 1][tx] = tT[c][p];
-        }
+          for (int p = 0; p < Q; ++p) sR[c * Q + p][ty][tx + 1] = t[c][p];
+        trace_y<+1, EQ, K, R>(U, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) sT[c * Q + p][ty + 1][tx] = t[c][p];
+        trace_x<-1, EQ, K, R>(U, tL);
+        trace_y<-1, EQ, K, R>(U, tB);
+      }
       if (tx == 0) {
         R h[NC][Q];
-        neighbour_trace<EQ, K, 0>(eq, ph, g, bc, S, i, j, a.tst[s], tL, h);
+        neighbour_trace<EQ, K, 0>(g, ph, bc, S, i, j, a.tst[s], tL, h);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -311,16 +439,56 @@ __global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, 
       }
       if (ty == 0) {
         R h[NC][Q];
-        neighbour_trace<EQ, K, 2>(eq, ph, g, bc, S, i, j, a.tst[s], tB, h);
+        neighbour_trace<EQ, K, 2>(g, ph, bc, S, i, j, a.tst[s], tB, h);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
           for (int p = 0; p < Q; ++p) sT[c * Q + p][0][tx] = h[c][p];
       }
-      if (last_col) neighbour_trace<EQ, K, 1>(eq, ph, g, bc, S, i, j, a.tst[s], tR, tRn);
-      if (last_row) neighbour_trace<EQ, K, 3>(eq, ph, g, bc, S, i, j, a.tst[s], tT, tTn);
     }
     __syncthreads();
+    // the right / top neighbours' traces for the edge faces: the own trace is
+    // in LDS now, needed by the transmissive ghost rule
+    if (last_col) {
+      R own[NC][Q], h[NC][Q];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) own[c][p] = sR[c * Q + p][ty][tx + 1];
+      neighbour_trace<EQ, K, 1>(g, ph, bc, S, i, j, a.tst[s], own, h);
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        R qa[NC], qb[NC], F[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = own[c][p];
+          qb[c] = h[c][p];
+        }
+        eq.template num_flux<0>(qa, qb, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gR[c * Q + p][ty] += w * (double)F[c];
+      }
+    }
+    if (last_row) {
+      R own[NC][Q], h[NC][Q];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) own[c][p] = sT[c * Q + p][ty + 1][tx];
+      neighbour_trace<EQ, K, 3>(g, ph, bc, S, i, j, a.tst[s], own, h);
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        R qa[NC], qb[NC], F[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = own[c][p];
+          qb[c] = h[c][p];
+        }
+        eq.template num_flux<1>(qa, qb, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gT[c * Q + p][tx] += w * (double)F[c];
+      }
+    }
     if (active) {
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
@@ -332,7 +500,7 @@ __global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, 
         }
         eq.template num_flux<0>(qa, qb, F);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) GL[c][p] = GL[c][p] + w * F[c];
+        for (int c = 0; c < NC; ++c) GL[c][p] += w * (double)F[c];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           qa[c] = sT[c * Q + p][ty][tx];
@@ -340,76 +508,77 @@ __global__ __launch_bounds__(BX* BY) void k_final2(PhysDev ph, Geo g, BCDev bc, 
         }
         eq.template num_flux<1>(qa, qb, F);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) GB[c][p] = GB[c][p] + w * F[c];
-      }
-      if (last_col) {
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          R qa[NC], qb[NC], F[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            qa[c] = sR[c * Q + p][ty][tx + 1];
-            qb[c] = tRn[c][p];
-          }
-          eq.template num_flux<0>(qa, qb, F);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) GR[c][p] = GR[c][p] + w * F[c];
-        }
-      }
-      if (last_row) {
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          R qa[NC], qb[NC], F[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            qa[c] = sT[c * Q + p][ty + 1][tx];
-            qb[c] = tTn[c][p];
-          }
-          eq.template num_flux<1>(qa, qb, F);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) GT[c][p] = GT[c][p] + w * F[c];
-        }
+        for (int c = 0; c < NC; ++c) GB[c][p] += w * (double)F[c];
       }
     }
     __syncthreads();
   }
-  // share the combined fluxes: a cell's right face is its right neighbour's left face
+  // a cell's right face is its right neighbour's left face: share G
   if (active) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
-        sR[c * Q + p][ty][tx] = GL[c][p];
-        sT[c * Q + p][ty][tx] = GB[c][p];
+        gx[c * Q + p][ty][tx] = GL[c][p];
+        gy[c * Q + p][ty][tx] = GB[c][p];
       }
   }
   __syncthreads();
   if (!active) return;
-  if (!last_col) {
+  double GR[NC][Q], GT[NC][Q];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      GR[c][p] = last_col ? gR[c * Q + p][ty] : gx[c * Q + p][ty][tx + 1];
+      GT[c][p] = last_row ? gT[c * Q + p][tx] : gy[c * Q + p][ty + 1][tx];
+    }
+  // cell averages: FP64 update from the FP64 face sums (equation (avg))
+  {
+    constexpr GTab<Q> T = Tab<Q>::t;
+    const double lx = -0.5 * dt * g.inv_dx, ly = -0.5 * dt * g.inv_dy;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        sx += T.W[p] * (GR[c][p] - GL[c][p]);
+        sy += T.W[p] * (GT[c][p] - GB[c][p]);
+      }
+      a0[c] += lx * sx + ly * sy;
+    }
+  }
+  // higher modes in the compute precision
+  {
+    R gr[NC][Q], gl[NC][Q];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int p = 0; p < Q; ++p) GR[c][p] = sR[c * Q + p][ty][tx + 1];
-  }
-  if (!last_row) {
+      for (int p = 0; p < Q; ++p) {
+        gr[c][p] = (R)GR[c][p];
+        gl[c][p] = (R)GL[c][p];
+      }
+    lift_x<EQ, K, R>(gr, gl, R(-0.5 * dt * g.inv_dx), acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int p = 0; p < Q; ++p) GT[c][p] = sT[c * Q + p][ty + 1][tx];
+      for (int p = 0; p < Q; ++p) {
+        gr[c][p] = (R)GT[c][p];
+        gl[c][p] = (R)GB[c][p];
+      }
+    lift_y<EQ, K, R>(gr, gl, R(-0.5 * dt * g.inv_dy), acc);
   }
-  const R ls = R(-0.5) * dt;
-  lift_x<EQ, K, R>(GR, GL, ls * R(g.inv_dx), acc);
-  lift_y<EQ, K, R>(GT, GB, ls * R(g.inv_dy), acc);
-  store_state<NC, NB>(a.out, g.N, cell, acc);
+  store_state<R, NC, NB, LAY>(a.out, g.N, cell, acc, a0);
 }
 
 // ---------------------------------------------------------------------------
-// K2 (1D): final stage on a row of 256 cells
+// K2 (1D): final stage on a row of 256 cells (FP64 only)
 // ---------------------------------------------------------------------------
 constexpr int B1 = 256;
 
 template <class EQ, int K>
 __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, FinalArgs a) {
+  using R = typename EQ::Real;
   constexpr int NC = EQ::NC, NB = K + 1;
   __shared__ R sR[NC][B1 + 1];
   const int tx = threadIdx.x;
@@ -425,15 +594,15 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
     for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
     GL[c][0] = GR[c][0] = 0.0;
   }
-  if (active && a.base) load_state<NC, NB>(a.base, g.N, i, acc);
+  if (active && a.base) load_state<R, NC, NB, L64>(a.base, g.N, i, acc);
 #pragma unroll 1
   for (int s = 0; s < a.ns; ++s) {
-    const double* __restrict__ S = a.st[s];
+    const void* __restrict__ S = a.st[s];
     const R w = a.w[s];
     R tL[NC][1], tR[NC][1], tRn[NC][1];
     if (active) {
       R U[NC][NB];
-      load_state<NC, NB>(S, g.N, i, U);
+      load_state<R, NC, NB, L64>(S, g.N, i, U);
       volume_acc<EQ, K, R>(eq, U, dt * w * R(g.inv_dx), R(0), acc);
       trace_x<+1, EQ, K, R>(U, tR);
       trace_x<-1, EQ, K, R>(U, tL);
@@ -441,11 +610,11 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
       for (int c = 0; c < NC; ++c) sR[c][tx + 1] = tR[c][0];
       if (tx == 0) {
         R h[NC][1];
-        neighbour_trace<EQ, K, 0>(eq, ph, g, bc, S, i, 0, a.tst[s], tL, h);
+        neighbour_trace<EQ, K, 0>(g, ph, bc, S, i, 0, a.tst[s], tL, h);
 #pragma unroll
         for (int c = 0; c < NC; ++c) sR[c][0] = h[c][0];
       }
-      if (last_col) neighbour_trace<EQ, K, 1>(eq, ph, g, bc, S, i, 0, a.tst[s], tR, tRn);
+      if (last_col) neighbour_trace<EQ, K, 1>(g, ph, bc, S, i, 0, a.tst[s], tR, tRn);
     }
     __syncthreads();
     if (active) {
@@ -482,27 +651,28 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
     for (int c = 0; c < NC; ++c) GR[c][0] = sR[c][tx + 1];
   }
   lift_x<EQ, K, R>(GR, GL, R(-dt) * R(g.inv_dx), acc);
-  store_state<NC, NB>(a.out, g.N, i, acc);
+  store_state<R, NC, NB, L64>(a.out, g.N, i, acc);
 }
 
 // ---------------------------------------------------------------------------
-// local operator applied once: out = loc(in)
+// local operator applied once: out = loc(in)   (FP64 layout)
 // ---------------------------------------------------------------------------
 template <class EQ, int K>
 __global__ __launch_bounds__(256) void k_loc(PhysDev ph, Geo g, const double* __restrict__ in,
                                              double* __restrict__ out) {
+  using R = typename EQ::Real;
   constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   if (cell >= g.N) return;
   const EQ eq = make_eq<EQ>(ph);
   R u[NC][NB], acc[NC][NB];
-  load_state<NC, NB>(in, g.N, cell, u);
+  load_state<R, NC, NB, L64>(in, g.N, cell, u);
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
   loc_acc<EQ, K, R>(eq, u, R(1), R(g.inv_dx), R(g.inv_dy), acc);
-  store_state<NC, NB>(out, g.N, cell, acc);
+  store_state<R, NC, NB, L64>(out, g.N, cell, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,16 +721,7 @@ __global__ __launch_bounds__(256) void k_combine(long long n, CombineArgs a) {
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double w = __shfl_xor(v, o, 64);
-    v = (w > v || w != w) ? w : v;  // propagate NaN
-  }
-  return v;
-}
-
-// deterministic block sum: fixed tree in LDS
+// deterministic block sum / max: fixed tree in LDS
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int t = threadIdx.x;
@@ -606,8 +767,8 @@ __device__ __forceinline__ double cell_speed(const PhysDev& ph, const Geo& g, co
   }
 }
 
-template <class EQ, int K>
-__global__ __launch_bounds__(256) void k_wave_partial(PhysDev ph, Geo g, const double* __restrict__ u,
+template <class EQ, int K, int LAY>
+__global__ __launch_bounds__(256) void k_wave_partial(PhysDev ph, Geo g, const void* __restrict__ u,
                                                       double* __restrict__ partial) {
   constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
   __shared__ double sh[256];
@@ -616,7 +777,7 @@ __global__ __launch_bounds__(256) void k_wave_partial(PhysDev ph, Geo g, const d
        cell += (long long)gridDim.x * 256) {
     double q[4];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = u[(long long)(c * NB) * g.N + cell];
+    for (int c = 0; c < NC; ++c) q[c] = load_avg<NC, NB, LAY>(u, g.N, c, cell);
     const double s = cell_speed<EQ>(ph, g, q);
     if (s > m || s != s) m = s;
   }
@@ -639,9 +800,10 @@ __global__ __launch_bounds__(256) void k_wave_final(const double* __restrict__ p
   }
 }
 
-template <class EQ, int K>
-__global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const double* __restrict__ u,
-                                                       int ic, const double* __restrict__ params,
+template <class EQ, int K, int LAY>
+__global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const void* __restrict__ u,
+                                                       int ic,
+                                                       const double* __restrict__ params,
                                                        const double* __restrict__ aux, double t,
                                                        int comp, double* __restrict__ partial) {
   constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, Q = K + 1, QE = K + 3;
@@ -656,9 +818,8 @@ __global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const 
        cell += (long long)gridDim.x * 256) {
     const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
     const double xc = g.x0 + (i + 0.5) * g.dx, yc = g.y0 + (j + 0.5) * g.dy;
-    double U[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) U[b] = u[(long long)(comp * NB + b) * g.N + cell];
+    double Ua[NC][NB];
+    load_state<double, NC, NB, LAY>(u, g.N, cell, Ua);
 #pragma unroll
     for (int a = 0; a < QE; ++a)
 #pragma unroll
@@ -668,7 +829,7 @@ __global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const 
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int m = b % Q, n = b / Q;
-          v += U[b] * leg(m, xi) * (DIM == 2 ? leg(n, eta) : 1.0);
+          v += Ua[comp][b] * leg(m, xi) * (DIM == 2 ? leg(n, eta) : 1.0);
         }
         double q[4];
         exact_state<EQ>(ic, P, aux, g, ph, xc + 0.5 * g.dx * xi, yc + 0.5 * g.dy * eta, t, q);
@@ -689,15 +850,15 @@ __global__ __launch_bounds__(256) void k_error_partial(PhysDev ph, Geo g, const 
   }
 }
 
-template <class EQ, int K>
-__global__ __launch_bounds__(256) void k_total_partial(Geo g, const double* __restrict__ u, int comp,
-                                                       double* __restrict__ partial) {
-  constexpr int NB = Sizes<K, EQ::DIM>::NB;
+template <class EQ, int K, int LAY>
+__global__ __launch_bounds__(256) void k_total_partial(Geo g, const void* __restrict__ u,
+                                                       int comp, double* __restrict__ partial) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
   __shared__ double sh[256];
   double s = 0.0;
   for (long long cell = (long long)blockIdx.x * 256 + threadIdx.x; cell < g.N;
        cell += (long long)gridDim.x * 256)
-    s += u[(long long)(comp * NB) * g.N + cell];
+    s += load_avg<NC, NB, LAY>(u, g.N, comp, cell);
   s = block_sum<256>(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -726,13 +887,13 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-// L2 projection of an initial condition with a (k+3)-point rule
+// L2 projection of an initial condition with a (k+3)-point rule (FP64 math)
 // ---------------------------------------------------------------------------
-template <class EQ, int K>
+template <class EQ, int K, int LAY>
 __global__ __launch_bounds__(256) void k_project(PhysDev ph, Geo g, int ic,
                                                  const double* __restrict__ params,
                                                  const double* __restrict__ aux, double t,
-                                                 double* __restrict__ u) {
+                                                 void* __restrict__ u) {
   constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, Q = K + 1, QE = K + 3;
   constexpr int DIM = EQ::DIM;
   constexpr GTab<QE> E = Tab<QE>::t;
@@ -761,12 +922,13 @@ __global__ __launch_bounds__(256) void k_project(PhysDev ph, Geo g, int ic,
     for (int b = 0; b < NB; ++b) {
       const int m = b % Q, n = b / Q;
       const double norm = DIM == 2 ? (2 * m + 1) * (2 * n + 1) / 4.0 : (2 * m + 1) / 2.0;
-      u[(long long)(c * NB + b) * g.N + cell] = acc[c][b] * norm;
+      acc[c][b] *= norm;
     }
+  store_state<double, NC, NB, LAY>(u, g.N, cell, acc);
 }
 
 // ---------------------------------------------------------------------------
-// TVB minmod limiter, once per step after the final stage (in place)
+// TVB minmod limiter, once per step after the final stage (in place, FP64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double minmod3(double a, double b, double c) {
   const bool pos = a > 0.0 && b > 0.0 && c > 0.0;
@@ -812,36 +974,56 @@ __device__ void euler_eigvec(double gamma, const double* q, int d, double* L, do
     }
 }
 
-template <class EQ, int K>
-__device__ bool physical_points(const PhysDev& ph, const double (&U)[EQ::NC][Sizes<K, EQ::DIM>::NB]) {
-  if constexpr (!EQ::EULER) {
-    return true;
-  } else {
-    constexpr int Q = K + 1, NB = Q * Q;
-    constexpr GTab<Q> T = Tab<Q>::t;
-    auto ok = [&](double xi, double eta) {
+// density and pressure positive at the operator's volume and face points
+template <int K>
+__device__ bool physical_points(double gamma, const double (&U)[4][(K + 1) * (K + 1)]) {
+  constexpr int Q = K + 1;
+  Euler2<double> eq;
+  eq.gam = gamma;
+  eq.gm1 = gamma - 1.0;
+  auto ok = [&](const double* q) {
+    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+    return q[0] > 0.0 && p > 0.0;
+  };
+  // volume points, line by line (x fastest in the reference square)
+  constexpr GTab<Q> T = Tab<Q>::t;
+  for (int a = 0; a < Q; ++a) {
+    for (int b = 0; b < Q; ++b) {
       double q[4];
       for (int c = 0; c < 4; ++c) {
         double s = 0.0;
-        for (int b = 0; b < NB; ++b) s += U[c][b] * leg(b % Q, xi) * leg(b / Q, eta);
+        for (int n = 0; n < Q; ++n) {
+          double t = 0.0;
+          for (int m = 0; m < Q; ++m) t += U[c][m + Q * n] * T.P[m][a];
+          s += t * T.P[n][b];
+        }
         q[c] = s;
       }
-      const double p = (ph.gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
-      return q[0] > 0.0 && p > 0.0;
-    };
-    for (int a = 0; a < Q; ++a) {
-      for (int b = 0; b < Q; ++b)
-        if (!ok(T.X[a], T.X[b])) return false;
-      if (!ok(-1.0, T.X[a]) || !ok(1.0, T.X[a]) || !ok(T.X[a], -1.0) || !ok(T.X[a], 1.0))
-        return false;
+      if (!ok(q)) return false;
+    }
+  }
+  double tr[4][Q];
+  auto face_ok = [&]() {
+    for (int p = 0; p < Q; ++p) {
+      double q[4] = {tr[0][p], tr[1][p], tr[2][p], tr[3][p]};
+      if (!ok(q)) return false;
     }
     return true;
-  }
+  };
+  trace_x<+1, Euler2<double>, K, double>(U, tr);
+  if (!face_ok()) return false;
+  trace_x<-1, Euler2<double>, K, double>(U, tr);
+  if (!face_ok()) return false;
+  trace_y<+1, Euler2<double>, K, double>(U, tr);
+  if (!face_ok()) return false;
+  trace_y<-1, Euler2<double>, K, double>(U, tr);
+  return face_ok();
 }
 
-template <class EQ, int K>
+template <class EQ, int K, int LAY>
 __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, double M,
-                                               double* __restrict__ u, uint8_t* __restrict__ flags,
+                                               void* __restrict__ u,
+                                               uint8_t* __restrict__ flags,
                                                unsigned long long* __restrict__ counters) {
   constexpr int NC = EQ::NC, DIM = EQ::DIM, Q = K + 1, NB = Sizes<K, DIM>::NB;
   __shared__ unsigned int cnt[2];
@@ -853,9 +1035,10 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
   if (cell < g.N) {
     const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
     double U[NC][NB];
-    load_state<NC, NB>(u, g.N, cell, U);
+    load_state<double, NC, NB, LAY>(u, g.N, cell, U);
     double avg[NC];
-    for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
+    for (int c = 0; c < NC; ++c) avg[c] = load_avg<NC, NB, LAY>(u, g.N, c, cell);
+    for (int c = 0; c < NC; ++c) U[c][0] = avg[c];
     if constexpr (EQ::EULER) {
       const double p = (ph.gamma - 1.0) * (avg[3] - 0.5 * (avg[1] * avg[1] + avg[2] * avg[2]) / avg[0]);
       bad = !(avg[0] > 0.0) || !(p > 0.0);
@@ -877,20 +1060,19 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
         ni = (ni + g.nx) % g.nx;
         nj = (nj + g.ny) % g.ny;
       }
-      for (int c = 0; c < NC; ++c) qa[c] = u[(long long)(c * NB) * g.N + (long long)nj * g.nx + ni];
+      for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
     };
     auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
-    double dp[2][NC], dm[2][NC];
     bool troubled = false;
     if (K >= 1 && !bad) {
       for (int d = 0; d < DIM; ++d) {
         const double h = d == 0 ? g.dx : g.dy;
         const double Mh2 = M * h * h;
-        double qn[NC], a[NC], at[NC];
+        double qn[NC], a[NC], at[NC], dp[NC], dm[NC];
         nbr_avg(d, +1, qn);
-        for (int c = 0; c < NC; ++c) dp[d][c] = qn[c] - avg[c];
+        for (int c = 0; c < NC; ++c) dp[c] = qn[c] - avg[c];
         nbr_avg(d, -1, qn);
-        for (int c = 0; c < NC; ++c) dm[d][c] = avg[c] - qn[c];
+        for (int c = 0; c < NC; ++c) dm[c] = avg[c] - qn[c];
         for (int c = 0; c < NC; ++c) {
           a[c] = 0.0;
           at[c] = 0.0;
@@ -909,13 +1091,13 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
             for (int c = 0; c < NC; ++c) {
               ca[r] += L[r * 4 + c] * a[c];
               cat[r] += L[r * 4 + c] * at[c];
-              cp[r] += L[r * 4 + c] * dp[d][c];
-              cm[r] += L[r * 4 + c] * dm[d][c];
+              cp[r] += L[r * 4 + c] * dp[c];
+              cm[r] += L[r * 4 + c] * dm[c];
             }
           }
         } else {
           for (int c = 0; c < NC; ++c) {
-            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
+            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[c]; cm[c] = dm[c];
           }
         }
         for (int r = 0; r < NC; ++r)
@@ -929,13 +1111,12 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
         const double h = d == 0 ? g.dx : g.dy;
         const double Mh2 = M * h * h;
         const int sm = mode_of(d, 1);
-        double sl[NC], pp[NC], mm[NC];
-        double qn[NC];
+        double sl[NC], pp[NC], mm[NC], qn[NC];
         nbr_avg(d, +1, qn);
         for (int c = 0; c < NC; ++c) pp[c] = qn[c] - avg[c];
         nbr_avg(d, -1, qn);
         for (int c = 0; c < NC; ++c) mm[c] = avg[c] - qn[c];
-        for (int c = 0; c < NC; ++c) sl[c] = U[c][sm];
+        for (int c = 0; c < NC; ++c) sl[c] = V[c][sm];
         if constexpr (EQ::EULER) {
           double L[16], Rm[16], lim[NC];
           euler_eigvec(ph.gamma, avg, d, L, Rm);
@@ -969,20 +1150,18 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
       changed = true;
     }
     if constexpr (EQ::EULER) {
-      if (!bad && K >= 1 && !physical_points<EQ, K>(ph, U)) {
+      if (!bad && K >= 1 && !physical_points<K>(ph.gamma, U)) {
         if (!troubled) reconstruct(U);
         flag = 2;
         changed = true;
-        if (!physical_points<EQ, K>(ph, U)) {
+        if (!physical_points<K>(ph.gamma, U)) {
           for (int c = 0; c < NC; ++c)
             for (int b = 1; b < NB; ++b) U[c][b] = 0.0;
           flag = 3;
         }
       }
     }
-    if (changed)
-      for (int c = 0; c < NC; ++c)
-        for (int b = 1; b < NB; ++b) u[(long long)(c * NB + b) * g.N + cell] = U[c][b];
+    if (changed) store_state<double, NC, NB, LAY>(u, g.N, cell, U, avg);
     if (flags) flags[cell] = flag;
   }
   if (counters) {
@@ -1003,8 +1182,8 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <template <class, int> class F, class... A>
-hipError_t dispatch(int eq, int k, A&&... args) {
+template <template <class, int> class F, class R, class... A>
+hipError_t dispatch_r(int eq, int k, A&&... args) {
   switch (eq * 4 + k) {
     case EQ_ADV1 * 4 + 0: return F<Adv<R, 1>, 0>::run(args...);
     case EQ_ADV1 * 4 + 1: return F<Adv<R, 1>, 1>::run(args...);
@@ -1018,6 +1197,21 @@ hipError_t dispatch(int eq, int k, A&&... args) {
     case EQ_EULER2 * 4 + 1: return F<Euler2<R>, 1>::run(args...);
     case EQ_EULER2 * 4 + 2: return F<Euler2<R>, 2>::run(args...);
     case EQ_EULER2 * 4 + 3: return F<Euler2<R>, 3>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <template <class, int> class F, class... A>
+hipError_t dispatch(int eq, int k, A&&... args) {
+  return dispatch_r<F, double>(eq, k, args...);
+}
+// FP32-bulk kernels exist for 2D Euler, k = 1..3
+template <template <class, int> class F, class... A>
+hipError_t dispatch_mixed(int eq, int k, A&&... args) {
+  if (eq != EQ_EULER2) return hipErrorInvalidValue;
+  switch (k) {
+    case 1: return F<Euler2<float>, 1>::run(args...);
+    case 2: return F<Euler2<float>, 2>::run(args...);
+    case 3: return F<Euler2<float>, 3>::run(args...);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1054,29 +1248,39 @@ struct RunLoc {
 };
 template <class EQ, int K>
 struct RunWave {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const double* u, double* partial,
+  static hipError_t run(const PhysDev& ph, const Geo& g, const void* u, int lay, double* partial,
                         int nb, double cfl, double* smax, double* dt, hipStream_t s) {
-    hipLaunchKernelGGL((k_wave_partial<EQ, K>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
+    if (lay == LMIX)
+      hipLaunchKernelGGL((k_wave_partial<EQ, K, LMIX>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
+    else
+      hipLaunchKernelGGL((k_wave_partial<EQ, K, L64>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
     hipLaunchKernelGGL(k_wave_final, dim3(1), dim3(256), 0, s, partial, nb, cfl, smax, dt);
     return hipGetLastError();
   }
 };
 template <class EQ, int K>
 struct RunError {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const double* u, int ic,
+  static hipError_t run(const PhysDev& ph, const Geo& g, const void* u, int lay, int ic,
                         const double* params, const double* aux, double t, int comp,
                         double* partial, int nb, double* out3, hipStream_t s) {
-    hipLaunchKernelGGL((k_error_partial<EQ, K>), dim3(nb), dim3(256), 0, s, ph, g, u, ic, params,
-                       aux, t, comp, partial);
+    if (lay == LMIX)
+      hipLaunchKernelGGL((k_error_partial<EQ, K, LMIX>), dim3(nb), dim3(256), 0, s, ph, g, u, ic,
+                         params, aux, t, comp, partial);
+    else
+      hipLaunchKernelGGL((k_error_partial<EQ, K, L64>), dim3(nb), dim3(256), 0, s, ph, g, u, ic,
+                         params, aux, t, comp, partial);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, 3, 1.0, out3);
     return hipGetLastError();
   }
 };
 template <class EQ, int K>
 struct RunTotal {
-  static hipError_t run(const Geo& g, const double* u, int comp, double* partial, int nb,
+  static hipError_t run(const Geo& g, const void* u, int lay, int comp, double* partial, int nb,
                         double* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_total_partial<EQ, K>), dim3(nb), dim3(256), 0, s, g, u, comp, partial);
+    if (lay == LMIX)
+      hipLaunchKernelGGL((k_total_partial<EQ, K, LMIX>), dim3(nb), dim3(256), 0, s, g, u, comp, partial);
+    else
+      hipLaunchKernelGGL((k_total_partial<EQ, K, L64>), dim3(nb), dim3(256), 0, s, g, u, comp, partial);
     const double area = g.dx * (EQ::DIM == 2 ? g.dy : 1.0);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, 1, area, out);
     return hipGetLastError();
@@ -1085,30 +1289,39 @@ struct RunTotal {
 template <class EQ, int K>
 struct RunProject {
   static hipError_t run(const PhysDev& ph, const Geo& g, int ic, const double* params,
-                        const double* aux, double t, double* u, hipStream_t s) {
-    hipLaunchKernelGGL((k_project<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, ic, params,
-                       aux, t, u);
+                        const double* aux, double t, void* u, int lay, hipStream_t s) {
+    if (lay == LMIX)
+      hipLaunchKernelGGL((k_project<EQ, K, LMIX>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, ic,
+                         params, aux, t, u);
+    else
+      hipLaunchKernelGGL((k_project<EQ, K, L64>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, ic,
+                         params, aux, t, u);
     return hipGetLastError();
   }
 };
 template <class EQ, int K>
 struct RunLimit {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, double M, double* u,
-                        uint8_t* flags, unsigned long long* counters, hipStream_t s) {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, double M, void* u,
+                        int lay, uint8_t* flags, unsigned long long* counters, hipStream_t s) {
     if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 2);
-    hipLaunchKernelGGL((k_limit<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M, u,
-                       flags, counters);
+    if (lay == LMIX)
+      hipLaunchKernelGGL((k_limit<EQ, K, LMIX>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M,
+                         u, flags, counters);
+    else
+      hipLaunchKernelGGL((k_limit<EQ, K, L64>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M,
+                         u, flags, counters);
     return hipGetLastError();
   }
 };
 
-hipError_t launch_inner(int eq, int k, const PhysDev& ph, const Geo& g, const InnerArgs& a,
-                        hipStream_t s) {
-  return dispatch<RunInner>(eq, k, ph, g, a, s);
+hipError_t launch_inner(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+                        const InnerArgs& a, hipStream_t s) {
+  return mixed ? dispatch_mixed<RunInner>(eq, k, ph, g, a, s) : dispatch<RunInner>(eq, k, ph, g, a, s);
 }
-hipError_t launch_final(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
-                        const FinalArgs& a, hipStream_t s) {
-  return dispatch<RunFinal>(eq, k, ph, g, bc, a, s);
+hipError_t launch_final(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, const FinalArgs& a, hipStream_t s) {
+  return mixed ? dispatch_mixed<RunFinal>(eq, k, ph, g, bc, a, s)
+               : dispatch<RunFinal>(eq, k, ph, g, bc, a, s);
 }
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s) {
@@ -1132,29 +1345,29 @@ hipError_t launch_combine(long long n, double* out, const double* base, int nx,
   hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, s, n, a);
   return hipGetLastError();
 }
-hipError_t launch_wavespeed(int eq, int k, const PhysDev& ph, const Geo& g, const double* u,
-                            double* partial, int nb, double cfl, double* smax, double* dt,
-                            hipStream_t s) {
-  return dispatch<RunWave>(eq, k, ph, g, u, partial, nb, cfl, smax, dt, s);
+hipError_t launch_wavespeed(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
+                            const void* u, double* partial, int nb, double cfl, double* smax,
+                            double* dt, hipStream_t s) {
+  return dispatch<RunWave>(eq, k, ph, g, u, lay, partial, nb, cfl, smax, dt, s);
 }
-hipError_t launch_error(int eq, int k, const PhysDev& ph, const Geo& g, const double* u, int ic,
-                        const double* params, const double* aux, double t, int comp,
+hipError_t launch_error(int eq, int k, int lay, const PhysDev& ph, const Geo& g, const void* u,
+                        int ic, const double* params, const double* aux, double t, int comp,
                         double* partial, int nb, double* out3, hipStream_t s) {
-  return dispatch<RunError>(eq, k, ph, g, u, ic, params, aux, t, comp, partial, nb, out3, s);
+  return dispatch<RunError>(eq, k, ph, g, u, lay, ic, params, aux, t, comp, partial, nb, out3, s);
 }
-hipError_t launch_total(int eq, int k, const Geo& g, const double* u, int comp, double* partial,
-                        int nb, double* out, hipStream_t s) {
-  return dispatch<RunTotal>(eq, k, g, u, comp, partial, nb, out, s);
+hipError_t launch_total(int eq, int k, int lay, const Geo& g, const void* u, int comp,
+                        double* partial, int nb, double* out, hipStream_t s) {
+  return dispatch<RunTotal>(eq, k, g, u, lay, comp, partial, nb, out, s);
 }
-hipError_t launch_project(int eq, int k, const PhysDev& ph, const Geo& g, int ic,
-                          const double* params, const double* aux, double t, double* u,
+hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& g, int ic,
+                          const double* params, const double* aux, double t, void* u,
                           hipStream_t s) {
-  return dispatch<RunProject>(eq, k, ph, g, ic, params, aux, t, u, s);
+  return dispatch<RunProject>(eq, k, ph, g, ic, params, aux, t, u, lay, s);
 }
-hipError_t launch_limit(int eq, int k, const PhysDev& ph, const Geo& g, const BCDev& bc,
-                        double M, double* u, uint8_t* flags, unsigned long long* counters,
-                        hipStream_t s) {
-  return dispatch<RunLimit>(eq, k, ph, g, bc, M, u, flags, counters, s);
+hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, double M, void* u, uint8_t* flags,
+                        unsigned long long* counters, hipStream_t s) {
+  return dispatch<RunLimit>(eq, k, ph, g, bc, M, u, lay, flags, counters, s);
 }
 
 }  // namespace crk

@@ -19,6 +19,14 @@
 
 namespace crk {
 
+// keep the scheduler from interleaving independent quadrature lines: the
+// work is one line of points at a time, which bounds the live registers
+#ifndef CRK_NO_SCHED_FENCE
+#define CRK_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define CRK_FENCE()
+#endif
+
 // ---------------------------------------------------------------------------
 // Gauss--Legendre rules on [-1, 1] (closed forms for n <= 5, tabulated for n = 6)
 // ---------------------------------------------------------------------------
@@ -112,6 +120,7 @@ constexpr double sgn_pow(int m) { return (m % 2) ? -1.0 : 1.0; }  // (-1)^m
 // ---------------------------------------------------------------------------
 template <class R>
 struct Euler2 {
+  using Real = R;
   static constexpr int NC = 4, DIM = 2;
   static constexpr bool EULER = true;
   R gm1, gam;
@@ -159,6 +168,7 @@ struct Euler2 {
 
 template <class R, int DIM_>
 struct Adv {
+  using Real = R;
   static constexpr int NC = 1, DIM = DIM_;
   static constexpr bool EULER = false;
   R ax, ay;
@@ -286,6 +296,7 @@ __device__ __forceinline__ void volume_acc(const EQ& eq,
             acc[c][m + Q * n] = v;
           }
         }
+      CRK_FENCE();
     }
   }
 }
@@ -455,11 +466,13 @@ __device__ __forceinline__ void loc_acc(const EQ& eq, const R (&U)[EQ::NC][Sizes
     trace_flux<0, EQ, NP, R>(eq, t0, F0);
     trace_flux<0, EQ, NP, R>(eq, t1, F1);
     lift_x<EQ, K, R>(F0, F1, hx, acc);
+    CRK_FENCE();
     trace_y<+1, EQ, K, R>(U, t0);
     trace_y<-1, EQ, K, R>(U, t1);
     trace_flux<1, EQ, NP, R>(eq, t0, F0);
     trace_flux<1, EQ, NP, R>(eq, t1, F1);
     lift_y<EQ, K, R>(F0, F1, hy, acc);
+    CRK_FENCE();
   } else {
     const R hx = scale * inv_dx;
     volume_acc<EQ, K, R>(eq, U, -hx, R(0), acc);

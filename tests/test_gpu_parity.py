@@ -266,3 +266,72 @@ def test_limiter(K, k):
     assert rel_err(got[:, :, agree], lim_o[:, :, agree]) < 1e-13
     assert np.array_equal(got[:, 0], u[:, 0])  # means untouched
     assert abs(n_gpu - n_o) <= (~safe).sum()
+
+
+# --- FP32-bulk form (FP64 cell averages, FP32 higher modes and arithmetic) ----
+
+def mixed_solver(K, cfg, k, stages, bc_state=None):
+    x0, x1, y0, y1 = cfg["box"]
+    bc = tuple(BC[b] for b in cfg["bc"])
+    lm = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=bc,
+                     bc_state=bc_state, equation=K.EQ_EULER, precision=K.FP32_MIXED)
+    om = O.Mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=bc, bc_state=bc_state,
+                equation=O.EQ_EULER, flux=O.FLUX_LLF)
+    return K.Solver(lm, k, K.FLUX_LLF, stages), om
+
+
+def l2_rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+@pytest.mark.parametrize("k,tab,stages", [(2, "eq3", 3), (3, "rk4", 4), (1, "eq2", 2)])
+def test_mixed_density_wave_run(K, k, tab, stages):
+    """density-wave workload (Section 4.1.2 example), 48 x 40 cells, 60 steps:
+    the FP32-bulk form stays within 1e-5 relative L2 of the FP64 oracle, its
+    cell averages stay FP64 and the sums are conserved to FP64 round-off"""
+    cfg = dict(W.config("c3"), nx=48, ny=40)
+    s, om = mixed_solver(K, cfg, k, stages)
+    P = cfg["ic_params"]
+    s.crkdg_project(K.IC_EULER_WAVE, P)
+    u = O.project(om, k, O.IC_EULER_WAVE, P)
+    got0 = s.crkdg_get_state()
+    assert rel_err(got0[:, 0], u[:, 0]) < 1e-14          # FP64 averages
+    assert rel_err(got0, u) < 1e-7                       # FP32 higher modes
+    m0 = [s.crkdg_total(c) for c in range(4)]
+    dt = cfg["cfl"] / O.max_wavespeed(om, k, u)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU[tab])
+    for n in range(60):
+        s.crkdg_step(dt)
+        u = O.step_crkdg(om, k, (A, b, c), n * dt, dt, u)
+    got = s.crkdg_get_state()
+    assert l2_rel(got, u) < 1e-5, l2_rel(got, u)
+    for cc in range(4):
+        assert abs(s.crkdg_total(cc) - m0[cc]) < 1e-13 * max(1.0, abs(m0[cc]))
+
+
+def test_mixed_shock_step_and_limiter(K):
+    cfg = W.config("c5", scale=32)  # 128 x 32
+    params, xi = W.shock_problem(2000, cfg["nx"], cfg["ny"])
+    ghost = W.post_shock_conserved(params[0])
+    import torch
+    s, om = mixed_solver(K, cfg, 2, 3, bc_state=[ghost] * 4)
+    s.crkdg_project(K.IC_SHOCK, params, aux=torch.from_numpy(xi).cuda())
+    s.crkdg_limit(50.0)
+    u = s.crkdg_get_state()        # the FP32-bulk state, as FP64
+    dt = cfg["cfl"] / O.max_wavespeed(om, 2, u)
+    s.crkdg_step(dt)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    ref = O.step_crkdg(om, 2, (A, b, c), 0.0, dt, u)
+    got = s.crkdg_get_state()
+    assert l2_rel(got, ref) < 1e-6
+    # limiter: FP64 test on the FP32-bulk state; compare where decisions are safe
+    flags = torch.zeros(om.ncells, dtype=torch.uint8, device="cuda")
+    s.crkdg_limit(50.0, flags)
+    lim_o, fl_o, _ = O.limit_tvb(om, 2, 50.0, got)
+    _, margin, _ = O.tvb_flags(om, 2, 50.0, got)
+    fg = flags.cpu().numpy()
+    safe = margin > 1e-7
+    assert np.array_equal(fg[safe] != 0, fl_o[safe] != 0)
+    after = s.crkdg_get_state()
+    agree = fg == fl_o
+    assert l2_rel(after[:, :, agree], lim_o[:, :, agree]) < 1e-6
