@@ -141,12 +141,44 @@ int crkdg_max_wavespeed(crkdg_state* st, double* s_max_host);
  * with constant M (threshold M h^2), limited P1 reconstruction of troubled
  * cells with every other non-mean mode zeroed, cell averages unchanged, then
  * an FP64 positivity check of rho and p at the operator's quadrature points
- * (demotion to P1, then P0).  flags_dev (uint8 per cell, may be NULL):
- * 0 untouched, 1 troubled, 2 demoted to P1, 3 demoted to P0.  If
+ * (demotion to P1, then P0).  flags_dev (uint8 per cell, may be NULL) is a
+ * bit mask: 1 troubled, 2 positivity failure (limited P1), 4 demoted to P0,
+ * 8 decided by the TVB fallback (learned-indicator mode).  If
  * n_flagged_host is not NULL the call syncs and returns the count there.
  * Returns CRKDG_ENONPHYSICAL (after syncing) only when n_flagged_host is
  * given and a cell average is non-physical. */
 int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagged_host);
+
+/* Learned troubled-cell indicator (not part of the paper's method): the
+ * same final-stage limiter, with the TVB troubled-cell test replaced by a
+ * 12 -> 32 -> 32 -> 1 perceptron (tanh, tanh, logistic output; parameters
+ * packed W1[32][12], b1[32], W2[32][32], b2[32], w3[32], b3 as 1505 device
+ * floats) on 12 stencil features.  p = sigmoid(logit): p >= tau_hi troubled,
+ * p <= tau_lo smooth, otherwise the FP64 TVB test decides (flag bit 8).
+ * Reconstruction and positivity check as in crkdg_limit.  counts_host
+ * (nullable, syncs): [0] flagged cells, [1] cells decided by the fallback.
+ * 2D Euler only (CRKDG_EUNSUPPORTED otherwise). */
+int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float tau_lo,
+                    float tau_hi, uint8_t* flags_dev, int64_t* counts_host);
+/* The 12 features of every cell of the current state, X[cell][12] FP32
+ * (computed in FP64): for q in {rho, E} and d in {x, y}, with a / at the
+ * forward / backward face-average jumps of q, dp / dm the neighbouring
+ * cell-average differences and s = |dp| + |dm| + M h_d^2 + 1e-300:
+ * a/s, at/s, (dp - dm)/s.  2D Euler only. */
+int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev);
+/* MLP kernels on device arrays (stream = hipStream_t or NULL):
+ * forward logits of B samples X[B][12]; the batch-mean weighted BCE loss
+ * pos_weight*y*softplus(-z) + (1-y)*softplus(z) and its gradient (1505
+ * floats; loss: 1 device float or NULL) with a deterministic two-level
+ * reduction in caller-owned work memory of crkdg_mlp_work_bytes(B); one
+ * Adam update with bias correction (step >= 1). */
+size_t crkdg_mlp_work_bytes(int B);
+int crkdg_mlp_forward(const float* params, const float* X, int B, float* logits, void* stream);
+int crkdg_mlp_grad(const float* params, const float* X, const uint8_t* y, int B,
+                   float pos_weight, float* grad, float* loss, void* work, size_t work_bytes,
+                   void* stream);
+int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int step, float lr,
+                   float beta1, float beta2, float eps, void* stream);
 
 /* L1, L2 (unnormalised integrals over the domain) and Linf errors of
  * component comp against exact solution ic at time t, (k+3)^dim Gauss points

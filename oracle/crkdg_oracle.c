@@ -880,22 +880,24 @@ int64_t or_limit_tvb(const or_mesh* m, int k, double M, double* u, uint8_t* flag
   int bad = 0;
   for (int cell = 0; cell < N; ++cell) {
     uint8_t fl = 0;
-    if (k >= 1 && tvb_test(m, k, M, u0, cell, NULL)) {
-      tvb_reconstruct(m, k, M, u0, u, cell);
-      fl = 1;
-    }
+    int cbad = 0;
     if (m->equation == OR_EQ_EULER) {
       double qb[OR_MAXC];
       for (int c = 0; c < nc; ++c) qb[c] = u0[(c * nb) * N + cell];
-      if (!(qb[0] > 0.0) || !(pressure(m, qb) > 0.0)) bad = 1;
-      if (!bad && k >= 1 && !physical_at_points(m, k, u, cell)) {
-        if (fl == 0) tvb_reconstruct(m, k, M, u0, u, cell);
-        fl = 2;
-        if (!physical_at_points(m, k, u, cell)) {
-          for (int c = 0; c < nc; ++c)
-            for (int b = 1; b < nb; ++b) u[(c * nb + b) * N + cell] = 0.0;
-          fl = 3;
-        }
+      cbad = !(qb[0] > 0.0) || !(pressure(m, qb) > 0.0);
+      bad |= cbad;
+    }
+    if (k >= 1 && !cbad && tvb_test(m, k, M, u0, cell, NULL)) {
+      tvb_reconstruct(m, k, M, u0, u, cell);
+      fl |= 1;
+    }
+    if (m->equation == OR_EQ_EULER && !cbad && k >= 1 && !physical_at_points(m, k, u, cell)) {
+      if (!(fl & 1)) tvb_reconstruct(m, k, M, u0, u, cell);
+      fl |= 2;
+      if (!physical_at_points(m, k, u, cell)) {
+        for (int c = 0; c < nc; ++c)
+          for (int b = 1; b < nb; ++b) u[(c * nb + b) * N + cell] = 0.0;
+        fl |= 4;
       }
     }
     if (flags) flags[cell] = fl;

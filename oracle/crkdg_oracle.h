@@ -104,10 +104,10 @@ int    or_step_wrong_ssp(const or_mesh* m, int k, int order, double t, double dt
 int    or_crkdg_stages(const or_mesh* m, int k, int s, const double* A, const double* b,
                        const double* c, double t, double dt, const double* u, double* stages);
 
-/* TVB minmod limiter applied once (after the final stage).  flags[cell]:
- * 0 untouched, 1 troubled (TVB), 2 demoted to P1 by the positivity check,
- * 3 demoted to P0.  Returns number of flagged cells, or -1 if a cell average
- * is non-physical. */
+/* TVB minmod limiter applied once (after the final stage).  flags[cell] is a
+ * bit mask: 1 troubled (TVB test), 2 positivity check failed (limited P1),
+ * 4 still non-physical (P0).  Returns the number of flagged cells, or -1 if
+ * a cell average is non-physical. */
 int64_t or_limit_tvb(const or_mesh* m, int k, double M, double* u, uint8_t* flags);
 /* troubled-cell indicator only, with decision margins (see or_limit_tvb) */
 int64_t or_tvb_flags(const or_mesh* m, int k, double M, const double* u, uint8_t* flags,

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libcrkdg.so")
-SOURCES = ["crkdg_kernels.hip", "crkdg_api.hip"]
+SOURCES = ["crkdg_kernels.hip", "crkdg_mlp.hip", "crkdg_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -70,6 +70,14 @@ def _sig():
         "crkdg_apply_op": (C.c_int, [vp, C.c_int, vp, vp, C.c_double]),
         "crkdg_combine": (C.c_int, [vp, vp, vp, C.c_int, dp, C.POINTER(vp)]),
         "crkdg_gauss_rule": (C.c_int, [C.c_int, dp, dp]),
+        "crkdg_limit_mlp": (C.c_int, [vp, C.c_double, vp, C.c_float, C.c_float, vp,
+                                      C.POINTER(C.c_int64)]),
+        "crkdg_mlp_features": (C.c_int, [vp, C.c_double, vp]),
+        "crkdg_mlp_work_bytes": (sz, [C.c_int]),
+        "crkdg_mlp_forward": (C.c_int, [vp, vp, C.c_int, vp, vp]),
+        "crkdg_mlp_grad": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, vp, vp, vp, sz, vp]),
+        "crkdg_mlp_adam": (C.c_int, [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float,
+                                     C.c_float, vp]),
         "crkdg_profile_begin": (C.c_int, [vp, C.c_int]),
         "crkdg_profile_end": (C.c_int, [vp, dp, C.POINTER(C.c_int64)]),
         "crkdg_destroy": (None, [vp]),
@@ -233,6 +241,21 @@ class Solver:
         _check(rc, "crkdg_limit")
         return n.value if count else None
 
+    def crkdg_limit_mlp(self, M, params, tau_lo, tau_hi, flags=None, count=True):
+        cnt = (C.c_int64 * 2)(-1, -1)
+        f = None if flags is None else C.c_void_p(flags.data_ptr())
+        _check(lib().crkdg_limit_mlp(self.h, float(M), C.c_void_p(params.data_ptr()),
+                                     float(tau_lo), float(tau_hi), f, cnt if count else None),
+               "crkdg_limit_mlp")
+        return (cnt[0], cnt[1]) if count else None
+
+    def crkdg_mlp_features(self, M, X=None):
+        if X is None:
+            X = self.torch.empty((self.ncells, 12), dtype=self.torch.float32, device="cuda")
+        _check(lib().crkdg_mlp_features(self.h, float(M), C.c_void_p(X.data_ptr())),
+               "crkdg_mlp_features")
+        return X
+
     def crkdg_error(self, ic, params=(), t=0.0, comp=0):
         P = np.ascontiguousarray(params, dtype=np.float64) if len(params) else None
         out = np.zeros(3)
@@ -287,3 +310,46 @@ class Solver:
                 n = self.ncomp * self.nmodes * self.ncells
                 return buf[off:off + 8 * n].view(self.torch.float64).view(self.shape)
         raise RuntimeError("current state pointer outside the bound buffers")
+
+
+# --- MLP kernels (no mesh) -------------------------------------------------
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def crkdg_mlp_forward(params, X, stream=None):
+    import torch
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().crkdg_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(out), _stream(stream)),
+           "crkdg_mlp_forward")
+    return out
+
+
+def crkdg_mlp_grad(params, X, y, pos_weight, grad=None, loss=None, work=None, stream=None):
+    import torch
+    B = X.shape[0]
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    nb = lib().crkdg_mlp_work_bytes(B)
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    _check(lib().crkdg_mlp_grad(_ptr(params), _ptr(X), _ptr(y), B, float(pos_weight), _ptr(grad),
+                                _ptr(loss), _ptr(work), nb, _stream(stream)), "crkdg_mlp_grad")
+    return grad, loss
+
+
+def crkdg_mlp_adam(params, m1, m2, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   stream=None):
+    _check(lib().crkdg_mlp_adam(_ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(step),
+                                float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+           "crkdg_mlp_adam")

@@ -476,27 +476,74 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
   return hip_rc(e);
 }
 
-int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagged) {
-  if (!st || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
-  if (!st->bound) return CRKDG_EUNBOUND;
+static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
+                      uint8_t* flags_dev, int64_t* counts, int ncounts) {
   unsigned long long* counters =
-      n_flagged ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
+      counts ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
   hipError_t e;
   {
     ProfScope ps(st, KC_LIMIT);
-    e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, cur_ptr(st), flags_dev,
-                     counters, st->stream);
+    e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, params, tau_lo, tau_hi,
+                     cur_ptr(st), flags_dev, counters, st->stream);
   }
   if (e != hipSuccess) return CRKDG_EHIP;
-  if (n_flagged) {
-    unsigned long long h[2] = {0, 0};
+  if (counts) {
+    unsigned long long h[3] = {0, 0, 0};
     e = hipMemcpyAsync(h, counters, sizeof h, hipMemcpyDeviceToHost, st->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
     if (e != hipSuccess) return CRKDG_EHIP;
-    *n_flagged = (int64_t)h[0];
+    counts[0] = (int64_t)h[0];
+    if (ncounts > 1) counts[1] = (int64_t)h[2];
     if (h[1]) return CRKDG_ENONPHYSICAL;
   }
   return CRKDG_OK;
+}
+
+int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagged) {
+  if (!st || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  return limit_impl(st, M, nullptr, 0.f, 0.f, flags_dev, n_flagged, 1);
+}
+
+int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float tau_lo,
+                    float tau_hi, uint8_t* flags_dev, int64_t* counts_host) {
+  if (!st || !params_dev || !isfinite(M) || M < 0.0 || !(tau_lo <= tau_hi)) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
+  return limit_impl(st, M, params_dev, tau_lo, tau_hi, flags_dev, counts_host, 2);
+}
+
+int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev) {
+  if (!st || !X_dev || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
+  return hip_rc(launch_mlp_features(st->k, st->lay, st->geo, st->bc, M, cur_ptr(st), X_dev,
+                                    st->stream));
+}
+
+size_t crkdg_mlp_work_bytes(int B) { return B > 0 ? mlp_work_floats(B) * sizeof(float) : 0; }
+
+int crkdg_mlp_forward(const float* params, const float* X, int B, float* logits, void* stream) {
+  if (!params || !X || !logits || B < 1) return CRKDG_EINVAL;
+  return hip_rc(launch_mlp_forward(params, X, B, logits, (hipStream_t)stream));
+}
+
+int crkdg_mlp_grad(const float* params, const float* X, const uint8_t* y, int B, float pos_weight,
+                   float* grad, float* loss, void* work, size_t work_bytes, void* stream) {
+  if (!params || !X || !y || !grad || !work || B < 1 || !isfinite(pos_weight) || pos_weight <= 0)
+    return CRKDG_EINVAL;
+  if (work_bytes < crkdg_mlp_work_bytes(B)) return CRKDG_EINVAL;
+  return hip_rc(launch_mlp_grad(params, X, y, B, pos_weight, grad, loss, (float*)work,
+                                (hipStream_t)stream));
+}
+
+int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int step, float lr,
+                   float beta1, float beta2, float eps, void* stream) {
+  if (!params || !m1 || !m2 || !grad || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return CRKDG_EINVAL;
+  return hip_rc(launch_mlp_adam(params, m1, m2, grad, step, lr, beta1, beta2, eps,
+                                (hipStream_t)stream));
 }
 
 int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, double t, int comp,

@@ -85,9 +85,20 @@ hipError_t launch_total(int eq, int k, int lay, const Geo& g, const void* u, int
 hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& g, int ic,
                           const double* params, const double* aux, double t, void* u,
                           hipStream_t s);
+// mlp_params == NULL: TVB test; else learned indicator with the TVB fallback band
 hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
-                        const BCDev& bc, double M, void* u, uint8_t* flags,
-                        unsigned long long* counters, hipStream_t s);
+                        const BCDev& bc, double M, const float* mlp_params, float tau_lo,
+                        float tau_hi, void* u, uint8_t* flags, unsigned long long* counters,
+                        hipStream_t s);
+hipError_t launch_mlp_features(int k, int lay, const Geo& g, const BCDev& bc, double M,
+                               const void* u, float* X, hipStream_t s);
+// MLP training kernels (crkdg_mlp.hip)
+hipError_t launch_mlp_forward(const float* P, const float* X, int B, float* logits, hipStream_t s);
+hipError_t launch_mlp_grad(const float* P, const float* X, const uint8_t* y, int B,
+                           float pos_weight, float* grad, float* loss, float* work, hipStream_t s);
+hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, int step, float lr,
+                           float b1, float b2, float eps, hipStream_t s);
+size_t mlp_work_floats(int B);
 
 constexpr int RED_BLOCKS = 1024;  // blocks of the first reduction pass
 

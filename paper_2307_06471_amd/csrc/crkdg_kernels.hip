@@ -27,6 +27,7 @@
 
 #include "crkdg_internal.hpp"
 #include "dg_core.hpp"
+#include "mlp_core.hpp"
 
 #ifndef INNER_OCC_F32
 #define INNER_OCC_F32 2
@@ -1020,16 +1021,24 @@ __device__ bool physical_points(double gamma, const double (&U)[4][(K + 1) * (K 
   return face_ok();
 }
 
+struct LimitArgs {
+  double M;
+  int mlp;              // 0: TVB test decides; 1: learned indicator with TVB fallback band
+  const float* P;       // MLP parameters (device)
+  float tau_lo, tau_hi; // p <= tau_lo: smooth, p >= tau_hi: troubled, else TVB decides
+};
+
 template <class EQ, int K, int LAY>
-__global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, double M,
+__global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
                                                void* __restrict__ u,
                                                uint8_t* __restrict__ flags,
                                                unsigned long long* __restrict__ counters) {
   constexpr int NC = EQ::NC, DIM = EQ::DIM, Q = K + 1, NB = Sizes<K, DIM>::NB;
-  __shared__ unsigned int cnt[2];
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __shared__ unsigned int cnt[3];
+  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
   __syncthreads();
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  const double M = la.M;
   uint8_t flag = 0;
   bool bad = false;
   if (cell < g.N) {
@@ -1037,8 +1046,7 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
     double U[NC][NB];
     load_state<double, NC, NB, LAY>(u, g.N, cell, U);
     double avg[NC];
-    for (int c = 0; c < NC; ++c) avg[c] = load_avg<NC, NB, LAY>(u, g.N, c, cell);
-    for (int c = 0; c < NC; ++c) U[c][0] = avg[c];
+    for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
     if constexpr (EQ::EULER) {
       const double p = (ph.gamma - 1.0) * (avg[3] - 0.5 * (avg[1] * avg[1] + avg[2] * avg[2]) / avg[0]);
       bad = !(avg[0] > 0.0) || !(p > 0.0);
@@ -1063,16 +1071,21 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
       for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
     };
     auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
-    bool troubled = false;
-    if (K >= 1 && !bad) {
+    double dp[2][NC], dm[2][NC];
+    for (int d = 0; d < DIM; ++d) {
+      double qn[NC];
+      nbr_avg(d, +1, qn);
+      for (int c = 0; c < NC; ++c) dp[d][c] = qn[c] - avg[c];
+      nbr_avg(d, -1, qn);
+      for (int c = 0; c < NC; ++c) dm[d][c] = avg[c] - qn[c];
+    }
+    // the TVB minmod troubled-cell test (characteristic variables for Euler)
+    auto tvb_test = [&]() {
+      bool tr = false;
       for (int d = 0; d < DIM; ++d) {
         const double h = d == 0 ? g.dx : g.dy;
         const double Mh2 = M * h * h;
-        double qn[NC], a[NC], at[NC], dp[NC], dm[NC];
-        nbr_avg(d, +1, qn);
-        for (int c = 0; c < NC; ++c) dp[c] = qn[c] - avg[c];
-        nbr_avg(d, -1, qn);
-        for (int c = 0; c < NC; ++c) dm[c] = avg[c] - qn[c];
+        double a[NC], at[NC];
         for (int c = 0; c < NC; ++c) {
           a[c] = 0.0;
           at[c] = 0.0;
@@ -1091,18 +1104,47 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
             for (int c = 0; c < NC; ++c) {
               ca[r] += L[r * 4 + c] * a[c];
               cat[r] += L[r * 4 + c] * at[c];
-              cp[r] += L[r * 4 + c] * dp[c];
-              cm[r] += L[r * 4 + c] * dm[c];
+              cp[r] += L[r * 4 + c] * dp[d][c];
+              cm[r] += L[r * 4 + c] * dm[d][c];
             }
           }
         } else {
           for (int c = 0; c < NC; ++c) {
-            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[c]; cm[c] = dm[c];
+            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
           }
         }
         for (int r = 0; r < NC; ++r)
           if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r])
+            tr = true;
+      }
+      return tr;
+    };
+    bool troubled = false;
+    bool fallback = false;
+    if (K >= 1 && !bad) {
+      if constexpr (EQ::EULER && DIM == 2) {
+        if (la.mlp) {
+          float x[MLP_IN];
+          double dpa[2][4], dma[2][4];
+          for (int d = 0; d < 2; ++d)
+            for (int c = 0; c < 4; ++c) {
+              dpa[d][c] = dp[d][c];
+              dma[d][c] = dm[d][c];
+            }
+          cell_features<NB, Q>(U, dpa, dma, M * g.dx * g.dx, M * g.dy * g.dy, x);
+          const float z = mlp_forward1<false>(la.P, x);
+          const float pr = 1.0f / (1.0f + __expf(-z));
+          if (pr >= la.tau_hi) {
             troubled = true;
+          } else if (pr > la.tau_lo) {
+            fallback = true;
+            troubled = tvb_test();
+          }
+        } else {
+          troubled = tvb_test();
+        }
+      } else {
+        troubled = tvb_test();
       }
     }
     auto reconstruct = [&](double (&V)[NC][NB]) {
@@ -1111,11 +1153,7 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
         const double h = d == 0 ? g.dx : g.dy;
         const double Mh2 = M * h * h;
         const int sm = mode_of(d, 1);
-        double sl[NC], pp[NC], mm[NC], qn[NC];
-        nbr_avg(d, +1, qn);
-        for (int c = 0; c < NC; ++c) pp[c] = qn[c] - avg[c];
-        nbr_avg(d, -1, qn);
-        for (int c = 0; c < NC; ++c) mm[c] = avg[c] - qn[c];
+        double sl[NC];
         for (int c = 0; c < NC; ++c) sl[c] = V[c][sm];
         if constexpr (EQ::EULER) {
           double L[16], Rm[16], lim[NC];
@@ -1124,8 +1162,8 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
             double s1 = 0.0, s2 = 0.0, s3 = 0.0;
             for (int c = 0; c < NC; ++c) {
               s1 += L[r * 4 + c] * sl[c];
-              s2 += L[r * 4 + c] * pp[c];
-              s3 += L[r * 4 + c] * mm[c];
+              s2 += L[r * 4 + c] * dp[d][c];
+              s3 += L[r * 4 + c] * dm[d][c];
             }
             lim[r] = tvb(s1, s2, s3, Mh2);
           }
@@ -1135,7 +1173,7 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
             ns[d][c] = s;
           }
         } else {
-          for (int c = 0; c < NC; ++c) ns[d][c] = tvb(sl[c], pp[c], mm[c], Mh2);
+          for (int c = 0; c < NC; ++c) ns[d][c] = tvb(sl[c], dp[d][c], dm[d][c], Mh2);
         }
       }
       for (int c = 0; c < NC; ++c) {
@@ -1144,20 +1182,21 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
       }
     };
     bool changed = false;
+    if (fallback) flag |= 8;
     if (troubled) {
       reconstruct(U);
-      flag = 1;
+      flag |= 1;
       changed = true;
     }
     if constexpr (EQ::EULER) {
       if (!bad && K >= 1 && !physical_points<K>(ph.gamma, U)) {
         if (!troubled) reconstruct(U);
-        flag = 2;
+        flag |= 2;
         changed = true;
         if (!physical_points<K>(ph.gamma, U)) {
           for (int c = 0; c < NC; ++c)
             for (int b = 1; b < NB; ++b) U[c][b] = 0.0;
-          flag = 3;
+          flag |= 4;
         }
       }
     }
@@ -1165,14 +1204,58 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, doub
     if (flags) flags[cell] = flag;
   }
   if (counters) {
-    if (flag) atomicAdd(&cnt[0], 1u);
+    if (flag & 7) atomicAdd(&cnt[0], 1u);
     if (bad) atomicAdd(&cnt[1], 1u);
+    if (flag & 8) atomicAdd(&cnt[2], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
       if (cnt[0]) atomicAdd(&counters[0], (unsigned long long)cnt[0]);
       if (cnt[1]) atomicAdd(&counters[1], (unsigned long long)cnt[1]);
+      if (cnt[2]) atomicAdd(&counters[2], (unsigned long long)cnt[2]);
     }
   }
+}
+
+// 12 stencil features per cell for the learned indicator (training data)
+template <int K, int LAY>
+__global__ __launch_bounds__(256) void k_mlp_features(Geo g, BCDev bc, double M,
+                                                      const void* __restrict__ u,
+                                                      float* __restrict__ X) {
+  constexpr int NC = 4, Q = K + 1, NB = Q * Q;
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= g.N) return;
+  const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
+  double U[NC][NB];
+  load_state<double, NC, NB, LAY>(u, g.N, cell, U);
+  double dp[2][4], dm[2][4];
+  for (int d = 0; d < 2; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
+      const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
+      double qa[NC];
+      if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
+        const int type = bc.type[side];
+        if (type == CRKDG_BC_TRANSMISSIVE) {
+          for (int c = 0; c < NC; ++c) qa[c] = U[c][0];
+        } else if (type == CRKDG_BC_DIRICHLET) {
+          for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
+        } else {
+          ni = (ni + g.nx) % g.nx;
+          nj = (nj + g.ny) % g.ny;
+          for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
+        }
+      } else {
+        for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
+      }
+      for (int c = 0; c < NC; ++c) {
+        if (s > 0) dp[d][c] = qa[c] - U[c][0];
+        else dm[d][c] = U[c][0] - qa[c];
+      }
+    }
+  float x[MLP_IN];
+  cell_features<NB, Q>(U, dp, dm, M * g.dx * g.dx, M * g.dy * g.dy, x);
+#pragma unroll
+  for (int f = 0; f < MLP_IN; ++f) X[cell * MLP_IN + f] = x[f];
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -1301,14 +1384,15 @@ struct RunProject {
 };
 template <class EQ, int K>
 struct RunLimit {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, double M, void* u,
-                        int lay, uint8_t* flags, unsigned long long* counters, hipStream_t s) {
-    if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 2);
+  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const LimitArgs& la,
+                        void* u, int lay, uint8_t* flags, unsigned long long* counters,
+                        hipStream_t s) {
+    if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 3);
     if (lay == LMIX)
-      hipLaunchKernelGGL((k_limit<EQ, K, LMIX>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M,
+      hipLaunchKernelGGL((k_limit<EQ, K, LMIX>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, la,
                          u, flags, counters);
     else
-      hipLaunchKernelGGL((k_limit<EQ, K, L64>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, M,
+      hipLaunchKernelGGL((k_limit<EQ, K, L64>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, la,
                          u, flags, counters);
     return hipGetLastError();
   }
@@ -1365,9 +1449,25 @@ hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& 
   return dispatch<RunProject>(eq, k, ph, g, ic, params, aux, t, u, lay, s);
 }
 hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
-                        const BCDev& bc, double M, void* u, uint8_t* flags,
-                        unsigned long long* counters, hipStream_t s) {
-  return dispatch<RunLimit>(eq, k, ph, g, bc, M, u, lay, flags, counters, s);
+                        const BCDev& bc, double M, const float* mlp_params, float tau_lo,
+                        float tau_hi, void* u, uint8_t* flags, unsigned long long* counters,
+                        hipStream_t s) {
+  LimitArgs la{M, mlp_params != nullptr, mlp_params, tau_lo, tau_hi};
+  return dispatch<RunLimit>(eq, k, ph, g, bc, la, u, lay, flags, counters, s);
+}
+hipError_t launch_mlp_features(int k, int lay, const Geo& g, const BCDev& bc, double M,
+                               const void* u, float* X, hipStream_t s) {
+  const dim3 grid(nblk(g.N, 256));
+  switch (k * 4 + lay) {
+    case 1 * 4 + L64: hipLaunchKernelGGL((k_mlp_features<1, L64>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    case 2 * 4 + L64: hipLaunchKernelGGL((k_mlp_features<2, L64>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    case 3 * 4 + L64: hipLaunchKernelGGL((k_mlp_features<3, L64>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    case 1 * 4 + LMIX: hipLaunchKernelGGL((k_mlp_features<1, LMIX>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    case 2 * 4 + LMIX: hipLaunchKernelGGL((k_mlp_features<2, LMIX>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    case 3 * 4 + LMIX: hipLaunchKernelGGL((k_mlp_features<3, LMIX>), grid, dim3(256), 0, s, g, bc, M, u, X); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace crk

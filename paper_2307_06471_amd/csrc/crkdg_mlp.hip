@@ -1,0 +1,170 @@
+// crkdg_mlp.hip -- training kernels of the learned troubled-cell indicator
+// (not part of the paper's method; FP32).
+//
+//   k_mlp_forward       logits of a batch of feature vectors
+//   k_mlp_grad_partial  forward + backward of 64 samples per workgroup: each
+//                       lane runs one sample, the activations go to LDS, then
+//                       each lane sums a fixed subset of the 1505 parameter
+//                       gradients over the 64 samples in a fixed order
+//   k_mlp_grad_final    sums the workgroup partials in a fixed order, so the
+//                       gradient is bitwise reproducible
+//   k_mlp_adam          Adam with bias correction
+//
+// Loss: the mean over the batch of the weighted binary cross-entropy with
+// logits, pw * y * softplus(-z) + (1 - y) * softplus(z).
+#include <math.h>
+
+#include "crkdg_internal.hpp"
+#include "mlp_core.hpp"
+
+namespace crk {
+
+constexpr int MB = 64;  // samples per workgroup of the gradient kernel
+constexpr int NPART = MLP_NPAR + 1;  // partial gradients + partial loss
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P,
+                                                     const float* __restrict__ X, int B,
+                                                     float* __restrict__ out) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= B) return;
+  float x[MLP_IN];
+#pragma unroll
+  for (int i = 0; i < MLP_IN; ++i) x[i] = X[(long long)n * MLP_IN + i];
+  out[n] = mlp_forward1<false>(P, x);
+}
+
+__device__ __forceinline__ float softplus_f(float x) {
+  return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+}
+
+__global__ __launch_bounds__(MB) void k_mlp_grad_partial(const float* __restrict__ P,
+                                                         const float* __restrict__ X,
+                                                         const uint8_t* __restrict__ y, int B,
+                                                         float pw, float* __restrict__ partial) {
+  __shared__ float sx[MB][MLP_IN];
+  __shared__ float sh1[MB][MLP_H1];
+  __shared__ float sh2[MB][MLP_H2];
+  __shared__ float sd1[MB][MLP_H1];
+  __shared__ float sd2[MB][MLP_H2];
+  __shared__ float sdz[MB];
+  __shared__ float sloss[MB];
+  const int t = threadIdx.x;
+  const int n = blockIdx.x * MB + t;
+  const float invB = 1.0f / (float)B;
+  if (n < B) {
+    float x[MLP_IN], h1[MLP_H1], h2[MLP_H2];
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) x[i] = X[(long long)n * MLP_IN + i];
+    const float z = mlp_forward1<true>(P, x, h1, h2);
+    const float yy = y[n] ? 1.0f : 0.0f;
+    const float sg = 1.0f / (1.0f + expf(-z));
+    sloss[t] = pw * yy * softplus_f(-z) + (1.0f - yy) * softplus_f(z);
+    const float dz = (-pw * yy * (1.0f - sg) + (1.0f - yy) * sg) * invB;
+    sdz[t] = dz;
+    float d2[MLP_H2];
+#pragma unroll
+    for (int o = 0; o < MLP_H2; ++o) {
+      d2[o] = dz * P[MLP_OW3 + o] * (1.0f - h2[o] * h2[o]);
+      sd2[t][o] = d2[o];
+      sh2[t][o] = h2[o];
+    }
+#pragma unroll 4
+    for (int i = 0; i < MLP_H1; ++i) {
+      float s = 0.0f;
+#pragma unroll
+      for (int o = 0; o < MLP_H2; ++o) s = s + P[MLP_OW2 + o * MLP_H1 + i] * d2[o];
+      sd1[t][i] = s * (1.0f - h1[i] * h1[i]);
+      sh1[t][i] = h1[i];
+    }
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) sx[t][i] = x[i];
+  } else {
+    for (int i = 0; i < MLP_IN; ++i) sx[t][i] = 0.0f;
+    for (int o = 0; o < MLP_H1; ++o) sh1[t][o] = sd1[t][o] = 0.0f;
+    for (int o = 0; o < MLP_H2; ++o) sh2[t][o] = sd2[t][o] = 0.0f;
+    sdz[t] = 0.0f;
+    sloss[t] = 0.0f;
+  }
+  __syncthreads();
+  float* out = partial + (long long)blockIdx.x * NPART;
+  for (int p = t; p < MLP_NPAR; p += MB) {
+    float g = 0.0f;
+    if (p < MLP_OB1) {
+      const int o = p / MLP_IN, i = p % MLP_IN;
+      for (int s = 0; s < MB; ++s) g = g + sd1[s][o] * sx[s][i];
+    } else if (p < MLP_OW2) {
+      const int o = p - MLP_OB1;
+      for (int s = 0; s < MB; ++s) g = g + sd1[s][o];
+    } else if (p < MLP_OB2) {
+      const int q = p - MLP_OW2, o = q / MLP_H1, i = q % MLP_H1;
+      for (int s = 0; s < MB; ++s) g = g + sd2[s][o] * sh1[s][i];
+    } else if (p < MLP_OW3) {
+      const int o = p - MLP_OB2;
+      for (int s = 0; s < MB; ++s) g = g + sd2[s][o];
+    } else if (p < MLP_OB3) {
+      const int o = p - MLP_OW3;
+      for (int s = 0; s < MB; ++s) g = g + sdz[s] * sh2[s][o];
+    } else {
+      for (int s = 0; s < MB; ++s) g = g + sdz[s];
+    }
+    out[p] = g;
+  }
+  if (t == 0) {
+    float l = 0.0f;
+    for (int s = 0; s < MB; ++s) l = l + sloss[s];
+    out[MLP_NPAR] = l;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad_final(const float* __restrict__ partial, int nblk,
+                                                        int B, float* __restrict__ grad,
+                                                        float* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= NPART) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblk; ++b) s = s + partial[(long long)b * NPART + p];
+  if (p < MLP_NPAR)
+    grad[p] = s;
+  else if (loss)
+    loss[0] = s / (float)B;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ m1,
+                                                  float* __restrict__ m2,
+                                                  const float* __restrict__ g, float c1, float c2,
+                                                  float lr, float b1, float b2, float eps) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= MLP_NPAR) return;
+  const float gp = g[p];
+  const float a = b1 * m1[p] + (1.0f - b1) * gp;
+  const float v = b2 * m2[p] + (1.0f - b2) * gp * gp;
+  m1[p] = a;
+  m2[p] = v;
+  P[p] = P[p] - lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+size_t mlp_work_floats(int B) { return (size_t)((B + MB - 1) / MB) * NPART; }
+
+hipError_t launch_mlp_forward(const float* P, const float* X, int B, float* logits, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3((B + 255) / 256), dim3(256), 0, s, P, X, B, logits);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float* P, const float* X, const uint8_t* y, int B, float pw,
+                           float* grad, float* loss, float* work, hipStream_t s) {
+  const int nblk = (B + MB - 1) / MB;
+  hipLaunchKernelGGL(k_mlp_grad_partial, dim3(nblk), dim3(MB), 0, s, P, X, y, B, pw, work);
+  hipLaunchKernelGGL(k_mlp_grad_final, dim3((NPART + 255) / 256), dim3(256), 0, s, work, nblk, B,
+                     grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, int step, float lr,
+                           float b1, float b2, float eps, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPAR + 255) / 256), dim3(256), 0, s, P, m1, m2, grad, c1,
+                     c2, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+}  // namespace crk

@@ -1,0 +1,185 @@
+"""Learned troubled-cell indicator: data generation, training and the
+decision band (not part of the paper's method).
+
+Everything numeric runs in the library's HIP kernels through the C ABI:
+the FP64 cRKDG solver with the TVB limiter generates the labels, the
+feature kernel the inputs, the MLP kernels the training (forward, backward,
+Adam).  This module only orchestrates: seeds, sampling, minibatch order.
+
+Labels: the FP64 TVB troubled-cell decision (flag bit 1) on the pre-limiter
+state after each sampled step, on seeded four-quadrant Riemann problems.
+Negatives are subsampled to at most 10 per positive (seeded).
+"""
+import math
+
+import numpy as np
+
+from . import crkdg as K
+from . import workloads as W
+
+NPAR = 12 * 32 + 32 + 32 * 32 + 32 + 32 + 1
+
+
+def quadrant_solver(seed, n, precision=K.FP64, split=None):
+    cfg = W.config("c4", scale=1)
+    cfg["nx"] = cfg["ny"] = n
+    x0, x1, y0, y1 = cfg["box"]
+    mesh = K.make_mesh(2, n, n, x0=x0, x1=x1, y0=y0, y1=y1, bc=(1, 1, 1, 1), equation=K.EQ_EULER,
+                       gamma=W.GAMMA, precision=precision)
+    s = K.Solver(mesh, cfg["k"], K.FLUX_LLF, 3)
+    rng = np.random.default_rng(10_000 + seed)
+    sp = split if split is not None else (0.5 + 0.02 * rng.uniform(-1, 1),
+                                          0.5 + 0.02 * rng.uniform(-1, 1))
+    s.crkdg_project(K.IC_QUADRANT, W.quadrant_params(seed, split=sp))
+    return s, cfg
+
+
+def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample_seed=0,
+             report=None):
+    """features X (float32 [S, 12]) and TVB labels y (uint8 [S]) from FP64
+    TVB runs of the four-quadrant problems with the given seeds, each run
+    until the fastest initial wave has crossed t_frac of the domain, sampled
+    at about `samples` evenly spaced steps.
+
+    Some random quadrant states (strong collisions of low-pressure gas) drive
+    a cell average out of the physical set, which neither the TVB limiter nor
+    the positivity safeguard can repair; such a run stops there and keeps the
+    samples taken before.  `report` (a dict, optional) receives the list of
+    those seeds under "stopped"."""
+    import torch
+    Xs, ys = [], []
+    stopped = []
+    rng = np.random.default_rng(sample_seed)
+    for seed in seeds:
+        s, cfg = quadrant_solver(seed, n)
+        s.crkdg_limit(M)  # the projected jumps overshoot
+        smax = s.crkdg_max_wavespeed()          # sum over directions of speed / h
+        h = (cfg["box"][1] - cfg["box"][0]) / n
+        speed = smax * h / 2.0
+        T = t_frac / speed
+        nsteps = int(math.ceil(T / (cfg["cfl"] / smax)))
+        stride = max(1, nsteps // samples)
+        t, step = 0.0, 0
+        flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+        X = torch.empty((s.ncells, 12), dtype=torch.float32, device="cuda")
+        while t < T - 1e-14:
+            dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), T - t)
+            s.crkdg_step(dt)
+            t += dt
+            step += 1
+            sample = step % stride == 0
+            if sample:
+                s.crkdg_mlp_features(M, X)
+            try:
+                s.crkdg_limit(M, flags if sample else None)
+            except K.CrkdgError as e:
+                if e.code != K.CRKDG_ENONPHYSICAL:
+                    raise
+                stopped.append(seed)
+                break
+            if sample:
+                xs = X.cpu().numpy()
+                lab = ((flags & 1) != 0).cpu().numpy().astype(np.uint8)
+                pos = np.nonzero(lab)[0]
+                neg = np.nonzero(lab == 0)[0]
+                take = min(len(neg), max(neg_ratio * len(pos), 256))
+                neg = rng.choice(neg, take, replace=False)
+                idx = np.concatenate([pos, neg])
+                Xs.append(xs[idx])
+                ys.append(lab[idx])
+    if report is not None:
+        report["stopped"] = stopped
+    if not Xs:
+        return np.zeros((0, 12), np.float32), np.zeros(0, np.uint8)
+    return np.concatenate(Xs).astype(np.float32), np.concatenate(ys).astype(np.uint8)
+
+
+def init_params(seed=0):
+    """Glorot-uniform weights, zero biases (float64 host array)"""
+    rng = np.random.default_rng(seed)
+    P = np.zeros(NPAR)
+    o = 0
+    for fan_out, fan_in in ((32, 12), (32, 32)):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        P[o:o + fan_out * fan_in] = rng.uniform(-lim, lim, fan_out * fan_in)
+        o += fan_out * fan_in + fan_out
+    lim = math.sqrt(6.0 / 33)
+    P[o:o + 32] = rng.uniform(-lim, lim, 32)
+    return P
+
+
+def train(X, y, epochs=10, batch=4096, lr=1e-3, pos_weight=None, seed=0):
+    """Adam on the weighted BCE; deterministic given the seed.  Returns the
+    device parameters and the per-epoch mean loss."""
+    import torch
+    dev = "cuda"
+    if pos_weight is None:
+        npos = max(1, int(y.sum()))
+        pos_weight = (len(y) - npos) / npos
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.uint8)).to(dev)
+    P = torch.from_numpy(init_params(seed).astype(np.float32)).to(dev)
+    m1 = torch.zeros_like(P)
+    m2 = torch.zeros_like(P)
+    grad = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    work = torch.empty(K.lib().crkdg_mlp_work_bytes(batch), dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(seed + 1)
+    step = 0
+    hist = []
+    for _ in range(epochs):
+        perm = torch.from_numpy(rng.permutation(len(y))).to(dev)
+        tot, nb = 0.0, 0
+        for b0 in range(0, len(y) - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            xb = Xd.index_select(0, idx).contiguous()
+            yb = yd.index_select(0, idx).contiguous()
+            K.crkdg_mlp_grad(P, xb, yb, pos_weight, grad, loss, work)
+            step += 1
+            K.crkdg_mlp_adam(P, m1, m2, grad, step, lr)
+            tot += float(loss.item()) if nb % 16 == 0 else 0.0
+            nb += 1
+        hist.append(tot)
+    return P, {"steps": step, "pos_weight": pos_weight, "loss_samples": hist}
+
+
+def probabilities(P, X):
+    import torch
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    z = K.crkdg_mlp_forward(P, Xd).cpu().numpy().astype(np.float64)
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def choose_band(P, Xval, yval, fn_target=0.01, fp_target=0.01):
+    """tau_lo: the largest threshold with at most fn_target of the TVB
+    positives at or below it (those would be missed); tau_hi: the smallest
+    threshold with at most fp_target of the negatives at or above it.  Cells
+    in between go to the FP64 TVB test.  Thresholds are taken among the
+    distinct probabilities, so tied values cannot push a rate past its target."""
+    p = probabilities(P, Xval)
+    pos = np.sort(p[yval == 1])
+    neg = np.sort(p[yval == 0])
+    k = int(math.floor(fn_target * len(pos)))
+    vals = np.unique(pos)
+    le = np.searchsorted(pos, vals, side="right")        # positives <= each value
+    ok = vals[le <= k]
+    tau_lo = float(ok[-1]) if ok.size else float(np.nextafter(pos[0], -np.inf))
+    j = int(math.floor(fp_target * len(neg)))
+    vals = np.unique(neg)
+    ge = len(neg) - np.searchsorted(neg, vals, side="left")  # negatives >= each value
+    ok = vals[ge <= j]
+    tau_hi = float(ok[0]) if ok.size else float(np.nextafter(neg[-1], np.inf))
+    tau_hi = max(tau_hi, tau_lo)
+    return tau_lo, tau_hi
+
+
+def rates(P, X, y, tau_lo, tau_hi):
+    p = probabilities(P, X)
+    pos = y == 1
+    smooth = p <= tau_lo
+    trouble = p >= tau_hi
+    band = ~smooth & ~trouble
+    return {"fn_rate": float((smooth & pos).sum() / max(1, pos.sum())),
+            "fp_rate": float((trouble & ~pos).sum() / max(1, (~pos).sum())),
+            "fallback_fraction": float(band.mean()),
+            "n": int(len(y)), "positives": int(pos.sum())}
