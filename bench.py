@@ -32,32 +32,35 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def algorithmic_bytes(cls, state_bytes, ncells, stages_final):
+def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final):
     """bytes a kernel class must move per launch (its inputs and outputs):
     inner: read u^n, write the stored stage state(s); final: read u^n and the
-    final-stage states, write u^{n+1}; limiter: read the state, write one
-    flag byte per cell; dt: read the cell averages."""
+    stored stage states, write u^{n+1}; limiter: read the state, write one
+    flag byte per cell; dt: read the cell averages (4 doubles per cell)."""
     if cls == "inner":
-        return state_bytes * (1 + (stages_final - 1))
+        return state_bytes + stage_bytes * (stages_final - 1)
     if cls == "final":
-        return state_bytes * (stages_final + 1)
+        return 2 * state_bytes + stage_bytes * (stages_final - 1)
     if cls == "limit":
         return state_bytes + ncells
     if cls == "dt":
-        return state_bytes // 9
+        return ncells * 32
     return None
 
 
-def make_solver(K, W, scale=1, precision=0):
-    import torch
-    cfg = W.config("c5", scale=scale)
-    params, xi = W.shock_problem(2000, cfg["nx"], cfg["ny"])
-    ghost = W.post_shock_conserved(params[0])
+def shock_mesh(K, W, cfg, theta, precision):
     x0, x1, y0, y1 = cfg["box"]
-    mesh = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(2, 1, 1, 1),
+    ghost = W.post_shock_conserved(theta)
+    return K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(2, 1, 1, 1),
                        bc_state=[ghost] * 4, equation=K.EQ_EULER, gamma=W.GAMMA,
                        precision=precision)
-    s = K.Solver(mesh, cfg["k"], K.FLUX_LLF, 3)
+
+
+def make_solver(K, W, scale=1, precision=0, field_grid=None):
+    import torch
+    cfg = W.config("c5", scale=scale)
+    params, xi = W.shock_problem(2000, cfg["nx"], cfg["ny"], field_grid=field_grid)
+    s = K.Solver(shock_mesh(K, W, cfg, params[0], precision), cfg["k"], K.FLUX_LLF, 3)
     s.crkdg_project(K.IC_SHOCK, params, aux=torch.from_numpy(xi).cuda())
     s.crkdg_limit(cfg["limiter"][1])  # the projected shock overshoots: limit once
     return s, cfg, params, xi
@@ -96,10 +99,56 @@ def cpu_baseline(W, seconds=12.0):
         n += 1
     el = time.perf_counter() - t0
     dofs = nx * ny * (k + 1) ** 2 * 4
+    host = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            host = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": dofs * n / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "host": host,
             "sample": f"{nx}x{ny}-cell patch of the same workload (Q2, eq3, LLF, TVB M=50, "
                       f"same cell size and boundary types), {n} steps after 1 warm-up, "
                       f"serial FP64 C oracle, {el:.1f} s"}
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def train_indicator(K, ML):
+    """train the learned troubled-cell indicator with the library's own kernels
+    on runs labelled by the FP64 TVB test (M = 50): four-quadrant Riemann
+    problems and planar-shock problems with seeds other than the benchmark's;
+    choose the decision band on held-out seeds"""
+    t0 = time.perf_counter()
+    rep = {}
+    parts = [ML.generate(range(0, 32), n=128, report=rep),
+             ML.generate(range(2100, 2108), n=4, family="shock"),
+             ML.generate(range(2100, 2104), n=1, family="shock", max_steps=400, samples=10)]
+    Xtr = np.concatenate([p[0] for p in parts])
+    ytr = np.concatenate([p[1] for p in parts])
+    vparts = [ML.generate(range(64, 72), n=128, sample_seed=1),
+              ML.generate(range(2200, 2202), n=4, family="shock", sample_seed=1),
+              ML.generate([2200], n=1, family="shock", max_steps=400, samples=10, sample_seed=1)]
+    Xva = np.concatenate([p[0] for p in vparts])
+    yva = np.concatenate([p[1] for p in vparts])
+    t1 = time.perf_counter()
+    P, info = ML.train(Xtr, ytr, epochs=10, batch=4096, seed=0)
+    lo, hi = ML.choose_band(P, Xva, yva)
+    rv = ML.rates(P, Xva, yva, lo, hi)
+    t2 = time.perf_counter()
+    return P, lo, hi, {
+        "train": "four-quadrant Riemann problems (seeds 0-31, 128x128 Q2, to 0.25 domain "
+                 "crossings) + planar-shock problems (seeds 2100-2107 at 1024x256 to T=0.25; "
+                 "seeds 2100-2103 at 4096x1024, 400 steps); labels: FP64 TVB test, M=50",
+        "validation_sets": "quadrant seeds 64-71; shock seeds 2200-2201 at 1024x256, 2200 at "
+                           "4096x1024 (400 steps)",
+        "samples": int(len(ytr)), "positives": int(ytr.sum()),
+        "runs_stopped_nonphysical": rep.get("stopped", []),
+        "adam_steps": info["steps"], "epochs": 10, "batch": 4096,
+        "tau_lo": lo, "tau_hi": hi, "validation": rv,
+        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
 
 
 def main():
@@ -108,8 +157,13 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--equal-error-scale", type=int, default=4,
+                    help="the equal-error runs use the workload with cell counts divided by this")
     ap.add_argument("--scale", type=int, default=1, help="divide the cell counts (debug only)")
     args = ap.parse_args()
+    if args.equal_error_scale < 2:
+        ap.error("--equal-error-scale must be at least 2 (the reference is twice as fine)")
     if args.gpus != 1:
         print(f"bench.py measures one GPU; this build has no multi-GPU path (--gpus {args.gpus})",
               file=sys.stderr)
@@ -117,14 +171,22 @@ def main():
 
     import torch
     from paper_2307_06471_amd import crkdg as K
+    from paper_2307_06471_amd import mlp as ML
     from paper_2307_06471_amd import workloads as W
 
+    P, lo, hi, mlp_info = train_indicator(K, ML)
+    log(f"indicator trained: {mlp_info['samples']} samples, band ({lo:.4g}, {hi:.4g}), "
+        f"validation {mlp_info['validation']}")
+    mlp = (P, lo, hi)
+
     forms = {}
-    for name, prec in (("fp32-bulk + TVB", K.FP32_MIXED), ("fp64 + TVB", K.FP64)):
-        forms[name] = run_form(K, W, args, prec)
-        print(f"# {name}: {forms[name]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    head = forms["fp32-bulk + TVB"]
+    for name, prec, ind in (("fp32-bulk + MLP", K.FP32_MIXED, mlp), ("fp64 + TVB", K.FP64, None),
+                            ("fp32-bulk + TVB", K.FP32_MIXED, None)):
+        forms[name] = run_form(K, W, args, prec, ind)
+        log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
+    head = forms["fp32-bulk + MLP"]
     plain = forms["fp64 + TVB"]
+    tvb32 = forms["fp32-bulk + TVB"]
     out = {
         "metric": METRIC, "value": head["value"], "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -132,23 +194,30 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D Euler Mach-3 shock into a smoothed density field, "
                                f"{head['nx']}x{head['ny']} Q2 cells on [0,4]x[0,1], cRKDG scheme "
-                               f"eq3, Lax-Friedrichs flux, TVB minmod M=50 (FP64 test), "
+                               f"eq3, Lax-Friedrichs flux, final-stage limiter M=50, "
                                f"per-step dt (CFL 0.1)",
                    "form": "fp32-bulk (FP32 contractions and fluxes, FP64 cell averages and "
-                           "face-flux sums) + TVB limiter",
+                           "face-flux sums) + learned troubled-cell indicator (12-32-32-1 MLP, "
+                           "FP64 TVB test inside its uncertainty band)",
                    "cells": head["cells"], "dofs": head["dofs"], "parallelism": "1 GPU"},
         "roofline": head["roofline"],
         "kernels": head["kernels"],
         "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"],
                        "roofline": plain["roofline"], "kernels": plain["kernels"]},
+        "fp32_bulk_tvb": {"value": tvb32["value"], "ms_per_step": tvb32["ms_per_step"],
+                          "kernels": tvb32["kernels"]},
         "speedup_vs_fp64_plain": head["value"] / plain["value"],
+        "mlp": mlp_info,
     }
+    if not args.no_equal_error:
+        out["equal_error"] = equal_error(K, W, args.equal_error_scale, mlp)
+        log(f"equal error: {out['equal_error']['verdict']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
 
 
-def run_form(K, W, args, precision):
+def run_form(K, W, args, precision, mlp=None):
     import torch
     s, cfg, params, xi = make_solver(K, W, args.scale, precision)
     stream = s.stream
@@ -156,10 +225,19 @@ def run_form(K, W, args, precision):
     flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
     M = cfg["limiter"][1]
 
+    if mlp is None:
+        def limit():
+            s.crkdg_limit(M, flags, count=False)
+    else:
+        P, lo, hi = mlp
+
+        def limit():
+            s.crkdg_limit_mlp(M, P, lo, hi, flags, count=False)
+
     def step():
         s.crkdg_compute_dt(cfg["cfl"], dt_dev)
         s.crkdg_step_dev(dt_dev)
-        s.crkdg_limit(M, flags, count=False)
+        limit()
 
     for _ in range(args.warmup):
         step()
@@ -179,13 +257,14 @@ def run_form(K, W, args, precision):
 
     dofs = s.ncells * s.nmodes * s.ncomp
     stages_final = 2  # scheme (eq:3): b = (1/4, 0, 3/4)
+    stage_bytes = s.ncells * s.nmodes * s.ncomp * (4 if precision == K.FP32_MIXED else 8)
     kern = {}
     for cls, (tms, cnt) in prof.items():
-        by = algorithmic_bytes(cls, s.state_bytes, s.ncells, stages_final)
+        by = algorithmic_bytes(cls, s.state_bytes, stage_bytes, s.ncells, stages_final)
         kern[cls] = {"ms_per_launch": tms / cnt, "launches": cnt, "share": tms / ms,
                      "achieved_GBs": None if by is None else by / (tms / cnt * 1e-3) / 1e9}
     dom = max(prof, key=lambda c: prof[c][0])
-    by = algorithmic_bytes(dom, s.state_bytes, s.ncells, stages_final)
+    by = algorithmic_bytes(dom, s.state_bytes, stage_bytes, s.ncells, stages_final)
     achieved = by / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
@@ -193,6 +272,93 @@ def run_form(K, W, args, precision):
     return {"value": dofs * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
             "roofline": roof, "kernels": kern, "flagged_cells_end": n_flag,
             "cells": s.ncells, "dofs": dofs, "nx": cfg["nx"], "ny": cfg["ny"]}
+
+
+def equal_error(K, W, scale, mlp, samples=10):
+    """the same shock workload with cell counts divided by `scale`, run to
+    T = 0.25 by FP64 + TVB, FP32-bulk + TVB and FP32-bulk + learned indicator;
+    L1/L2 density errors of the cell averages against FP64 + TVB on the 2x
+    finer mesh restricted to this one.  At about `samples` steps of the
+    learned-indicator run its decisions are compared with the FP64 TVB test
+    on the same (pre-limiter) state."""
+    import torch
+    P, lo, hi = mlp
+    T = W.config("c5")["T"]
+
+    coarse = W.config("c5", scale)
+    grid = (coarse["nx"], coarse["ny"])  # the reference sees the same initial density field
+
+    def run(scale_, precision, indicator, rates=False):
+        s, cfg, params, _ = make_solver(K, W, scale_, precision, field_grid=grid)
+        M = cfg["limiter"][1]
+        flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+        clone = None
+        if rates:  # an FP64 copy of the state takes the TVB decisions for comparison
+            clone = K.Solver(shock_mesh(K, W, cfg, params[0], K.FP64), cfg["k"], K.FLUX_LLF, 3)
+            tflags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+        t, n = 0.0, 0
+        tot = {"flagged": 0, "fallback": 0, "cells": 0, "tvb_pos": 0, "fn": 0, "fp": 0,
+               "sampled": 0}
+        nsteps_est = None
+        t0 = time.perf_counter()
+        while t < T - 1e-14:
+            dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), T - t)
+            if nsteps_est is None:
+                nsteps_est = int(T / dt) + 1
+            s.crkdg_step(dt)
+            t += dt
+            n += 1
+            sample = rates and n % max(1, nsteps_est // samples) == 0
+            if sample:
+                clone.crkdg_set_state(s.crkdg_get_state())
+                clone.crkdg_limit(M, tflags)
+            if indicator is None:
+                tot["flagged"] += s.crkdg_limit(M, flags if sample else None)
+            else:
+                nf, nb = s.crkdg_limit_mlp(M, P, lo, hi, flags if sample else None)
+                tot["flagged"] += nf
+                tot["fallback"] += nb
+            tot["cells"] += s.ncells
+            if sample:
+                tv = (tflags & 1).bool()
+                ml = (flags & 1).bool()
+                tot["tvb_pos"] += int(tv.sum())
+                tot["fn"] += int((tv & ~ml).sum())
+                tot["fp"] += int((ml & ~tv).sum())
+                tot["sampled"] += s.ncells
+        torch.cuda.synchronize()
+        return s, n, tot, time.perf_counter() - t0
+
+    ref, nref, _, tref = run(max(1, scale // 2), K.FP64, None)
+    log(f"equal-error reference {ref.mesh.nx}x{ref.mesh.ny}: {nref} steps, {tref:.1f} s")
+    res = {}
+    same = None
+    for name, prec, ind in (("fp64 + TVB", K.FP64, None), ("fp32-bulk + TVB", K.FP32_MIXED, None),
+                            ("fp32-bulk + MLP", K.FP32_MIXED, mlp)):
+        s, n, tot, el = run(scale, prec, ind, rates=ind is not None)
+        e = s.crkdg_error_ref(ref, 0)
+        r = {"L1": float(e[0]), "L2": float(e[1]), "Linf": float(e[2]), "steps": n,
+             "flagged_fraction": tot["flagged"] / tot["cells"]}
+        if same is None:
+            same = s  # FP64 + TVB on this mesh
+        else:
+            d = s.crkdg_error_ref(same, 0)
+            r["L1_vs_fp64_tvb_same_mesh"] = float(d[0])
+            r["L2_vs_fp64_tvb_same_mesh"] = float(d[1])
+        if ind is not None:
+            r["fallback_fraction"] = tot["fallback"] / tot["cells"]
+            r["fn_rate_vs_tvb"] = tot["fn"] / max(1, tot["tvb_pos"])
+            r["fp_rate_vs_tvb"] = tot["fp"] / max(1, tot["sampled"] - tot["tvb_pos"])
+            r["rate_samples_cells"] = tot["sampled"]
+        res[name] = r
+        log(f"  {name}: L1 {r['L1']:.4e} L2 {r['L2']:.4e} flagged {r['flagged_fraction']:.4f}")
+    base, cand = res["fp64 + TVB"], res["fp32-bulk + MLP"]
+    equal = cand["L1"] <= 1.05 * base["L1"] and cand["L2"] <= 1.05 * base["L2"]
+    return {"mesh": f"{W.config('c5', scale)['nx']}x{W.config('c5', scale)['ny']}",
+            "reference": f"FP64 + TVB on {ref.mesh.nx}x{ref.mesh.ny}, restricted",
+            "T": T, "criterion": "L1 and L2 of the density averages within 1.05x of FP64 + TVB",
+            "runs": res, "verdict": "equal" if equal else "not equal",
+            "L1_ratio": cand["L1"] / base["L1"], "L2_ratio": cand["L2"] / base["L2"]}
 
 
 if __name__ == "__main__":

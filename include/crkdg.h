@@ -185,6 +185,16 @@ int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int s
  * per cell; out on host (syncs).  Deterministic two-pass reduction. */
 int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, double t,
                 int comp, double out_l1_l2_linf[3]);
+/* L1, L2 (unnormalised, |K|-weighted sums) and Linf errors of the cell
+ * averages of component comp against a finer reference state `ref` restricted
+ * to this mesh: each coarse cell is compared with the mean of the r x ry fine
+ * cell averages covering it (r = ref nx / nx, ry = ref ny / ny; the error
+ * tables of Section 4 measure against a refined solution where no exact one
+ * exists).  Both states must be bound, have the same equation and domain, and
+ * the fine cell counts must be integer multiples of the coarse ones; ref may
+ * have any degree and precision.  out on host (syncs both streams).
+ * Deterministic two-pass reduction.  CRKDG_EINVAL on mismatched meshes. */
+int crkdg_error_ref(crkdg_state* st, crkdg_state* ref, int comp, double out_l1_l2_linf[3]);
 /* sum over cells of |K| * cell average of component comp (syncs) */
 int crkdg_total(crkdg_state* st, int comp, double* out_host);
 

@@ -154,9 +154,20 @@ def dlegendre(m, x):
     return lib().or_dlegendre(m, float(x))
 
 
+NPARAM = 24  # initial-condition parameters; unused trailing ones are zero
+
+
+def _params(params):
+    p = np.zeros(NPARAM)
+    v = np.asarray(params, dtype=np.float64).ravel()
+    assert v.size <= NPARAM
+    p[:v.size] = v
+    return p
+
+
 def project(mesh, k, ic, params=None, aux=None, t=0.0):
     u = mesh.zeros(k)
-    p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    p = None if params is None else _params(params)
     a = None if aux is None else np.ascontiguousarray(aux, dtype=np.float64)
     assert lib().or_project(mesh.ref, k, ic, _d(p), _d(a), t, _d(u)) == 0
     return u
@@ -254,7 +265,7 @@ def max_wavespeed(mesh, k, u):
 def errors(mesh, k, u, ic, params=None, aux=None, t=0.0, comp=0):
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros(3)
-    p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    p = None if params is None else _params(params)
     a = None if aux is None else np.ascontiguousarray(aux, dtype=np.float64)
     lib().or_errors(mesh.ref, k, _d(u), ic, _d(p), _d(a), t, comp, _d(out))
     return out

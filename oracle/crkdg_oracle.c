@@ -253,15 +253,18 @@ static void exact_state(const or_mesh* m, int ic, const double* P, const double*
         prim_to_cons(m, rs, uns * nxv, uns * nyv, ps, q);
         return;
       }
-      /* bilinear interpolation of the cell-centre field, periodic wrap */
-      double hx = cdx(m), hy = cdy(m);
+      /* bilinear interpolation of a cell-centre field given on an na x ma
+       * grid over the domain (P[8], P[9]; 0 means the mesh's cells),
+       * periodic wrap */
+      int na = P[8] > 0.0 ? (int)P[8] : m->nx, ma = P[9] > 0.0 ? (int)P[9] : m->ny;
+      double hx = (m->x1 - m->x0) / na, hy = (m->y1 - m->y0) / ma;
       double sx = (x - m->x0) / hx - 0.5, sy = (y - m->y0) / hy - 0.5;
       double fx = floor(sx), fy = floor(sy);
       double ax = sx - fx, ay = sy - fy;
-      int i0 = ((int)fx % m->nx + m->nx) % m->nx, j0 = ((int)fy % m->ny + m->ny) % m->ny;
-      int i1 = (i0 + 1) % m->nx, j1 = (j0 + 1) % m->ny;
-      double xi = (1 - ax) * (1 - ay) * aux[j0 * m->nx + i0] + ax * (1 - ay) * aux[j0 * m->nx + i1] +
-                  (1 - ax) * ay * aux[j1 * m->nx + i0] + ax * ay * aux[j1 * m->nx + i1];
+      int i0 = ((int)fx % na + na) % na, j0 = ((int)fy % ma + ma) % ma;
+      int i1 = (i0 + 1) % na, j1 = (j0 + 1) % ma;
+      double xi = (1 - ax) * (1 - ay) * aux[j0 * na + i0] + ax * (1 - ay) * aux[j0 * na + i1] +
+                  (1 - ax) * ay * aux[j1 * na + i0] + ax * ay * aux[j1 * na + i1];
       double rho = 1.0 + amp * xi;
       if (rho < rfloor) rho = rfloor;
       prim_to_cons(m, rho, 0.0, 0.0, 1.0, q);

@@ -66,6 +66,7 @@ def _sig():
         "crkdg_max_wavespeed": (C.c_int, [vp, dp]),
         "crkdg_limit": (C.c_int, [vp, C.c_double, vp, C.POINTER(C.c_int64)]),
         "crkdg_error": (C.c_int, [vp, C.c_int, dp, C.c_int, C.c_double, C.c_int, dp]),
+        "crkdg_error_ref": (C.c_int, [vp, vp, C.c_int, dp]),
         "crkdg_total": (C.c_int, [vp, C.c_int, dp]),
         "crkdg_apply_op": (C.c_int, [vp, C.c_int, vp, vp, C.c_double]),
         "crkdg_combine": (C.c_int, [vp, vp, vp, C.c_int, dp, C.POINTER(vp)]),
@@ -196,7 +197,8 @@ class Solver:
 
     def crkdg_set_state(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64)
-        assert u.size * 8 == self.state_bytes, (u.shape, self.state_bytes)
+        if u.size != self.ncomp * self.nmodes * self.ncells:
+            raise ValueError(f"state of shape {u.shape}, expected {self.shape}")
         _check(lib().crkdg_set_state(self.h, _dp(u)), "crkdg_set_state")
 
     def crkdg_get_state(self):
@@ -261,6 +263,13 @@ class Solver:
         out = np.zeros(3)
         _check(lib().crkdg_error(self.h, ic, _dp(P), 0 if P is None else P.size, float(t), comp,
                                  _dp(out)), "crkdg_error")
+        return out
+
+    def crkdg_error_ref(self, ref, comp=0):
+        """errors of this state's cell averages against the finer Solver `ref`
+        restricted to this mesh: (L1, L2, Linf)"""
+        out = np.zeros(3)
+        _check(lib().crkdg_error_ref(self.h, ref.h, comp, _dp(out)), "crkdg_error_ref")
         return out
 
     def crkdg_total(self, comp=0):

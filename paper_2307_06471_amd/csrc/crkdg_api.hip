@@ -578,6 +578,41 @@ int crkdg_total(crkdg_state* st, int comp, double* out) {
   return hip_rc(e);
 }
 
+static const double* avg_base(const crkdg_state* st, int comp) {
+  const double* u = (const double*)cur_ptr(st);
+  const long long N = st->geo.N;
+  return st->lay == LMIX ? u + (long long)comp * N : u + (long long)comp * st->nb * N;
+}
+
+int crkdg_error_ref(crkdg_state* st, crkdg_state* ref, int comp, double out[3]) {
+  if (!st || !ref || !out || comp < 0 || comp >= st->nc) return CRKDG_EINVAL;
+  if (!st->bound || !ref->bound) return CRKDG_EUNBOUND;
+  if (ref->eq != st->eq || ref->nc != st->nc) return CRKDG_EINVAL;
+  const Geo& g = st->geo;
+  const Geo& f = ref->geo;
+  const bool two_d = st->mesh.dim == 2;
+  if (ref->mesh.dim != st->mesh.dim || f.nx % g.nx != 0 || (two_d && f.ny % g.ny != 0))
+    return CRKDG_EINVAL;
+  const int r = f.nx / g.nx, ry = two_d ? f.ny / g.ny : 1;
+  // same domain: the fine cells must tile the coarse ones exactly
+  const double tol = 1e-12;
+  if (fabs(f.dx * r - g.dx) > tol * g.dx || fabs(f.x0 - g.x0) > tol * (g.dx + fabs(g.x0)) ||
+      (two_d && (fabs(f.dy * ry - g.dy) > tol * g.dy || fabs(f.y0 - g.y0) > tol * (g.dy + fabs(g.y0)))))
+    return CRKDG_EINVAL;
+  if (ref->stream != st->stream) {
+    hipError_t e = hipStreamSynchronize(ref->stream);
+    if (e != hipSuccess) return hip_rc(e);
+  }
+  double* partial = (double*)scratch_ptr(st);
+  double* res = (double*)(scratch_ptr(st) + SCRATCH - 256);
+  const double area = g.dx * (two_d ? g.dy : 1.0);
+  hipError_t e = launch_error_ref(g, avg_base(st, comp), avg_base(ref, comp), r, ry, f.nx, area,
+                                  partial, RED_BLOCKS, res, st->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return hip_rc(e);
+}
+
 int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_bc) {
   if (!st || !in || !out || (op != CRKDG_OP_LOC && op != CRKDG_OP_DG)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;

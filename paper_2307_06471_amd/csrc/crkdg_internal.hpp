@@ -82,6 +82,11 @@ hipError_t launch_error(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                         double* partial, int nblocks, double* out3, hipStream_t s);
 hipError_t launch_total(int eq, int k, int lay, const Geo& g, const void* u, int comp,
                         double* partial, int nblocks, double* out, hipStream_t s);
+// errors of cell averages ac[cell] against the r x ry restriction of the
+// finer averages af (row length nxf)
+hipError_t launch_error_ref(const Geo& g, const double* ac, const double* af, int r, int ry,
+                            long long nxf, double area, double* partial, int nb, double* out3,
+                            hipStream_t s);
 hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& g, int ic,
                           const double* params, const double* aux, double t, void* u,
                           hipStream_t s);

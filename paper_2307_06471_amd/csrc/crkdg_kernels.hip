@@ -215,15 +215,18 @@ __device__ void exact_state(int ic, const double* P, const double* aux, const Ge
         prim2cons(dim, ph.gamma, P[1], P[2] * cth, P[2] * sth, P[3], q);
         return;
       }
-      // bilinear interpolation of the cell-centre field, periodic wrap
-      const double fx = (x - g.x0) / g.dx - 0.5, fy = (y - g.y0) / g.dy - 0.5;
+      // bilinear interpolation of a cell-centre field on an na x ma grid over
+      // the domain (P[8], P[9]; 0: the mesh's own cells), periodic wrap
+      const int na = P[8] > 0.0 ? (int)P[8] : g.nx, ma = P[9] > 0.0 ? (int)P[9] : g.ny;
+      const double hxa = g.dx * g.nx / na, hya = g.dy * g.ny / ma;
+      const double fx = (x - g.x0) / hxa - 0.5, fy = (y - g.y0) / hya - 0.5;
       const double bx = floor(fx), by = floor(fy);
       const double wx = fx - bx, wy = fy - by;
-      int i0 = (int)bx % g.nx; if (i0 < 0) i0 += g.nx;
-      int j0 = (int)by % g.ny; if (j0 < 0) j0 += g.ny;
-      const int i1 = i0 + 1 == g.nx ? 0 : i0 + 1, j1 = j0 + 1 == g.ny ? 0 : j0 + 1;
-      const double a00 = aux[(long long)j0 * g.nx + i0], a10 = aux[(long long)j0 * g.nx + i1];
-      const double a01 = aux[(long long)j1 * g.nx + i0], a11 = aux[(long long)j1 * g.nx + i1];
+      int i0 = (int)bx % na; if (i0 < 0) i0 += na;
+      int j0 = (int)by % ma; if (j0 < 0) j0 += ma;
+      const int i1 = i0 + 1 == na ? 0 : i0 + 1, j1 = j0 + 1 == ma ? 0 : j0 + 1;
+      const double a00 = aux[(long long)j0 * na + i0], a10 = aux[(long long)j0 * na + i1];
+      const double a01 = aux[(long long)j1 * na + i0], a11 = aux[(long long)j1 * na + i1];
       const double xi = (1.0 - wy) * ((1.0 - wx) * a00 + wx * a10) + wy * ((1.0 - wx) * a01 + wx * a11);
       double rho = 1.0 + P[7] * xi;
       if (rho < P[6]) rho = P[6];
@@ -864,6 +867,39 @@ __global__ __launch_bounds__(256) void k_total_partial(Geo g, const void* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// errors of one component's cell averages against a finer reference mesh
+// restricted to this one (mean of the r x ry fine averages covering a cell;
+// each line of fine cells summed in x order, lines in y order)
+__global__ __launch_bounds__(256) void k_error_ref_partial(Geo g, const double* __restrict__ ac,
+                                                           const double* __restrict__ af, int r,
+                                                           int ry, long long nxf, double area,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const double inv = 1.0 / (double)(r * ry);
+  double l1 = 0.0, l2 = 0.0, li = 0.0;
+  for (long long cell = (long long)blockIdx.x * 256 + threadIdx.x; cell < g.N;
+       cell += (long long)gridDim.x * 256) {
+    const long long i = cell % g.nx, j = cell / g.nx;
+    double s = 0.0;
+    for (int jj = 0; jj < ry; ++jj) {
+      const double* row = af + (j * ry + jj) * nxf + i * r;
+      for (int ii = 0; ii < r; ++ii) s += row[ii];
+    }
+    const double e = fabs(ac[cell] - s * inv);
+    l1 += area * e;
+    l2 += area * e * e;
+    if (e > li || e != e) li = e;
+  }
+  l1 = block_sum<256>(l1, sh);
+  l2 = block_sum<256>(l2, sh);
+  li = block_max<256>(li, sh);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = l1;
+    partial[3 * blockIdx.x + 1] = l2;
+    partial[3 * blockIdx.x + 2] = li;
+  }
+}
+
 // sums (stride 3 groups: l1, l2 summed, linf max) in a fixed order
 __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int n, int width,
                                                    double scale, double* out) {
@@ -1438,6 +1474,14 @@ hipError_t launch_error(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                         int ic, const double* params, const double* aux, double t, int comp,
                         double* partial, int nb, double* out3, hipStream_t s) {
   return dispatch<RunError>(eq, k, ph, g, u, lay, ic, params, aux, t, comp, partial, nb, out3, s);
+}
+hipError_t launch_error_ref(const Geo& g, const double* ac, const double* af, int r, int ry,
+                            long long nxf, double area, double* partial, int nb, double* out3,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_error_ref_partial, dim3(nb), dim3(256), 0, s, g, ac, af, r, ry, nxf, area,
+                     partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, 3, 1.0, out3);
+  return hipGetLastError();
 }
 hipError_t launch_total(int eq, int k, int lay, const Geo& g, const void* u, int comp,
                         double* partial, int nb, double* out, hipStream_t s) {

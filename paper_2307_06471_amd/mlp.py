@@ -7,8 +7,9 @@ feature kernel the inputs, the MLP kernels the training (forward, backward,
 Adam).  This module only orchestrates: seeds, sampling, minibatch order.
 
 Labels: the FP64 TVB troubled-cell decision (flag bit 1) on the pre-limiter
-state after each sampled step, on seeded four-quadrant Riemann problems.
-Negatives are subsampled to at most 10 per positive (seeded).
+state after each sampled step, on seeded four-quadrant Riemann problems and
+seeded planar-shock problems.  Negatives are subsampled to at most 10 per
+positive (seeded).
 """
 import math
 
@@ -34,12 +35,35 @@ def quadrant_solver(seed, n, precision=K.FP64, split=None):
     return s, cfg
 
 
+def shock_solver(seed, scale, precision=K.FP64):
+    """the planar-shock workload (Mach 3 into a smoothed density field) with
+    cell counts divided by `scale` and the shock angle and noise from `seed`"""
+    import torch
+    cfg = W.config("c5", scale=scale)
+    params, xi = W.shock_problem(seed, cfg["nx"], cfg["ny"])
+    x0, x1, y0, y1 = cfg["box"]
+    ghost = W.post_shock_conserved(params[0])
+    mesh = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(2, 1, 1, 1),
+                       bc_state=[ghost] * 4, equation=K.EQ_EULER, gamma=W.GAMMA,
+                       precision=precision)
+    s = K.Solver(mesh, cfg["k"], K.FLUX_LLF, 3)
+    s.crkdg_project(K.IC_SHOCK, params, aux=torch.from_numpy(xi).cuda())
+    return s, cfg
+
+
 def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample_seed=0,
-             report=None):
+             report=None, family="quadrant", max_steps=None, max_pos=20000):
     """features X (float32 [S, 12]) and TVB labels y (uint8 [S]) from FP64
-    TVB runs of the four-quadrant problems with the given seeds, each run
-    until the fastest initial wave has crossed t_frac of the domain, sampled
-    at about `samples` evenly spaced steps.
+    TVB runs with the given seeds, sampled at about `samples` evenly spaced
+    steps.
+
+    family "quadrant": four-quadrant problems on n x n cells, each run until
+    the fastest initial wave has crossed t_frac of the domain.  family
+    "shock": the planar-shock workload with cell counts divided by n, run to
+    its final time or for max_steps steps.
+
+    Per sampled step at most max_pos positives are kept, and negatives are
+    subsampled to neg_ratio per positive (at least 256).
 
     Some random quadrant states (strong collisions of low-pressure gas) drive
     a cell average out of the physical set, which neither the TVB limiter nor
@@ -51,18 +75,27 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
     stopped = []
     rng = np.random.default_rng(sample_seed)
     for seed in seeds:
-        s, cfg = quadrant_solver(seed, n)
-        s.crkdg_limit(M)  # the projected jumps overshoot
-        smax = s.crkdg_max_wavespeed()          # sum over directions of speed / h
-        h = (cfg["box"][1] - cfg["box"][0]) / n
-        speed = smax * h / 2.0
-        T = t_frac / speed
-        nsteps = int(math.ceil(T / (cfg["cfl"] / smax)))
+        if family == "quadrant":
+            s, cfg = quadrant_solver(seed, n)
+            s.crkdg_limit(M)  # the projected jumps overshoot
+            smax = s.crkdg_max_wavespeed()          # sum over directions of speed / h
+            h = (cfg["box"][1] - cfg["box"][0]) / n
+            T = t_frac / (smax * h / 2.0)
+            nsteps = int(math.ceil(T / (cfg["cfl"] / smax)))
+        elif family == "shock":
+            s, cfg = shock_solver(seed, n)
+            s.crkdg_limit(M)
+            T = cfg["T"]
+            nsteps = int(math.ceil(T / (cfg["cfl"] / s.crkdg_max_wavespeed())))
+        else:
+            raise ValueError(family)
+        if max_steps is not None and nsteps > max_steps:
+            nsteps = max_steps
         stride = max(1, nsteps // samples)
         t, step = 0.0, 0
         flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
         X = torch.empty((s.ncells, 12), dtype=torch.float32, device="cuda")
-        while t < T - 1e-14:
+        while t < T - 1e-14 and step < nsteps:
             dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), T - t)
             s.crkdg_step(dt)
             t += dt
@@ -78,15 +111,17 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
                 stopped.append(seed)
                 break
             if sample:
-                xs = X.cpu().numpy()
-                lab = ((flags & 1) != 0).cpu().numpy().astype(np.uint8)
+                lab = ((flags & 1) != 0).cpu().numpy()
                 pos = np.nonzero(lab)[0]
-                neg = np.nonzero(lab == 0)[0]
+                neg = np.nonzero(~lab)[0]
+                if len(pos) > max_pos:
+                    pos = rng.choice(pos, max_pos, replace=False)
                 take = min(len(neg), max(neg_ratio * len(pos), 256))
                 neg = rng.choice(neg, take, replace=False)
-                idx = np.concatenate([pos, neg])
-                Xs.append(xs[idx])
-                ys.append(lab[idx])
+                idx = np.sort(np.concatenate([pos, neg]))
+                Xs.append(X[torch.from_numpy(idx).cuda()].cpu().numpy())
+                ys.append(lab[idx].astype(np.uint8))
+        del s
     if report is not None:
         report["stopped"] = stopped
     if not Xs:

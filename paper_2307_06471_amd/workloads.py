@@ -111,12 +111,18 @@ def smoothed_noise(rng, nx, ny, sigma_cells=8.0):
     return np.ascontiguousarray(f)
 
 
-def shock_problem(seed, nx, ny):
-    """parameters of the shock workload and its noise field xi[ny][nx]"""
+def shock_problem(seed, nx, ny, field_grid=None):
+    """parameters of the shock workload and its noise field xi on the nx x ny
+    cell-centre grid, or on the field_grid = (na, ma) grid over the same
+    domain (so that meshes of different resolution see the same initial
+    density function; the grid size then travels in params[8:10])"""
     theta, rng = shock_angle(seed)
-    xi = smoothed_noise(rng, nx, ny)
+    na, ma = field_grid if field_grid is not None else (nx, ny)
+    xi = smoothed_noise(rng, na, ma)
     rho_s, un_s, p_s = POST_SHOCK
     params = [theta, rho_s, un_s, p_s, 0.5, 0.5, 0.5, 0.1]
+    if field_grid is not None:
+        params += [float(na), float(ma)]
     return params, xi
 
 

@@ -187,7 +187,8 @@ def test_bitwise_determinism(K):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("ic", ["const", "adv1", "adv2", "wave", "vortex", "quadrant", "shock"])
+@pytest.mark.parametrize("ic", ["const", "adv1", "adv2", "wave", "vortex", "quadrant", "shock",
+                                "shock_coarse_field"])
 def test_projection(K, ic):
     k = 2
     if ic in ("adv1",):
@@ -208,8 +209,11 @@ def test_projection(K, ic):
             p, oid, lid = [5.0, 1.0, 1.0, 2.0, 2.0], O.IC_VORTEX, K.IC_VORTEX
         elif ic == "quadrant":
             p, oid, lid = W.quadrant_params(3, split=(1.03, 0.97)), O.IC_QUADRANT, K.IC_QUADRANT
-        else:
+        elif ic == "shock":
             p, aux = W.shock_problem(2000, 130, 33)
+            oid, lid = O.IC_SHOCK, K.IC_SHOCK
+        else:  # the noise field on a coarser grid than the mesh
+            p, aux = W.shock_problem(2000, 130, 33, field_grid=(45, 17))
             oid, lid = O.IC_SHOCK, K.IC_SHOCK
     s = solver(K, lm, k, "llf" if ic not in ("adv1", "adv2") else "upwind")
     if aux is not None:
@@ -335,3 +339,32 @@ def test_mixed_shock_step_and_limiter(K):
     after = s.crkdg_get_state()
     agree = fg == fl_o
     assert l2_rel(after[:, :, agree], lim_o[:, :, agree]) < 1e-6
+
+
+# --- errors against a restricted finer reference ------------------------------
+
+@pytest.mark.parametrize("r,ry,kc,kf", [(2, 2, 2, 2), (3, 2, 2, 1), (1, 1, 3, 0)])
+def test_error_against_restricted_reference(K, r, ry, kc, kf):
+    """L1/L2/Linf of the cell averages against the r x ry block means of a
+    finer state equal the oracle's averaged-error routine on the same data
+    (diagnostic of the error tables of Section 4)"""
+    nx, ny = 37, 13
+    box = (0.0, 2.0, -1.0, 0.5)
+    omc, lmc = meshes(K, 2, nx, ny, "euler", box=box)
+    omf, lmf = meshes(K, 2, r * nx, ry * ny, "euler", box=box)
+    sc, sf = solver(K, lmc, kc, "llf"), solver(K, lmf, kf, "llf")
+    uc = random_state("euler", omc.shape(kc), 5)
+    uf = random_state("euler", omf.shape(kf), 6)
+    sc.crkdg_set_state(uc)
+    sf.crkdg_set_state(uf)
+    for comp in (0, 3):
+        fine = uf[comp, 0].reshape(ry * ny, r * nx)
+        ref = fine.reshape(ny, ry, nx, r).mean(axis=(1, 3)).reshape(-1)
+        want = O.errors_vs_avg(omc, kc, uc, ref, comp=comp)
+        got = sc.crkdg_error_ref(sf, comp)
+        assert np.allclose(got, want, rtol=1e-12, atol=0.0), (got, want)
+    # mismatched meshes are rejected
+    omb, lmb = meshes(K, 2, 2 * nx + 1, ny, "euler", box=box)
+    sb = solver(K, lmb, 1, "llf")
+    with pytest.raises(K.CrkdgError):
+        sc.crkdg_error_ref(sb, 0)
