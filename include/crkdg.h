@@ -87,8 +87,11 @@ typedef struct crkdg_state crkdg_state;
  * (Q^k on rectangles, P^k in 1D; Section 2.1).  flux: CRKDG_FLUX_*.
  * rk_stages selects the paper's tableaus: 1 forward Euler, 2 scheme (eq:2),
  * 3 scheme (eq:3), 4 classical RK4 (Section 2.2 and Section 4).
- * Returns CRKDG_EINVAL for bad sizes/arguments, CRKDG_EUNSUPPORTED for an
- * unsupported combination.  *out is set only on success. */
+ * Returns CRKDG_EINVAL for bad sizes/arguments, including meshes whose
+ * cells x max((k+1)^dim, 4) x 8 bytes reach 4 GiB (one component of one
+ * state must stay below 4 GiB: 59.6 M cells for Q2, 33.5 M for Q3),
+ * CRKDG_EUNSUPPORTED for an unsupported combination.
+ * *out is set only on success. */
 int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out);
 
 /* Replace the tableau by an explicit one (Section 2.1, equation (butcher)):

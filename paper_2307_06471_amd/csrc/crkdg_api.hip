@@ -128,6 +128,15 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   if (k < 0 || k > 3) return CRKDG_EINVAL;
   if (mesh->dim != 1 && mesh->dim != 2) return CRKDG_EINVAL;
   if (mesh->nx < 1 || mesh->ny < 1 || (mesh->dim == 1 && mesh->ny != 1)) return CRKDG_EINVAL;
+  // device addressing uses 32-bit byte offsets within each component slab of
+  // a state (and within the block of FP64 cell averages): cap the mesh so
+  // that 8 bytes x max(modes, components) x cells stays below 4 GiB
+  {
+    const long long ncell = (long long)mesh->nx * mesh->ny;
+    const long long nbm = mesh->dim == 2 ? (long long)(k + 1) * (k + 1) : (long long)(k + 1);
+    const long long span = nbm > 4 ? nbm : 4;
+    if (k >= 0 && k <= 3 && ncell * span * 8 >= (1LL << 32)) return CRKDG_EINVAL;
+  }
   if (!(mesh->x1 > mesh->x0) || (mesh->dim == 2 && !(mesh->y1 > mesh->y0))) return CRKDG_EINVAL;
   if (rk_stages < 1 || rk_stages > 4) return CRKDG_EINVAL;
   if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF) return CRKDG_EINVAL;

@@ -47,30 +47,66 @@ namespace crk {
 // ---------------------------------------------------------------------------
 // state access (layouts in crkdg_internal.hpp)
 // ---------------------------------------------------------------------------
+// State arrays are read and written with buffer instructions: a resource
+// descriptor (scalar registers) per component slab, the array's start within
+// the slab as a scalar offset, and one 32-bit per-lane byte offset shared by
+// every array.  No per-load 64-bit address arithmetic, and the compiler keeps
+// a single offset register live instead of a 64-bit address per array.
+// crkdg_create caps the mesh so that every component slab (and the block of
+// FP64 averages) stays below 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)0xffffffff,
+                                           0x00020000);
+}
+__device__ __forceinline__ const void* byte_add(const void* p, long long bytes) {
+  return (const char*)p + bytes;
+}
+template <class T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <class T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r,
+        (int)voff, (int)soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(
+        __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r,
+        (int)voff, (int)soff, 0);
+}
+
 template <class T, int NC, int NB, int LAY>
 __device__ __forceinline__ void load_state(const void* __restrict__ p, long long N, long long cell,
                                            T (&u)[NC][NB]) {
+  const unsigned o8 = (unsigned)cell * 8u, o4 = (unsigned)cell * 4u;
   if constexpr (LAY == L64) {
-    const double* q = (const double*)p;
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) u[c][b] = (T)q[(long long)(c * NB + b) * N + cell];
-  } else if constexpr (LAY == LMIX) {
-    const double* a = (const double*)p;
-    const float* h = (const float*)(a + (long long)NC * N);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      u[c][0] = (T)a[(long long)c * N + cell];
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 8));
 #pragma unroll
-      for (int b = 1; b < NB; ++b) u[c][b] = (T)h[(long long)(c * (NB - 1) + b - 1) * N + cell];
+      for (int b = 0; b < NB; ++b) u[c][b] = (T)bload<double>(r, o8, (unsigned)(b * N * 8));
+    }
+  } else if constexpr (LAY == LMIX) {
+    const auto ra = rsrc(p);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u[c][0] = (T)bload<double>(ra, o8, (unsigned)(c * N * 8));
+      const auto rh = rsrc(byte_add(p, (long long)NC * N * 8 + (long long)c * (NB - 1) * N * 4));
+#pragma unroll
+      for (int b = 1; b < NB; ++b) u[c][b] = (T)bload<float>(rh, o4, (unsigned)((b - 1) * N * 4));
     }
   } else {
-    const float* q = (const float*)p;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 4));
 #pragma unroll
-      for (int b = 0; b < NB; ++b) u[c][b] = (T)q[(long long)(c * NB + b) * N + cell];
+      for (int b = 0; b < NB; ++b) u[c][b] = (T)bload<float>(r, o4, (unsigned)(b * N * 4));
+    }
   }
 }
 
@@ -78,29 +114,31 @@ __device__ __forceinline__ void load_state(const void* __restrict__ p, long long
 template <class T, int NC, int NB, int LAY>
 __device__ __forceinline__ void store_state(void* __restrict__ p, long long N, long long cell,
                                             const T (&u)[NC][NB], const double* a0 = nullptr) {
+  const unsigned o8 = (unsigned)cell * 8u, o4 = (unsigned)cell * 4u;
   if constexpr (LAY == L64) {
-    double* q = (double*)p;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      q[(long long)(c * NB) * N + cell] = a0 ? a0[c] : (double)u[c][0];
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 8));
+      bstore<double>(a0 ? a0[c] : (double)u[c][0], r, o8, 0u);
 #pragma unroll
-      for (int b = 1; b < NB; ++b) q[(long long)(c * NB + b) * N + cell] = (double)u[c][b];
+      for (int b = 1; b < NB; ++b) bstore<double>((double)u[c][b], r, o8, (unsigned)(b * N * 8));
     }
   } else if constexpr (LAY == LMIX) {
-    double* a = (double*)p;
-    float* h = (float*)(a + (long long)NC * N);
+    const auto ra = rsrc(p);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      a[(long long)c * N + cell] = a0 ? a0[c] : (double)u[c][0];
+      bstore<double>(a0 ? a0[c] : (double)u[c][0], ra, o8, (unsigned)(c * N * 8));
+      const auto rh = rsrc(byte_add(p, (long long)NC * N * 8 + (long long)c * (NB - 1) * N * 4));
 #pragma unroll
-      for (int b = 1; b < NB; ++b) h[(long long)(c * (NB - 1) + b - 1) * N + cell] = (float)u[c][b];
+      for (int b = 1; b < NB; ++b) bstore<float>((float)u[c][b], rh, o4, (unsigned)((b - 1) * N * 4));
     }
   } else {
-    float* q = (float*)p;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 4));
 #pragma unroll
-      for (int b = 0; b < NB; ++b) q[(long long)(c * NB + b) * N + cell] = (float)u[c][b];
+      for (int b = 0; b < NB; ++b) bstore<float>((float)u[c][b], r, o4, (unsigned)(b * N * 4));
+    }
   }
 }
 
@@ -108,9 +146,12 @@ __device__ __forceinline__ void store_state(void* __restrict__ p, long long N, l
 template <int NC, int NB, int LAY>
 __device__ __forceinline__ double load_avg(const void* __restrict__ p, long long N, int c,
                                            long long cell) {
-  if constexpr (LAY == L64) return ((const double*)p)[(long long)(c * NB) * N + cell];
-  else if constexpr (LAY == LMIX) return ((const double*)p)[(long long)c * N + cell];
-  else return (double)((const float*)p)[(long long)(c * NB) * N + cell];
+  if constexpr (LAY == L64)
+    return bload<double>(rsrc(byte_add(p, (long long)c * NB * N * 8)), (unsigned)cell * 8u, 0u);
+  else if constexpr (LAY == LMIX)
+    return bload<double>(rsrc(p), (unsigned)cell * 8u, (unsigned)(c * N * 8));
+  else
+    return (double)bload<float>(rsrc(byte_add(p, (long long)c * NB * N * 4)), (unsigned)cell * 4u, 0u);
 }
 
 // the step kernels' layout follows the compute type: FP64 layout for the

@@ -118,6 +118,14 @@ constexpr double sgn_pow(int m) { return (m % 2) ? -1.0 : 1.0; }  // (-1)^m
 // ---------------------------------------------------------------------------
 // Equations (Section 2.1 conservation law; Euler fluxes of Section 4.1.2)
 // ---------------------------------------------------------------------------
+// reciprocal and square root in the compute precision: IEEE-rounded in FP64
+// (the FP64 method), the hardware instructions (within 1 ulp) in the FP32-bulk
+// form
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <class R>
 struct Euler2 {
   using Real = R;
@@ -126,7 +134,7 @@ struct Euler2 {
   R gm1, gam;
 
   __device__ __forceinline__ void flux2(const R (&q)[4], R (&f)[4], R (&g)[4]) const {
-    const R ir = R(1) / q[0];
+    const R ir = rcp_r(q[0]);
     const R u = q[1] * ir, v = q[2] * ir;
     const R p = gm1 * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
     const R e = q[3] + p;
@@ -136,7 +144,7 @@ struct Euler2 {
   // normal flux f.e_D and spectral radius |u_D| + c
   template <int D>
   __device__ __forceinline__ void nflux(const R (&q)[4], R (&f)[4], R& lam) const {
-    const R ir = R(1) / q[0];
+    const R ir = rcp_r(q[0]);
     const R u = q[1] * ir, v = q[2] * ir;
     const R p = gm1 * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
     const R un = D == 0 ? u : v;
@@ -145,7 +153,7 @@ struct Euler2 {
     f[1] = q[1] * un + (D == 0 ? p : R(0));
     f[2] = q[2] * un + (D == 1 ? p : R(0));
     f[3] = (q[3] + p) * un;
-    lam = fabs(un) + sqrt(gam * p * ir);
+    lam = fabs(un) + sqrt_r(gam * p * ir);
   }
   template <int D>
   __device__ __forceinline__ void nflux_only(const R (&q)[4], R (&f)[4]) const {
