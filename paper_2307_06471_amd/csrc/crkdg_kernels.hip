@@ -41,6 +41,18 @@
 #ifndef FINAL_OCC_F64
 #define FINAL_OCC_F64 1
 #endif
+#ifndef FINAL_TX_F32
+#define FINAL_TX_F32 64
+#endif
+#ifndef FINAL_TY_F32
+#define FINAL_TY_F32 4
+#endif
+#ifndef FINAL_TX_F64
+#define FINAL_TX_F64 64
+#endif
+#ifndef FINAL_TY_F64
+#define FINAL_TY_F64 4
+#endif
 
 namespace crk {
 
@@ -383,200 +395,291 @@ __device__ __forceinline__ void neighbour_trace(const Geo& g, const PhysDev& ph,
 }
 
 // ---------------------------------------------------------------------------
-// K2 (2D): final stage on a 64x4 tile
+// K2 (2D): final stage on a tile of TX x TY cells
 // ---------------------------------------------------------------------------
-constexpr int BX = 64, BY = 4;
+// Tile shape per compute type (measured on the 4096 x 1024 Q2 shock workload:
+// 64 x 4 beats 32 x 8 and 16 x 16, whose shorter rows coalesce worse).
+template <class R>
+struct FinalTile {
+  static constexpr int TX = sizeof(R) == 4 ? FINAL_TX_F32 : FINAL_TX_F64;
+  static constexpr int TY = sizeof(R) == 4 ? FINAL_TY_F32 : FINAL_TY_F64;
+};
 
-template <class R, int NV>
+// the exterior trace across side `side` (0 left, 1 right, 2 bottom, 3 top) of
+// cell (ci, cj): the neighbour's facing trace, or the boundary ghost (Section
+// 3.4: boundary data enter only here).  Uses the same trace functions as the
+// owner of the neighbour cell, so both tiles sharing a face see identical
+// traces and compute identical fluxes.
+template <class EQ, int K>
+__device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, const BCDev& bc,
+                                           const void* __restrict__ S, int side, int ci, int cj,
+                                           double tb, typename EQ::Real (&out)[EQ::NC][K + 1]) {
+  using R = typename EQ::Real;
+  constexpr int NC = EQ::NC, Q = K + 1, NB = Q * Q;
+  int ni = ci + (side == 0 ? -1 : side == 1 ? 1 : 0);
+  int nj = cj + (side == 2 ? -1 : side == 3 ? 1 : 0);
+  int face = side ^ 1;  // the neighbour's face: left side <- its right trace, ...
+  if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
+    const int type = bc.type[side];
+    if (type == CRKDG_BC_DIRICHLET) {
+      constexpr GTab<Q> T = Tab<Q>::t;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        double q[4];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = bc.state[side][c];
+        if constexpr (!EQ::EULER) {
+          // time-dependent inflow data (advection): sin(pi(x - a t)) sin(pi(y - b t))
+          // at the stage time
+          if (bc.exact == CRKDG_IC_ADV_SIN) {
+            const double xc = g.x0 + (ci + 0.5) * g.dx, yc = g.y0 + (cj + 0.5) * g.dy;
+            const double x = side < 2 ? xc + (side == 0 ? -0.5 : 0.5) * g.dx : xc + 0.5 * g.dx * T.X[p];
+            const double y = side < 2 ? yc + 0.5 * g.dy * T.X[p] : yc + (side == 2 ? -0.5 : 0.5) * g.dy;
+            q[0] = sin(M_PI * (x - ph.ax * tb)) * sin(M_PI * (y - ph.ay * tb));
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c][p] = (R)q[c];
+      }
+      return;
+    }
+    if (type == CRKDG_BC_TRANSMISSIVE) {
+      ni = ci;  // the exterior trace is the cell's own trace on this face
+      nj = cj;
+      face = side;
+    } else {  // periodic
+      if (ni < 0) ni += g.nx;
+      if (ni >= g.nx) ni -= g.nx;
+      if (nj < 0) nj += g.ny;
+      if (nj >= g.ny) nj -= g.ny;
+    }
+  }
+  R U[NC][NB];
+  load_state<R, NC, NB, StepLayout<EQ>::value>(S, g.N, (long long)nj * g.nx + ni, U);
+  switch (face) {
+    case 0: trace_x<-1, EQ, K, R>(U, out); break;
+    case 1: trace_x<+1, EQ, K, R>(U, out); break;
+    case 2: trace_y<-1, EQ, K, R>(U, out); break;
+    default: trace_y<+1, EQ, K, R>(U, out); break;
+  }
+}
+
+// face point f of a TX x TY tile: x faces first (TX + 1 per row, TY rows, Q
+// points each), then y faces (TX per row, TY + 1 rows); column index fastest,
+// quadrature point slowest.  Returns true for a y face.
+template <int TX, int TY>
+__device__ __forceinline__ bool face_point(int f, int nxp, int& fx, int& fy, int& p) {
+  const bool dy = f >= nxp;
+  const int e = dy ? f - nxp : f;
+  const int w = dy ? TX : TX + 1, h = dy ? TY + 1 : TY;
+  fx = e % w;
+  const int r = e / w;
+  fy = r % h;
+  p = r / h;
+  return dy;
+}
+
+template <class R, int NV, int TX, int TY>
 struct FinalSmem {
-  // traces of the current stage (R): right-face traces [v][ty][tx+1] with the
-  // left halo in column 0; top-face traces [v][ty+1][tx] with the bottom halo
-  // in row 0; the right/top neighbours' traces for the tile's edge faces
-  static constexpr int NR = NV * BY * (BX + 1), NT = NV * (BY + 1) * BX;
-  static constexpr int NLH = NV * BY, NBH = NV * BX;
-  static constexpr size_t TRACE_BYTES = sizeof(R) * (NR + NT + NLH + NBH);
-  // after the stage loop the same bytes hold every cell's left/bottom G (FP64)
-  static constexpr size_t GEX_BYTES = sizeof(double) * (2 * NV * BY * BX);
-  static constexpr size_t UNION_BYTES = TRACE_BYTES > GEX_BYTES ? TRACE_BYTES : GEX_BYTES;
-  // edge-face G of the tile's last column / row (FP64), alive over all stages
-  static constexpr size_t EDGE_BYTES = sizeof(double) * (NV * BY + NV * BX);
-  static constexpr size_t BYTES = UNION_BYTES + EDGE_BYTES;
+  // traces of the current stage (R), per face row/column of the tile:
+  //   tR[v][y][x]: right trace of cell x-1 (x = 0: the left halo cell's)
+  //   tL[v][y][x]: left trace of cell x   (x = nx_tile: the right halo's)
+  //   tT[v][y][x]: top trace of cell row y-1 (y = 0: the bottom halo's)
+  //   tB[v][y][x]: bottom trace of row y   (y = ny_tile: the top halo's)
+  static constexpr int NXF = NV * TY * (TX + 1), NYF = NV * (TY + 1) * TX;
+  static constexpr size_t TRACE_BYTES = sizeof(R) * 2 * (NXF + NYF);
+  // after the stage loop the same bytes hold the face sums G (FP64)
+  static constexpr size_t G_BYTES = sizeof(double) * (NXF + NYF);
+  static constexpr size_t BYTES = TRACE_BYTES > G_BYTES ? TRACE_BYTES : G_BYTES;
 };
 
 template <class EQ, int K>
-__global__ __launch_bounds__(BX* BY, (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
-                                                                      FinalArgs a) {
+__global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typename EQ::Real>::TY,
+                             (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
+                                                                 FinalArgs a) {
   using R = typename EQ::Real;
+  constexpr int TX = FinalTile<R>::TX, TY = FinalTile<R>::TY, NT = TX * TY;
   constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q, LAY = StepLayout<EQ>::value;
-  using SM = FinalSmem<R, NV>;
+  using SM = FinalSmem<R, NV, TX, TY>;
+  // face points of the tile: x faces (TX + 1 per row, TY rows), then y faces
+  constexpr int NXP = Q * (TX + 1) * TY, NFP = NXP + Q * TX * (TY + 1);
+  constexpr int NPASS = (NFP + NT - 1) / NT;
+  constexpr int NHALO = 2 * TY + 2 * TX;
+  static_assert(NHALO <= NT, "one lane per halo cell");
   __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
-  R(*sR)[BY][BX + 1] = reinterpret_cast<R(*)[BY][BX + 1]>(smem);
-  R(*sT)[BY + 1][BX] = reinterpret_cast<R(*)[BY + 1][BX]>(smem + sizeof(R) * SM::NR);
-  R(*sLh)[BY] = reinterpret_cast<R(*)[BY]>(smem + sizeof(R) * (SM::NR + SM::NT));
-  R(*sBh)[BX] = reinterpret_cast<R(*)[BX]>(smem + sizeof(R) * (SM::NR + SM::NT + SM::NLH));
-  double(*gx)[BY][BX] = reinterpret_cast<double(*)[BY][BX]>(smem);
-  double(*gy)[BY][BX] = reinterpret_cast<double(*)[BY][BX]>(smem + sizeof(double) * NV * BY * BX);
-  double(*gR)[BY] = reinterpret_cast<double(*)[BY]>(smem + SM::UNION_BYTES);
-  double(*gT)[BX] = reinterpret_cast<double(*)[BX]>(smem + SM::UNION_BYTES + sizeof(double) * NV * BY);
+  R(*tR)[TY][TX + 1] = reinterpret_cast<R(*)[TY][TX + 1]>(smem);
+  R(*tL)[TY][TX + 1] = reinterpret_cast<R(*)[TY][TX + 1]>(smem + sizeof(R) * SM::NXF);
+  R(*tT)[TY + 1][TX] = reinterpret_cast<R(*)[TY + 1][TX]>(smem + sizeof(R) * 2 * SM::NXF);
+  R(*tB)[TY + 1][TX] = reinterpret_cast<R(*)[TY + 1][TX]>(smem + sizeof(R) * (2 * SM::NXF + SM::NYF));
+  double(*gx)[TY][TX + 1] = reinterpret_cast<double(*)[TY][TX + 1]>(smem);
+  double(*gy)[TY + 1][TX] = reinterpret_cast<double(*)[TY + 1][TX]>(smem + sizeof(double) * SM::NXF);
+  // flat views: component c of face point e at c * CSX + e (x) / c * CSY + e (y)
+  constexpr int CSX = Q * TY * (TX + 1), CSY = Q * (TY + 1) * TX;
+  const R* tRf = &tR[0][0][0];
+  const R* tLf = &tL[0][0][0];
+  const R* tTf = &tT[0][0][0];
+  const R* tBf = &tB[0][0][0];
+  double* gxf = &gx[0][0][0];
+  double* gyf = &gy[0][0][0];
 
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty;
-  const bool active = i < g.nx && j < g.ny;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int nax = min(TX, g.nx - i0), nay = min(TY, g.ny - j0);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool active = tx < nax && ty < nay;
+  const bool full = nax == TX && nay == TY;
   const long long cell = (long long)j * g.nx + i;
-  const bool last_col = active && (tx == BX - 1 || i == g.nx - 1);
-  const bool last_row = active && (ty == BY - 1 || j == g.ny - 1);
   const EQ eq = make_eq<EQ>(ph);
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
 
+  // this lane's halo cell: left column, right column, bottom row, top row
+  int hside = -1, hci = 0, hcj = 0, hslot = 0;
+  if (tid < TY) {
+    hside = 0; hci = i0; hcj = j0 + tid; hslot = tid;
+    if (tid >= nay) hside = -1;
+  } else if (tid < 2 * TY) {
+    hside = 1; hci = i0 + nax - 1; hcj = j0 + tid - TY; hslot = tid - TY;
+    if (tid - TY >= nay) hside = -1;
+  } else if (tid < 2 * TY + TX) {
+    hside = 2; hci = i0 + tid - 2 * TY; hcj = j0; hslot = tid - 2 * TY;
+    if (tid - 2 * TY >= nax) hside = -1;
+  } else if (tid < NHALO) {
+    hside = 3; hci = i0 + tid - 2 * TY - TX; hcj = j0 + nay - 1; hslot = tid - 2 * TY - TX;
+    if (tid - 2 * TY - TX >= nax) hside = -1;
+  }
+
   R acc[NC][NB];
-  double a0[NC];         // cell averages, FP64
-  double GL[NC][Q], GB[NC][Q];
+  double a0[NC];  // cell averages, FP64
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[c][b] = R(0);
     a0[c] = 0.0;
-#pragma unroll
-    for (int p = 0; p < Q; ++p) GL[c][p] = GB[c][p] = 0.0;
   }
+  // u^n is usually also the first final-stage state (u^(1) = u^n): then it is
+  // read once, in the stage loop
+  const bool base_is_st0 = a.base != nullptr && a.ns > 0 && a.base == a.st[0];
   if (active && a.base) {
-    load_state<R, NC, NB, LAY>(a.base, g.N, cell, acc);
+    if (!base_is_st0) load_state<R, NC, NB, LAY>(a.base, g.N, cell, acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c) a0[c] = load_avg<NC, NB, LAY>(a.base, g.N, c, cell);
   }
-  if (last_col)
-    for (int v = 0; v < NV; ++v) gR[v][ty] = 0.0;
-  if (last_row)
-    for (int v = 0; v < NV; ++v) gT[v][tx] = 0.0;
+  // FP64 stage-weighted face flux sums G = sum_i b_i F^(i) (equation (g)) of
+  // the face points this lane evaluates
+  double Gp[NPASS][NC];
+#pragma unroll
+  for (int k = 0; k < NPASS; ++k)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Gp[k][c] = 0.0;
 
 #pragma unroll 1
   for (int s = 0; s < a.ns; ++s) {
     const void* __restrict__ S = a.st[s];
     const double w = a.w[s];
-    R tL[NC][Q], tB[NC][Q];
     if (active) {
-      {
-        R U[NC][NB];
-        load_state<R, NC, NB, LAY>(S, g.N, cell, U);
-        const R vs = R(0.5 * dt * w);
-        volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
-        R t[NC][Q];
-        trace_x<+1, EQ, K, R>(U, t);
+      R U[NC][NB];
+      load_state<R, NC, NB, LAY>(S, g.N, cell, U);
+      if (s == 0 && base_is_st0) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int p = 0; p < Q; ++p) sR[c * Q + p][ty][tx + 1] = t[c][p];
-        trace_y<+1, EQ, K, R>(U, t);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int p = 0; p < Q; ++p) sT[c * Q + p][ty + 1][tx] = t[c][p];
-        trace_x<-1, EQ, K, R>(U, tL);
-        trace_y<-1, EQ, K, R>(U, tB);
+          for (int b = 0; b < NB; ++b) acc[c][b] = U[c][b];
       }
-      if (tx == 0) {
-        R h[NC][Q];
-        neighbour_trace<EQ, K, 0>(g, ph, bc, S, i, j, a.tst[s], tL, h);
+      const R vs = R(0.5 * dt * w);
+      volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
+      R t[NC][Q];
+      trace_x<+1, EQ, K, R>(U, t);
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int p = 0; p < Q; ++p) sR[c * Q + p][ty][0] = h[c][p];
-      }
-      if (ty == 0) {
-        R h[NC][Q];
-        neighbour_trace<EQ, K, 2>(g, ph, bc, S, i, j, a.tst[s], tB, h);
+        for (int p = 0; p < Q; ++p) tR[c * Q + p][ty][tx + 1] = t[c][p];
+      trace_x<-1, EQ, K, R>(U, t);
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int p = 0; p < Q; ++p) sT[c * Q + p][0][tx] = h[c][p];
-      }
+        for (int p = 0; p < Q; ++p) tL[c * Q + p][ty][tx] = t[c][p];
+      trace_y<+1, EQ, K, R>(U, t);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) tT[c * Q + p][ty + 1][tx] = t[c][p];
+      trace_y<-1, EQ, K, R>(U, t);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) tB[c * Q + p][ty][tx] = t[c][p];
+    }
+    if (hside >= 0) {
+      R h[NC][Q];
+      halo_trace<EQ, K>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          const int v = c * Q + p;
+          if (hside == 0) tR[v][hslot][0] = h[c][p];
+          else if (hside == 1) tL[v][hslot][nax] = h[c][p];
+          else if (hside == 2) tT[v][0][hslot] = h[c][p];
+          else tB[v][nay][hslot] = h[c][p];
+        }
     }
     __syncthreads();
-    // the right / top neighbours' traces for the edge faces: the own trace is
-    // in LDS now, needed by the transmissive ghost rule
-    if (last_col) {
-      R own[NC][Q], h[NC][Q];
+    // every face point of the tile once: qL from the cell below / to the
+    // left, qR from the cell above / to the right.  With the column index
+    // fastest, the face point's index is its offset in the trace arrays, and
+    // consecutive lanes read consecutive LDS words (no bank conflicts).
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int p = 0; p < Q; ++p) own[c][p] = sR[c * Q + p][ty][tx + 1];
-      neighbour_trace<EQ, K, 1>(g, ph, bc, S, i, j, a.tst[s], own, h);
-#pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        R qa[NC], qb[NC], F[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          qa[c] = own[c][p];
-          qb[c] = h[c][p];
-        }
-        eq.template num_flux<0>(qa, qb, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) gR[c * Q + p][ty] += w * (double)F[c];
+    for (int k = 0; k < NPASS; ++k) {
+      const int f = tid + k * NT;
+      if (f >= NFP) break;
+      const bool dy = f >= NXP;
+      const int e = dy ? f - NXP : f;
+      bool valid = full;
+      if (!full) {
+        int fx, fy, p;
+        face_point<TX, TY>(f, NXP, fx, fy, p);
+        valid = dy ? (fx < nax && fy <= nay) : (fx <= nax && fy < nay);
       }
-    }
-    if (last_row) {
-      R own[NC][Q], h[NC][Q];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int p = 0; p < Q; ++p) own[c][p] = sT[c * Q + p][ty + 1][tx];
-      neighbour_trace<EQ, K, 3>(g, ph, bc, S, i, j, a.tst[s], own, h);
-#pragma unroll
-      for (int p = 0; p < Q; ++p) {
+      if (valid) {
+        const R* A = dy ? tTf : tRf;
+        const R* B = dy ? tBf : tLf;
+        const int cs = dy ? CSY : CSX;
         R qa[NC], qb[NC], F[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          qa[c] = own[c][p];
-          qb[c] = h[c][p];
+          qa[c] = A[c * cs + e];
+          qb[c] = B[c * cs + e];
         }
-        eq.template num_flux<1>(qa, qb, F);
+        eq.num_flux_d(qa, qb, dy, F);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) gT[c * Q + p][tx] += w * (double)F[c];
-      }
-    }
-    if (active) {
-#pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        R qa[NC], qb[NC], F[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          qa[c] = sR[c * Q + p][ty][tx];
-          qb[c] = tL[c][p];
-        }
-        eq.template num_flux<0>(qa, qb, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) GL[c][p] += w * (double)F[c];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          qa[c] = sT[c * Q + p][ty][tx];
-          qb[c] = tB[c][p];
-        }
-        eq.template num_flux<1>(qa, qb, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) GB[c][p] += w * (double)F[c];
+        for (int c = 0; c < NC; ++c) Gp[k][c] += w * (double)F[c];
       }
     }
     __syncthreads();
   }
-  // a cell's right face is its right neighbour's left face: share G
-  if (active) {
+  // face sums to LDS (over the traces), then each cell reads its four faces
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+  for (int k = 0; k < NPASS; ++k) {
+    const int f = tid + k * NT;
+    if (f >= NFP) break;
+    const bool dy = f >= NXP;
+    const int e = dy ? f - NXP : f;
+    double* G = dy ? gyf : gxf;
+    const int cs = dy ? CSY : CSX;
 #pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        gx[c * Q + p][ty][tx] = GL[c][p];
-        gy[c * Q + p][ty][tx] = GB[c][p];
-      }
+    for (int c = 0; c < NC; ++c) G[c * cs + e] = Gp[k][c];
   }
   __syncthreads();
   if (!active) return;
-  double GR[NC][Q], GT[NC][Q];
+  double GL[NC][Q], GR[NC][Q], GB[NC][Q], GT[NC][Q];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-      GR[c][p] = last_col ? gR[c * Q + p][ty] : gx[c * Q + p][ty][tx + 1];
-      GT[c][p] = last_row ? gT[c * Q + p][tx] : gy[c * Q + p][ty + 1][tx];
+      GL[c][p] = gx[c * Q + p][ty][tx];
+      GR[c][p] = gx[c * Q + p][ty][tx + 1];
+      GB[c][p] = gy[c * Q + p][ty][tx];
+      GT[c][p] = gy[c * Q + p][ty + 1][tx];
     }
   // cell averages: FP64 update from the FP64 face sums (equation (avg))
   {
@@ -1029,8 +1132,9 @@ __device__ void euler_eigvec(double gamma, const double* q, int d, double* L, do
   const double q2 = u * u + v * v;
   const double p = (gamma - 1.0) * (q[3] - 0.5 * q[0] * q2);
   const double c = sqrt(gamma * p * ir);
+  const double ic = 1.0 / c;  // one division; the others become products
   const double H = (q[3] + p) * ir;
-  const double b1 = (gamma - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  const double b1 = (gamma - 1.0) * ic * ic, b2 = 0.5 * b1 * q2;
   const double un = d == 0 ? u : v, ut = d == 0 ? v : u;
   // in the rotated frame (normal, tangential); map back to (x, y) columns
   const int in = d == 0 ? 1 : 2, it = d == 0 ? 2 : 1;
@@ -1041,10 +1145,10 @@ __device__ void euler_eigvec(double gamma, const double* q, int d, double* L, do
   Rl[0][2] = 0.0; Rl[in][2] = 0.0;    Rl[it][2] = 1.0; Rl[3][2] = ut;
   Rl[0][3] = 1.0; Rl[in][3] = un + c; Rl[it][3] = ut; Rl[3][3] = H + un * c;
   double Ll[4][4] = {};
-  Ll[0][0] = 0.5 * (b2 + un / c); Ll[0][in] = -0.5 * (b1 * un + 1.0 / c); Ll[0][it] = -0.5 * b1 * ut; Ll[0][3] = 0.5 * b1;
-  Ll[1][0] = 1.0 - b2;            Ll[1][in] = b1 * un;                  Ll[1][it] = b1 * ut;        Ll[1][3] = -b1;
-  Ll[2][0] = -ut;                 Ll[2][in] = 0.0;                      Ll[2][it] = 1.0;            Ll[2][3] = 0.0;
-  Ll[3][0] = 0.5 * (b2 - un / c); Ll[3][in] = -0.5 * (b1 * un - 1.0 / c); Ll[3][it] = -0.5 * b1 * ut; Ll[3][3] = 0.5 * b1;
+  Ll[0][0] = 0.5 * (b2 + un * ic); Ll[0][in] = -0.5 * (b1 * un + ic); Ll[0][it] = -0.5 * b1 * ut; Ll[0][3] = 0.5 * b1;
+  Ll[1][0] = 1.0 - b2;             Ll[1][in] = b1 * un;               Ll[1][it] = b1 * ut;        Ll[1][3] = -b1;
+  Ll[2][0] = -ut;                  Ll[2][in] = 0.0;                   Ll[2][it] = 1.0;            Ll[2][3] = 0.0;
+  Ll[3][0] = 0.5 * (b2 - un * ic); Ll[3][in] = -0.5 * (b1 * un - ic); Ll[3][it] = -0.5 * b1 * ut; Ll[3][3] = 0.5 * b1;
   for (int r = 0; r < 4; ++r)
     for (int s = 0; s < 4; ++s) {
       L[r * 4 + s] = Ll[r][s];
@@ -1055,47 +1159,56 @@ __device__ void euler_eigvec(double gamma, const double* q, int d, double* L, do
 // density and pressure positive at the operator's volume and face points
 template <int K>
 __device__ bool physical_points(double gamma, const double (&U)[4][(K + 1) * (K + 1)]) {
+  // rho > 0 and p > 0 at every volume and face Gauss point.  With rho > 0 and
+  // gamma > 1, p > 0 is the same as rho E - |m|^2 / 2 > 0, which needs no
+  // division; the points are visited without early exit (no divergence).
+  (void)gamma;
   constexpr int Q = K + 1;
-  Euler2<double> eq;
-  eq.gam = gamma;
-  eq.gm1 = gamma - 1.0;
-  auto ok = [&](const double* q) {
-    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
-    return q[0] > 0.0 && p > 0.0;
-  };
-  // volume points, line by line (x fastest in the reference square)
   constexpr GTab<Q> T = Tab<Q>::t;
+  bool ok = true;
+  auto check = [&](double r, double mx, double my, double E) {
+    ok = ok && (r > 0.0) && (r * E - 0.5 * (mx * mx + my * my) > 0.0);
+  };
+  // volume points, sum-factorised: first the eta lines, then the xi points
+#pragma unroll
   for (int a = 0; a < Q; ++a) {
+    double t[4][Q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int n = 0; n < Q; ++n) {
+        double v = U[c][Q * n];
+#pragma unroll
+        for (int m = 1; m < Q; ++m) v += U[c][m + Q * n] * T.P[m][a];
+        t[c][n] = v;
+      }
+#pragma unroll
     for (int b = 0; b < Q; ++b) {
       double q[4];
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
-        double s = 0.0;
-        for (int n = 0; n < Q; ++n) {
-          double t = 0.0;
-          for (int m = 0; m < Q; ++m) t += U[c][m + Q * n] * T.P[m][a];
-          s += t * T.P[n][b];
-        }
-        q[c] = s;
+        double v = t[c][0];
+#pragma unroll
+        for (int n = 1; n < Q; ++n) v += t[c][n] * T.P[n][b];
+        q[c] = v;
       }
-      if (!ok(q)) return false;
+      check(q[0], q[1], q[2], q[3]);
     }
   }
   double tr[4][Q];
-  auto face_ok = [&]() {
-    for (int p = 0; p < Q; ++p) {
-      double q[4] = {tr[0][p], tr[1][p], tr[2][p], tr[3][p]};
-      if (!ok(q)) return false;
-    }
-    return true;
+  auto face = [&]() {
+#pragma unroll
+    for (int p = 0; p < Q; ++p) check(tr[0][p], tr[1][p], tr[2][p], tr[3][p]);
   };
   trace_x<+1, Euler2<double>, K, double>(U, tr);
-  if (!face_ok()) return false;
+  face();
   trace_x<-1, Euler2<double>, K, double>(U, tr);
-  if (!face_ok()) return false;
+  face();
   trace_y<+1, Euler2<double>, K, double>(U, tr);
-  if (!face_ok()) return false;
+  face();
   trace_y<-1, Euler2<double>, K, double>(U, tr);
-  return face_ok();
+  face();
+  return ok;
 }
 
 struct LimitArgs {
@@ -1390,8 +1503,9 @@ struct RunFinal {
   static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const FinalArgs& a,
                         hipStream_t s) {
     if constexpr (EQ::DIM == 2) {
-      dim3 grid(nblk(g.nx, BX), nblk(g.ny, BY));
-      hipLaunchKernelGGL((k_final2<EQ, K>), grid, dim3(BX, BY), 0, s, ph, g, bc, a);
+      using T = FinalTile<typename EQ::Real>;
+      dim3 grid(nblk(g.nx, T::TX), nblk(g.ny, T::TY));
+      hipLaunchKernelGGL((k_final2<EQ, K>), grid, dim3(T::TX * T::TY), 0, s, ph, g, bc, a);
     } else {
       hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
     }

@@ -172,6 +172,28 @@ struct Euler2 {
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[c] = R(0.5) * (fL[c] + fR[c] - a * (qR[c] - qL[c]));
   }
+  // the same with the direction chosen at run time (d = 0: x, 1: y), no branch
+  __device__ __forceinline__ void nflux_d(const R (&q)[4], bool dy, R (&f)[4], R& lam) const {
+    const R ir = rcp_r(q[0]);
+    const R u = q[1] * ir, v = q[2] * ir;
+    const R p = gm1 * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
+    const R un = dy ? v : u;
+    const R px = dy ? R(0) : p, py = dy ? p : R(0);
+    f[0] = dy ? q[2] : q[1];
+    f[1] = q[1] * un + px;
+    f[2] = q[2] * un + py;
+    f[3] = (q[3] + p) * un;
+    lam = fabs(un) + sqrt_r(gam * p * ir);
+  }
+  __device__ __forceinline__ void num_flux_d(const R (&qL)[4], const R (&qR)[4], bool dy,
+                                             R (&F)[4]) const {
+    R fL[4], fR[4], lL, lR;
+    nflux_d(qL, dy, fL, lL);
+    nflux_d(qR, dy, fR, lR);
+    const R a = lL > lR ? lL : lR;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[c] = R(0.5) * (fL[c] + fR[c] - a * (qR[c] - qL[c]));
+  }
 };
 
 template <class R, int DIM_>
@@ -193,6 +215,14 @@ struct Adv {
   template <int D>
   __device__ __forceinline__ void num_flux(const R (&qL)[1], const R (&qR)[1], R (&F)[1]) const {
     const R a = D == 0 ? ax : ay;
+    if (upwind)
+      F[0] = a >= R(0) ? a * qL[0] : a * qR[0];
+    else
+      F[0] = R(0.5) * (a * qL[0] + a * qR[0] - fabs(a) * (qR[0] - qL[0]));
+  }
+  __device__ __forceinline__ void num_flux_d(const R (&qL)[1], const R (&qR)[1], bool dy,
+                                             R (&F)[1]) const {
+    const R a = dy ? ay : ax;
     if (upwind)
       F[0] = a >= R(0) ? a * qL[0] : a * qR[0];
     else
