@@ -154,10 +154,13 @@ int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagge
 
 /* Learned troubled-cell indicator (not part of the paper's method): the
  * same final-stage limiter, with the TVB troubled-cell test replaced by a
- * 12 -> 32 -> 32 -> 1 perceptron (tanh, tanh, logistic output; parameters
+ * 12 -> 32 -> 32 -> 1 perceptron (ReLU, ReLU, logistic output; parameters
  * packed W1[32][12], b1[32], W2[32][32], b2[32], w3[32], b3 as 1505 device
- * floats) on 12 stencil features.  p = sigmoid(logit): p >= tau_hi troubled,
- * p <= tau_lo smooth, otherwise the FP64 TVB test decides (flag bit 8).
+ * floats) on 12 stencil features, evaluated at inference precision: the
+ * features, W1, W2 and the first hidden layer rounded to bfloat16 (nearest
+ * even) on the matrix cores with FP32 accumulation, the rest FP32.
+ * p = sigmoid(logit): p >= tau_hi troubled, p <= tau_lo smooth, otherwise
+ * the FP64 TVB test decides (flag bit 8); tau_lo <= tau_hi.
  * Reconstruction and positivity check as in crkdg_limit.  counts_host
  * (nullable, syncs): [0] flagged cells, [1] cells decided by the fallback.
  * 2D Euler only (CRKDG_EUNSUPPORTED otherwise). */
@@ -170,7 +173,8 @@ int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float ta
  * a/s, at/s, (dp - dm)/s.  2D Euler only. */
 int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev);
 /* MLP kernels on device arrays (stream = hipStream_t or NULL):
- * forward logits of B samples X[B][12]; the batch-mean weighted BCE loss
+ * forward logits of B samples X[B][12] at the limiter's inference precision;
+ * the batch-mean weighted BCE loss (FP32 forward and backward)
  * pos_weight*y*softplus(-z) + (1-y)*softplus(z) and its gradient (1505
  * floats; loss: 1 device float or NULL) with a deterministic two-level
  * reduction in caller-owned work memory of crkdg_mlp_work_bytes(B); one

@@ -10,6 +10,7 @@
 #include "crkdg_oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1030,16 +1031,18 @@ int or_mlp_features(const or_mesh* m, int k, double M, const double* u, double* 
 #define OB3 (OW3 + H2)
 #define NPAR (OB3 + 1)
 
+static double relu(double v) { return v > 0.0 ? v : 0.0; }
+
 static double mlp_one(const double* P, const double* x, double* h1, double* h2) {
   for (int o = 0; o < H1; ++o) {
     double s = P[OB1 + o];
     for (int i = 0; i < NF; ++i) s += P[OW1 + o * NF + i] * x[i];
-    h1[o] = tanh(s);
+    h1[o] = relu(s);
   }
   for (int o = 0; o < H2; ++o) {
     double s = P[OB2 + o];
     for (int i = 0; i < H1; ++i) s += P[OW2 + o * H1 + i] * h1[i];
-    h2[o] = tanh(s);
+    h2[o] = relu(s);
   }
   double z = P[OB3];
   for (int i = 0; i < H2; ++i) z += P[OW3 + i] * h2[i];
@@ -1049,6 +1052,47 @@ static double mlp_one(const double* P, const double* x, double* h1, double* h2) 
 int or_mlp_forward(const double* params, const double* X, int B, double* logits) {
   double h1[H1], h2[H2];
   for (int n = 0; n < B; ++n) logits[n] = mlp_one(params, X + (size_t)n * NF, h1, h2);
+  return 0;
+}
+
+/* round a binary32 value to bfloat16 (8 significand bits), round to nearest,
+ * ties to even, on the bit pattern; NaN stays NaN */
+float or_bf16(float f) {
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return f;
+  const uint32_t lsb = (b >> 16) & 1u;
+  b += 0x7fffu + lsb;
+  b &= 0xffff0000u;
+  float r;
+  memcpy(&r, &b, 4);
+  return r;
+}
+
+/* the forward pass at inference precision: features, W1, W2 and the first
+ * hidden layer rounded to bfloat16 (each sum of exact products then rounded
+ * to binary32 before the bias is added, as a binary32 accumulator holds it);
+ * second hidden layer, w3 and the output in binary64 */
+int or_mlp_infer(const double* P, const double* X, int B, double* logits) {
+  for (int n = 0; n < B; ++n) {
+    const double* x = X + (size_t)n * NF;
+    double xb[NF], h1[H1], h2[H2];
+    for (int i = 0; i < NF; ++i) xb[i] = or_bf16((float)x[i]);
+    for (int o = 0; o < H1; ++o) {
+      double s = 0.0;
+      for (int i = 0; i < NF; ++i) s += (double)or_bf16((float)P[OW1 + o * NF + i]) * xb[i];
+      const float v = (float)s + (float)P[OB1 + o];
+      h1[o] = or_bf16(v > 0.0f ? v : 0.0f);
+    }
+    for (int o = 0; o < H2; ++o) {
+      double s = 0.0;
+      for (int i = 0; i < H1; ++i) s += (double)or_bf16((float)P[OW2 + o * H1 + i]) * h1[i];
+      h2[o] = relu((double)((float)s + (float)P[OB2 + o]));
+    }
+    double z = P[OB3];
+    for (int i = 0; i < H2; ++i) z += P[OW3 + i] * h2[i];
+    logits[n] = z;
+  }
   return 0;
 }
 
@@ -1072,7 +1116,7 @@ double or_mlp_loss_grad(const double* P, const double* X, const uint8_t* y, int 
     grad[OB3] += dz;
     for (int i = 0; i < H2; ++i) {
       grad[OW3 + i] += dz * h2[i];
-      d2[i] = dz * P[OW3 + i] * (1.0 - h2[i] * h2[i]);
+      d2[i] = h2[i] > 0.0 ? dz * P[OW3 + i] : 0.0;
     }
     for (int o = 0; o < H2; ++o) {
       grad[OB2 + o] += d2[o];
@@ -1081,7 +1125,7 @@ double or_mlp_loss_grad(const double* P, const double* X, const uint8_t* y, int 
     for (int i = 0; i < H1; ++i) {
       double s = 0.0;
       for (int o = 0; o < H2; ++o) s += P[OW2 + o * H1 + i] * d2[o];
-      d1[i] = s * (1.0 - h1[i] * h1[i]);
+      d1[i] = h1[i] > 0.0 ? s : 0.0;
     }
     for (int o = 0; o < H1; ++o) {
       grad[OB1 + o] += d1[o];

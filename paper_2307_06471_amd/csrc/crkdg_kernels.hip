@@ -1213,55 +1213,61 @@ __device__ bool physical_points(double gamma, const double (&U)[4][(K + 1) * (K 
 
 struct LimitArgs {
   double M;
-  int mlp;              // 0: TVB test decides; 1: learned indicator with TVB fallback band
-  const float* P;       // MLP parameters (device)
-  float tau_lo, tau_hi; // p <= tau_lo: smooth, p >= tau_hi: troubled, else TVB decides
+  const float* P;       // MLP parameters (device; learned-indicator mode)
+  float z_lo, z_hi;     // logit thresholds: z <= z_lo smooth, z >= z_hi troubled,
+                        // else the TVB test decides
 };
 
-template <class EQ, int K, int LAY>
+// MLP = false: the TVB minmod test decides for every cell.  MLP = true
+// (2D Euler only): the learned indicator decides outside its uncertainty band
+// and the FP64 TVB test inside it; the network runs once per wavefront on
+// the matrix cores, so every lane takes part even past the last cell.
+template <class EQ, int K, int LAY, bool MLP>
 __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
                                                void* __restrict__ u,
                                                uint8_t* __restrict__ flags,
                                                unsigned long long* __restrict__ counters) {
   constexpr int NC = EQ::NC, DIM = EQ::DIM, Q = K + 1, NB = Sizes<K, DIM>::NB;
+  constexpr bool USE_MLP = MLP && EQ::EULER && DIM == 2 && K >= 1;
   __shared__ unsigned int cnt[3];
   if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
   __syncthreads();
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool in = cell < g.N;
   const double M = la.M;
   uint8_t flag = 0;
   bool bad = false;
-  if (cell < g.N) {
-    const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
-    double U[NC][NB];
+  const int i = in ? (int)(cell % g.nx) : 0, j = in ? (int)(cell / g.nx) : 0;
+  double U[NC][NB];
+  double avg[NC];
+  double dp[2][NC], dm[2][NC];
+  // neighbour averages in direction d, side s (ghost rule of the boundary)
+  auto nbr_avg = [&](int d, int s, double* qa) {
+    int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
+    const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
+    if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
+      const int type = bc.type[side];
+      if (type == CRKDG_BC_TRANSMISSIVE) {
+        for (int c = 0; c < NC; ++c) qa[c] = avg[c];
+        return;
+      }
+      if (type == CRKDG_BC_DIRICHLET) {
+        for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
+        return;
+      }
+      ni = (ni + g.nx) % g.nx;
+      nj = (nj + g.ny) % g.ny;
+    }
+    for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
+  };
+  auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
+  if (in) {
     load_state<double, NC, NB, LAY>(u, g.N, cell, U);
-    double avg[NC];
     for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
     if constexpr (EQ::EULER) {
       const double p = (ph.gamma - 1.0) * (avg[3] - 0.5 * (avg[1] * avg[1] + avg[2] * avg[2]) / avg[0]);
       bad = !(avg[0] > 0.0) || !(p > 0.0);
     }
-    // neighbour averages in direction d, side s (ghost rule of the boundary)
-    auto nbr_avg = [&](int d, int s, double* qa) {
-      int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
-      const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
-      if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
-        const int type = bc.type[side];
-        if (type == CRKDG_BC_TRANSMISSIVE) {
-          for (int c = 0; c < NC; ++c) qa[c] = avg[c];
-          return;
-        }
-        if (type == CRKDG_BC_DIRICHLET) {
-          for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
-          return;
-        }
-        ni = (ni + g.nx) % g.nx;
-        nj = (nj + g.ny) % g.ny;
-      }
-      for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
-    };
-    auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
-    double dp[2][NC], dm[2][NC];
     for (int d = 0; d < DIM; ++d) {
       double qn[NC];
       nbr_avg(d, +1, qn);
@@ -1269,82 +1275,79 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, Limi
       nbr_avg(d, -1, qn);
       for (int c = 0; c < NC; ++c) dm[d][c] = avg[c] - qn[c];
     }
-    // the TVB minmod troubled-cell test (characteristic variables for Euler)
-    auto tvb_test = [&]() {
-      bool tr = false;
-      for (int d = 0; d < DIM; ++d) {
-        const double h = d == 0 ? g.dx : g.dy;
-        const double Mh2 = M * h * h;
-        double a[NC], at[NC];
-        for (int c = 0; c < NC; ++c) {
-          a[c] = 0.0;
-          at[c] = 0.0;
-          for (int deg = 1; deg <= K; ++deg) {
-            const double v = U[c][mode_of(d, deg)];
-            a[c] += v;
-            at[c] += (deg % 2) ? v : -v;
-          }
+  }
+  // the TVB minmod troubled-cell test (characteristic variables for Euler)
+  auto tvb_test = [&]() {
+    bool tr = false;
+    for (int d = 0; d < DIM; ++d) {
+      const double h = d == 0 ? g.dx : g.dy;
+      const double Mh2 = M * h * h;
+      double a[NC], at[NC];
+      for (int c = 0; c < NC; ++c) {
+        a[c] = 0.0;
+        at[c] = 0.0;
+        for (int deg = 1; deg <= K; ++deg) {
+          const double v = U[c][mode_of(d, deg)];
+          a[c] += v;
+          at[c] += (deg % 2) ? v : -v;
         }
-        double ca[NC], cat[NC], cp[NC], cm[NC];
-        if constexpr (EQ::EULER) {
-          double L[16], Rm[16];
-          euler_eigvec(ph.gamma, avg, d, L, Rm);
-          for (int r = 0; r < NC; ++r) {
-            ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
-            for (int c = 0; c < NC; ++c) {
-              ca[r] += L[r * 4 + c] * a[c];
-              cat[r] += L[r * 4 + c] * at[c];
-              cp[r] += L[r * 4 + c] * dp[d][c];
-              cm[r] += L[r * 4 + c] * dm[d][c];
-            }
-          }
-        } else {
-          for (int c = 0; c < NC; ++c) {
-            ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
-          }
-        }
-        for (int r = 0; r < NC; ++r)
-          if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r])
-            tr = true;
       }
-      return tr;
-    };
-    bool troubled = false;
-    bool fallback = false;
-    if (K >= 1 && !bad) {
-      if constexpr (EQ::EULER && DIM == 2) {
-        if (la.mlp) {
-          float x[MLP_IN];
-          double dpa[2][4], dma[2][4];
-          for (int d = 0; d < 2; ++d)
-            for (int c = 0; c < 4; ++c) {
-              dpa[d][c] = dp[d][c];
-              dma[d][c] = dm[d][c];
-            }
-          cell_features<NB, Q>(U, dpa, dma, M * g.dx * g.dx, M * g.dy * g.dy, x);
-          const float z = mlp_forward1<false>(la.P, x);
-          const float pr = 1.0f / (1.0f + __expf(-z));
-          if (pr >= la.tau_hi) {
-            troubled = true;
-          } else if (pr > la.tau_lo) {
-            fallback = true;
-            troubled = tvb_test();
+      double ca[NC], cat[NC], cp[NC], cm[NC];
+      if constexpr (EQ::EULER) {
+        double L[16], Rm[16];
+        euler_eigvec(ph.gamma, avg, d, L, Rm);
+        for (int r = 0; r < NC; ++r) {
+          ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
+          for (int c = 0; c < NC; ++c) {
+            ca[r] += L[r * 4 + c] * a[c];
+            cat[r] += L[r * 4 + c] * at[c];
+            cp[r] += L[r * 4 + c] * dp[d][c];
+            cm[r] += L[r * 4 + c] * dm[d][c];
           }
-        } else {
-          troubled = tvb_test();
         }
       } else {
+        for (int c = 0; c < NC; ++c) {
+          ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
+        }
+      }
+      for (int r = 0; r < NC; ++r)
+        if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r])
+          tr = true;
+    }
+    return tr;
+  };
+  bool troubled = false;
+  bool fallback = false;
+  if constexpr (USE_MLP) {
+    __shared__ MlpWaveSmem sm[4];
+    __shared__ MlpWeightsSmem ws;
+    mlp_stage_weights(la.P, ws);
+    float x[MLP_IN];
+#pragma unroll
+    for (int e = 0; e < MLP_IN; ++e) x[e] = 0.0f;
+    if (in && !bad) cell_features<NB, Q>(U, dp, dm, M * g.dx * g.dx, M * g.dy * g.dy, x);
+    __syncthreads();  // the staged weights
+    const float z = mlp_infer_wave(la.P, ws, x, sm[threadIdx.x >> 6]);
+    if (in && !bad) {
+      if (z >= la.z_hi) {
+        troubled = true;
+      } else if (z > la.z_lo) {
+        fallback = true;
         troubled = tvb_test();
       }
     }
+  } else {
+    if (in && K >= 1 && !bad) troubled = tvb_test();
+  }
+  if (in) {
     auto reconstruct = [&](double (&V)[NC][NB]) {
       double ns[2][NC];
       for (int d = 0; d < DIM; ++d) {
         const double h = d == 0 ? g.dx : g.dy;
         const double Mh2 = M * h * h;
-        const int sm = mode_of(d, 1);
+        const int sm1 = mode_of(d, 1);
         double sl[NC];
-        for (int c = 0; c < NC; ++c) sl[c] = V[c][sm];
+        for (int c = 0; c < NC; ++c) sl[c] = V[c][sm1];
         if constexpr (EQ::EULER) {
           double L[16], Rm[16], lim[NC];
           euler_eigvec(ph.gamma, avg, d, L, Rm);
@@ -1576,15 +1579,21 @@ struct RunProject {
 template <class EQ, int K>
 struct RunLimit {
   static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const LimitArgs& la,
-                        void* u, int lay, uint8_t* flags, unsigned long long* counters,
+                        bool mlp, void* u, int lay, uint8_t* flags, unsigned long long* counters,
                         hipStream_t s) {
     if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 3);
-    if (lay == LMIX)
-      hipLaunchKernelGGL((k_limit<EQ, K, LMIX>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, la,
-                         u, flags, counters);
-    else
-      hipLaunchKernelGGL((k_limit<EQ, K, L64>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, bc, la,
-                         u, flags, counters);
+    const dim3 grid(nblk(g.N, 256));
+    if (mlp) {
+      if (lay == LMIX)
+        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+      else
+        hipLaunchKernelGGL((k_limit<EQ, K, L64, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+    } else {
+      if (lay == LMIX)
+        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+      else
+        hipLaunchKernelGGL((k_limit<EQ, K, L64, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+    }
     return hipGetLastError();
   }
 };
@@ -1651,8 +1660,14 @@ hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, double M, const float* mlp_params, float tau_lo,
                         float tau_hi, void* u, uint8_t* flags, unsigned long long* counters,
                         hipStream_t s) {
-  LimitArgs la{M, mlp_params != nullptr, mlp_params, tau_lo, tau_hi};
-  return dispatch<RunLimit>(eq, k, ph, g, bc, la, u, lay, flags, counters, s);
+  // probabilities to logit thresholds (monotone, so the decisions agree)
+  auto logit = [](float p) -> float {
+    if (!(p > 0.0f)) return -INFINITY;
+    if (!(p < 1.0f)) return INFINITY;
+    return (float)log((double)p / (1.0 - (double)p));
+  };
+  LimitArgs la{M, mlp_params, logit(tau_lo), logit(tau_hi)};
+  return dispatch<RunLimit>(eq, k, ph, g, bc, la, mlp_params != nullptr, u, lay, flags, counters, s);
 }
 hipError_t launch_mlp_features(int k, int lay, const Geo& g, const BCDev& bc, double M,
                                const void* u, float* X, hipStream_t s) {

@@ -1,7 +1,8 @@
 // crkdg_mlp.hip -- training kernels of the learned troubled-cell indicator
 // (not part of the paper's method; FP32).
 //
-//   k_mlp_forward       logits of a batch of feature vectors
+//   k_mlp_forward       logits of a batch of feature vectors, at inference
+//                       precision (bf16 matrix cores, as in the limiter)
 //   k_mlp_grad_partial  forward + backward of 64 samples per workgroup: each
 //                       lane runs one sample, the activations go to LDS, then
 //                       each lane sums a fixed subset of the 1505 parameter
@@ -22,15 +23,20 @@ namespace crk {
 constexpr int MB = 64;  // samples per workgroup of the gradient kernel
 constexpr int NPART = MLP_NPAR + 1;  // partial gradients + partial loss
 
+// logits at inference precision (the same routine the limiter uses)
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P,
                                                      const float* __restrict__ X, int B,
                                                      float* __restrict__ out) {
+  __shared__ MlpWaveSmem sm[4];
+  __shared__ MlpWeightsSmem ws;
+  mlp_stage_weights(P, ws);
+  __syncthreads();
   const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= B) return;
   float x[MLP_IN];
 #pragma unroll
-  for (int i = 0; i < MLP_IN; ++i) x[i] = X[(long long)n * MLP_IN + i];
-  out[n] = mlp_forward1<false>(P, x);
+  for (int i = 0; i < MLP_IN; ++i) x[i] = n < B ? X[(long long)n * MLP_IN + i] : 0.0f;
+  const float z = mlp_infer_wave(P, ws, x, sm[threadIdx.x >> 6]);
+  if (n < B) out[n] = z;
 }
 
 __device__ __forceinline__ float softplus_f(float x) {
@@ -64,7 +70,7 @@ __global__ __launch_bounds__(MB) void k_mlp_grad_partial(const float* __restrict
     float d2[MLP_H2];
 #pragma unroll
     for (int o = 0; o < MLP_H2; ++o) {
-      d2[o] = dz * P[MLP_OW3 + o] * (1.0f - h2[o] * h2[o]);
+      d2[o] = h2[o] > 0.0f ? dz * P[MLP_OW3 + o] : 0.0f;
       sd2[t][o] = d2[o];
       sh2[t][o] = h2[o];
     }
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(MB) void k_mlp_grad_partial(const float* __restrict
       float s = 0.0f;
 #pragma unroll
       for (int o = 0; o < MLP_H2; ++o) s = s + P[MLP_OW2 + o * MLP_H1 + i] * d2[o];
-      sd1[t][i] = s * (1.0f - h1[i] * h1[i]);
+      sd1[t][i] = h1[i] > 0.0f ? s : 0.0f;
       sh1[t][i] = h1[i];
     }
 #pragma unroll

@@ -52,7 +52,7 @@ def shock_solver(seed, scale, precision=K.FP64):
 
 
 def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample_seed=0,
-             report=None, family="quadrant", max_steps=None, max_pos=20000):
+             report=None, family="quadrant", max_steps=None, max_pos=20000, policy=None):
     """features X (float32 [S, 12]) and TVB labels y (uint8 [S]) from FP64
     TVB runs with the given seeds, sampled at about `samples` evenly spaced
     steps.
@@ -61,6 +61,11 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
     the fastest initial wave has crossed t_frac of the domain.  family
     "shock": the planar-shock workload with cell counts divided by n, run to
     its final time or for max_steps steps.
+
+    policy = (params, tau_lo, tau_hi): the runs are limited by the learned
+    indicator instead of the TVB test (the states it will meet in use); the
+    labels stay the FP64 TVB decisions, taken on an FP64 copy of each
+    sampled state.
 
     Per sampled step at most max_pos positives are kept, and negatives are
     subsampled to neg_ratio per positive (at least 256).
@@ -95,6 +100,9 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
         t, step = 0.0, 0
         flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
         X = torch.empty((s.ncells, 12), dtype=torch.float32, device="cuda")
+        clone = None
+        if policy is not None:
+            clone = K.Solver(s.mesh, cfg["k"], K.FLUX_LLF, 3)
         while t < T - 1e-14 and step < nsteps:
             dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), T - t)
             s.crkdg_step(dt)
@@ -104,7 +112,13 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
             if sample:
                 s.crkdg_mlp_features(M, X)
             try:
-                s.crkdg_limit(M, flags if sample else None)
+                if policy is None:
+                    s.crkdg_limit(M, flags if sample else None)
+                else:
+                    if sample:  # labels: the TVB decision on the same state
+                        clone.crkdg_set_state(s.crkdg_get_state())
+                        clone.crkdg_limit(M, flags)
+                    s.crkdg_limit_mlp(M, policy[0], policy[1], policy[2], None)
             except K.CrkdgError as e:
                 if e.code != K.CRKDG_ENONPHYSICAL:
                     raise
@@ -130,15 +144,16 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
 
 
 def init_params(seed=0):
-    """Glorot-uniform weights, zero biases (float64 host array)"""
+    """He-uniform weights (suited to ReLU layers), zero biases (float64 host
+    array)"""
     rng = np.random.default_rng(seed)
     P = np.zeros(NPAR)
     o = 0
     for fan_out, fan_in in ((32, 12), (32, 32)):
-        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        lim = math.sqrt(6.0 / fan_in)
         P[o:o + fan_out * fan_in] = rng.uniform(-lim, lim, fan_out * fan_in)
         o += fan_out * fan_in + fan_out
-    lim = math.sqrt(6.0 / 33)
+    lim = math.sqrt(6.0 / 32)
     P[o:o + 32] = rng.uniform(-lim, lim, 32)
     return P
 

@@ -193,3 +193,53 @@ def test_adam_first_step_closed_form():
     m1, m2 = np.zeros(3), np.zeros(3)
     O.adam(p, m1, m2, g, 1, lr=0.01, eps=1e-8)
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_bf16_rounding_ties_to_even():
+    """bfloat16 keeps 8 significand bits: spacing 2^-7 just above 1"""
+    assert O.bf16(1.0 + 2.0 ** -8) == 1.0                      # tie, even neighbour below
+    assert O.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6      # tie, even neighbour above
+    assert O.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert O.bf16(-(1.0 + 2.0 ** -8)) == -1.0
+    assert O.bf16(0.15625) == 0.15625                          # already representable
+
+
+def hand_network():
+    """W1: h1_0 = x0, h1_1 = x1 - 0.5; W2: h2_0 = 3 h1_0 + 5 h1_1, h2_1 = -h1_0;
+    output z = 2 h2_0 + 4 h2_1 - 1 (all other weights zero)"""
+    P = np.zeros(O.N_MLP_PARAMS)
+    OW1, OB1 = 0, 12 * 32
+    OW2, OB2 = OB1 + 32, OB1 + 32 + 32 * 32
+    OW3, OB3 = OB2 + 32, OB2 + 64
+    P[OW1 + 0 * 12 + 0] = 1.0
+    P[OW1 + 1 * 12 + 1] = 1.0
+    P[OB1 + 1] = -0.5
+    P[OW2 + 0 * 32 + 0] = 3.0
+    P[OW2 + 0 * 32 + 1] = 5.0
+    P[OW2 + 1 * 32 + 0] = -1.0
+    P[OW3 + 0] = 2.0
+    P[OW3 + 1] = 4.0
+    P[OB3] = -1.0
+    return P
+
+
+def test_mlp_relu_network_by_hand():
+    P = hand_network()
+    X = np.zeros((3, 12))
+    X[0, :2] = [1.0, 2.0]     # h1 = (1, 1.5): h2 = (10.5, 0): z = 20
+    X[1, :2] = [-1.0, 0.25]   # h1 = (0, 0): h2 = (0, 0): z = -1
+    X[2, :2] = [-2.0, 1.0]    # h1 = (0, 0.5): h2 = (2.5, 0): z = 4
+    assert np.array_equal(O.mlp_forward(P, X), [20.0, -1.0, 4.0])
+    assert np.array_equal(O.mlp_infer(P, X), [20.0, -1.0, 4.0])   # all values bf16-exact
+
+
+def test_mlp_infer_matches_forward_within_bf16():
+    rng = np.random.default_rng(3)
+    P = 0.3 * rng.standard_normal(O.N_MLP_PARAMS)
+    X = rng.standard_normal((200, 12))
+    z64 = O.mlp_forward(P, X)
+    zin = O.mlp_infer(P, X)
+    # bfloat16 carries 2^-9 relative error per rounded value; a few percent of
+    # the logit scale at most
+    assert np.abs(zin - z64).max() < 0.05 * max(1.0, np.abs(z64).max())
+    assert np.abs(zin - z64).max() > 0.0  # the rounding is really applied
