@@ -181,6 +181,10 @@ def main():
     ap.add_argument("--equal-error-scale", type=int, default=4,
                     help="the equal-error runs use the workload with cell counts divided by this")
     ap.add_argument("--scale", type=int, default=1, help="divide the cell counts (debug only)")
+    ap.add_argument("--no-mlp", action="store_true",
+                    help="profiling runs only: skip the learned indicator (training and form)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 256 MiB device copy (traffic counter calibration)")
     args = ap.parse_args()
     if args.equal_error_scale < 2:
         ap.error("--equal-error-scale must be at least 2 (the reference is twice as fine)")
@@ -194,17 +198,20 @@ def main():
     from paper_2307_06471_amd import mlp as ML
     from paper_2307_06471_amd import workloads as W
 
-    P, lo, hi, mlp_info = train_indicator(K, ML)
-    log(f"indicator trained: {mlp_info['samples']} samples, band ({lo:.4g}, {hi:.4g}), "
-        f"validation {mlp_info['validation']}")
-    mlp = (P, lo, hi)
+    mlp = None
+    if not args.no_mlp:
+        P, lo, hi, mlp_info = train_indicator(K, ML)
+        log(f"indicator trained: {mlp_info['samples']} samples, band ({lo:.4g}, {hi:.4g}), "
+            f"validation {mlp_info['validation']}")
+        mlp = (P, lo, hi)
 
     forms = {}
-    for name, prec, ind in (("fp32-bulk + MLP", K.FP32_MIXED, mlp), ("fp64 + TVB", K.FP64, None),
-                            ("fp32-bulk + TVB", K.FP32_MIXED, None)):
+    plan = [("fp32-bulk + MLP", K.FP32_MIXED, mlp)] if mlp is not None else []
+    plan += [("fp64 + TVB", K.FP64, None), ("fp32-bulk + TVB", K.FP32_MIXED, None)]
+    for name, prec, ind in plan:
         forms[name] = run_form(K, W, args, prec, ind)
         log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
-    head = forms["fp32-bulk + MLP"]
+    head = forms["fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"]
     plain = forms["fp64 + TVB"]
     tvb32 = forms["fp32-bulk + TVB"]
     out = {
@@ -216,9 +223,11 @@ def main():
                                f"{head['nx']}x{head['ny']} Q2 cells on [0,4]x[0,1], cRKDG scheme "
                                f"eq3, Lax-Friedrichs flux, final-stage limiter M=50, "
                                f"per-step dt (CFL 0.1)",
-                   "form": "fp32-bulk (FP32 contractions and fluxes, FP64 cell averages and "
-                           "face-flux sums) + learned troubled-cell indicator (12-32-32-1 MLP, "
-                           "FP64 TVB test inside its uncertainty band)",
+                   "form": ("fp32-bulk (FP32 contractions and fluxes, FP64 cell averages and "
+                            "face-flux sums) + learned troubled-cell indicator (12-32-32-1 ReLU "
+                            "MLP on the bf16 matrix cores, FP64 TVB test inside its uncertainty "
+                            "band)") if mlp is not None else
+                           "fp32-bulk + TVB (profiling run without the learned indicator)",
                    "cells": head["cells"], "dofs": head["dofs"], "parallelism": "1 GPU"},
         "roofline": head["roofline"],
         "kernels": head["kernels"],
@@ -227,15 +236,32 @@ def main():
         "fp32_bulk_tvb": {"value": tvb32["value"], "ms_per_step": tvb32["ms_per_step"],
                           "kernels": tvb32["kernels"]},
         "speedup_vs_fp64_plain": head["value"] / plain["value"],
-        "mlp": mlp_info,
     }
-    if not args.no_equal_error:
+    if mlp is not None:
+        out["mlp"] = mlp_info
+    if not args.no_equal_error and mlp is not None:
         out["equal_error"] = equal_error(K, W, args.equal_error_scale, mlp)
         log(f"equal error: {out['equal_error']['verdict']} "
             f"{json.dumps(out['equal_error']['mean_error_ratio_vs_fp64_tvb'])}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, precision_tag):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None"""
+    from paper_2307_06471_amd import profsummary as PS
+    d = PS.read_traffic(os.path.join(ROOT, "profiles", f"k_{kernel}_{precision_tag}_traffic.txt"))
+    if not d or d.get("kernel source hash") != PS.kernel_source_hash():
+        return None
+    return float(d["traffic_bytes_per_launch"])
 
 
 def run_form(K, W, args, precision, mlp=None):
@@ -287,9 +313,13 @@ def run_form(K, W, args, precision, mlp=None):
     dom = max(prof, key=lambda c: prof[c][0])
     by = algorithmic_bytes(dom, s.state_bytes, stage_bytes, s.ncells, stages_final)
     achieved = by / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e9
+    traffic = measured_traffic({"final": "final2", "inner": "inner", "limit": "limit"}.get(dom, dom),
+                               "fp32" if precision == K.FP32_MIXED else "fp64")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_launch": by}
+    if traffic is not None:
+        roof["traffic_over_algorithmic"] = round(traffic / by, 3)
     return {"value": dofs * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
             "roofline": roof, "kernels": kern, "flagged_cells_end": n_flag,
             "cells": s.ncells, "dofs": dofs, "nx": cfg["nx"], "ny": cfg["ny"]}

@@ -1,0 +1,105 @@
+"""Short text summaries of rocprofv3 output, for the files under profiles/.
+
+  python -m paper_2307_06471_amd.profsummary stats <kernel_stats.csv> <out.txt> <title> <command>
+      per-kernel calls, average and total duration (from --kernel-trace --stats)
+
+  python -m paper_2307_06471_amd.profsummary traffic <fetch counter_collection.csv>
+      <write counter_collection.csv> <kernel substring> <copy_bytes> <out.txt> <command>
+      HBM traffic of one kernel per launch: FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch) averaged over its dispatches, each scaled by the ratio of a
+      plain device copy's known size to what the same counter reads for it
+      (the largest copy dispatch in the same run), plus the hash of the kernel
+      sources it was measured on (the benchmark reports the traffic only while
+      the sources still hash the same).
+"""
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/crkdg_kernels.hip", "csrc/dg_core.hpp", "csrc/crkdg_internal.hpp",
+                  "csrc/mlp_core.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats(path, out, title, command):
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"# {title}", "", "command (repo root on the MI355X box, after "
+             "`cd /tmp && export TMPDIR=/tmp`):", f"  {command}", "",
+             f"kernel source hash: {kernel_source_hash()}", "",
+             "%-72s %7s %11s %11s %7s" % ("kernel", "calls", "avg_us", "total_ms", "pct")]
+    for d in rows:
+        n = d["Name"].replace("crk::", "")
+        if len(n) > 72:
+            n = n[:69] + "..."
+        lines.append("%-72s %7s %11.1f %11.3f %7.2f" % (
+            n, d["Calls"], float(d["AverageNs"]) / 1e3, float(d["TotalDurationNs"]) / 1e6,
+            float(d["Percentage"])))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path, counter):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    return rows
+
+
+def traffic(fetch_csv, write_csv, kernel, copy_bytes, out, command):
+    res = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _per_dispatch(path, counter)
+        kern = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        copies = [r for r in rows if "copy" in r["Kernel_Name"].lower()]
+        if not kern or not copies:
+            raise SystemExit(f"no {counter} rows for {kernel!r} or for a copy kernel in {path}")
+        big = max(int(r["Grid_Size"]) for r in copies)
+        cval = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
+        kib_copy = sum(cval) / len(cval)
+        factor = copy_bytes / (kib_copy * 1024.0)
+        kib = sum(kern) / len(kern)
+        res[name] = {"kib_per_dispatch": kib, "dispatches": len(kern), "copy_kib": kib_copy,
+                     "factor": factor, "bytes_per_launch": kib * 1024.0 * factor}
+    lines = [f"# HBM traffic per launch of {kernel}", "",
+             "commands (repo root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):",
+             f"  {command}", "",
+             f"kernel source hash: {kernel_source_hash()}",
+             f"calibration copy bytes: {int(copy_bytes)}"]
+    for name in ("fetch", "write"):
+        r = res[name]
+        lines += [f"{name}_kib_per_dispatch: {r['kib_per_dispatch']:.1f}",
+                  f"{name}_dispatches: {r['dispatches']}",
+                  f"{name}_copy_kib: {r['copy_kib']:.1f}",
+                  f"{name}_factor: {r['factor']:.5f}",
+                  f"{name}_bytes_per_launch: {r['bytes_per_launch']:.0f}"]
+    lines.append(f"traffic_bytes_per_launch: {res['fetch']['bytes_per_launch'] + res['write']['bytes_per_launch']:.0f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def read_traffic(path):
+    """the key: value lines of a traffic summary, or None"""
+    if not os.path.exists(path):
+        return None
+    d = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ")):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    return d
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:6])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], sys.argv[7])
+    else:
+        raise SystemExit(__doc__)
