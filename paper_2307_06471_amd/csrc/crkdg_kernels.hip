@@ -532,20 +532,18 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
   const EQ eq = make_eq<EQ>(ph);
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
 
-  // this lane's halo cell: left column, right column, bottom row, top row
+  // this lane's halo cell: bottom row, top row, then the left and right
+  // columns, so that with TX = 64 each halo wave runs one trace variant
   int hside = -1, hci = 0, hcj = 0, hslot = 0;
-  if (tid < TY) {
-    hside = 0; hci = i0; hcj = j0 + tid; hslot = tid;
-    if (tid >= nay) hside = -1;
-  } else if (tid < 2 * TY) {
-    hside = 1; hci = i0 + nax - 1; hcj = j0 + tid - TY; hslot = tid - TY;
-    if (tid - TY >= nay) hside = -1;
-  } else if (tid < 2 * TY + TX) {
-    hside = 2; hci = i0 + tid - 2 * TY; hcj = j0; hslot = tid - 2 * TY;
-    if (tid - 2 * TY >= nax) hside = -1;
+  if (tid < TX) {
+    hside = tid < nax ? 2 : -1; hci = i0 + tid; hcj = j0; hslot = tid;
+  } else if (tid < 2 * TX) {
+    hside = tid - TX < nax ? 3 : -1; hci = i0 + tid - TX; hcj = j0 + nay - 1; hslot = tid - TX;
+  } else if (tid < 2 * TX + TY) {
+    hside = tid - 2 * TX < nay ? 0 : -1; hci = i0; hcj = j0 + tid - 2 * TX; hslot = tid - 2 * TX;
   } else if (tid < NHALO) {
-    hside = 3; hci = i0 + tid - 2 * TY - TX; hcj = j0 + nay - 1; hslot = tid - 2 * TY - TX;
-    if (tid - 2 * TY - TX >= nax) hside = -1;
+    hside = tid - 2 * TX - TY < nay ? 1 : -1; hci = i0 + nax - 1; hcj = j0 + tid - 2 * TX - TY;
+    hslot = tid - 2 * TX - TY;
   }
 
   R acc[NC][NB];
