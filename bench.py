@@ -3,10 +3,10 @@
 One "step" is one pass of the whole hot path over the 2D Euler shock
 workload (4096 x 1024 cells, Q^2, scheme (eq:3), Lax--Friedrichs flux, Mach-3
 shock into a smoothed density field; see paper_2307_06471_amd/workloads.py):
-  dt from the cell averages (device reduction, no host sync)
-  -> inner stages (local operator)
+  inner stages (local operator)
   -> final stage (DG operator, face fluxes, conservative update)
-  -> TVB minmod limiter (M = 50).
+  -> final-stage limiter (M = 50), which also reduces the cell wave speeds
+     for the next step's dt (device reduction, no host sync).
 The timed region holds K such steps with the state resident in HBM; the
 result is DOF-updates/s (cells x modes x components per step).
 
@@ -36,7 +36,8 @@ def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final):
     """bytes a kernel class must move per launch (its inputs and outputs):
     inner: read u^n, write the stored stage state(s); final: read u^n and the
     stored stage states, write u^{n+1}; limiter: read the state, write one
-    flag byte per cell; dt: read the cell averages (4 doubles per cell)."""
+    flag byte per cell; dt: the final max over the limiter's per-block
+    wave-speed maxima."""
     if cls == "inner":
         return state_bytes + stage_bytes * (stages_final - 1)
     if cls == "final":
@@ -44,7 +45,7 @@ def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final):
     if cls == "limit":
         return state_bytes + ncells
     if cls == "dt":
-        return ncells * 32
+        return ((ncells + 255) // 256) * 8  # the limiter's per-block maxima
     return None
 
 
@@ -272,20 +273,15 @@ def run_form(K, W, args, precision, mlp=None):
     flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
     M = cfg["limiter"][1]
 
-    if mlp is None:
-        def limit():
-            s.crkdg_limit(M, flags, count=False)
-    else:
-        P, lo, hi = mlp
-
-        def limit():
-            s.crkdg_limit_mlp(M, P, lo, hi, flags, count=False)
+    P, lo, hi = mlp if mlp is not None else (None, 0.0, 0.0)
 
     def step():
-        s.crkdg_compute_dt(cfg["cfl"], dt_dev)
+        # one step, then the limiter, which also leaves the next step's dt
+        # (from the cell averages it reads; the limiter does not change them)
         s.crkdg_step_dev(dt_dev)
-        limit()
+        s.crkdg_limit_dt(M, cfg["cfl"], dt_dev, flags, params=P, tau_lo=lo, tau_hi=hi)
 
+    s.crkdg_compute_dt(cfg["cfl"], dt_dev)  # dt of the first step
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -166,6 +166,15 @@ int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagge
  * 2D Euler only (CRKDG_EUNSUPPORTED otherwise). */
 int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float tau_lo,
                     float tau_hi, uint8_t* flags_dev, int64_t* counts_host);
+/* The final-stage limiter followed by the next step's dt: crkdg_limit
+ * (params_dev == NULL) or crkdg_limit_mlp (params_dev set, with the band
+ * tau_lo <= tau_hi), and dt = cfl / s_max of the limited state written to
+ * dt_dev (1 device double), with s_max as in crkdg_compute_dt.  The limiter
+ * never changes a cell average, so s_max comes from the averages the limiter
+ * has already read: this saves the separate pass of crkdg_compute_dt.
+ * Stream-ordered, no sync, no counts; flags_dev nullable. */
+int crkdg_limit_dt(crkdg_state* st, double M, const float* params_dev, float tau_lo,
+                   float tau_hi, uint8_t* flags_dev, double cfl, double* dt_dev);
 /* The 12 features of every cell of the current state, X[cell][12] FP32
  * (computed in FP64): for q in {rho, E} and d in {x, y}, with a / at the
  * forward / backward face-average jumps of q, dp / dm the neighbouring

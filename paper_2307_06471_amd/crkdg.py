@@ -65,6 +65,8 @@ def _sig():
         "crkdg_compute_dt": (C.c_int, [vp, C.c_double, vp]),
         "crkdg_max_wavespeed": (C.c_int, [vp, dp]),
         "crkdg_limit": (C.c_int, [vp, C.c_double, vp, C.POINTER(C.c_int64)]),
+        "crkdg_limit_dt": (C.c_int, [vp, C.c_double, vp, C.c_float, C.c_float, vp, C.c_double,
+                                     vp]),
         "crkdg_error": (C.c_int, [vp, C.c_int, dp, C.c_int, C.c_double, C.c_int, dp]),
         "crkdg_error_ref": (C.c_int, [vp, vp, C.c_int, dp]),
         "crkdg_total": (C.c_int, [vp, C.c_int, dp]),
@@ -242,6 +244,15 @@ class Solver:
         rc = lib().crkdg_limit(self.h, float(M), f, C.byref(n) if count else None)
         _check(rc, "crkdg_limit")
         return n.value if count else None
+
+    def crkdg_limit_dt(self, M, cfl, dt_tensor, flags=None, params=None, tau_lo=0.0, tau_hi=0.0):
+        """limiter (TVB, or the learned indicator when params is given) and
+        the next step's dt into dt_tensor (1 device double)"""
+        f = None if flags is None else C.c_void_p(flags.data_ptr())
+        pp = None if params is None else C.c_void_p(params.data_ptr())
+        _check(lib().crkdg_limit_dt(self.h, float(M), pp, float(tau_lo), float(tau_hi), f,
+                                    float(cfl), C.c_void_p(dt_tensor.data_ptr())),
+               "crkdg_limit_dt")
 
     def crkdg_limit_mlp(self, M, params, tau_lo, tau_hi, flags=None, count=True):
         cnt = (C.c_int64 * 2)(-1, -1)

@@ -61,6 +61,14 @@ char* nxt_ptr(const crkdg_state* st) { return st->cur ? st->dofs : slot_ptr(st, 
 char* stage_ptr(const crkdg_state* st, int i) { return slot_ptr(st, i); }          // i = 1..3
 char* lbuf_ptr(const crkdg_state* st, int j) { return slot_ptr(st, MAXS + j); }    // j = 0..2
 char* scratch_ptr(const crkdg_state* st) { return slot_ptr(st, 2 * MAXS - 1); }
+// per-block wave-speed maxima written by the limiter (one double per 256 cells)
+int wave_blocks(const crkdg_state* st) { return (int)((st->geo.N + 255) / 256); }
+size_t wave_partial_bytes(const crkdg_state* st) {
+  return round_up((size_t)wave_blocks(st) * sizeof(double));
+}
+double* wave_partial_ptr(const crkdg_state* st) {
+  return (double*)(scratch_ptr(st) + round_up(SCRATCH));
+}
 
 void set_tableau_internal(crkdg_state* st, int s, const double* c, const double* A,
                           const double* b) {
@@ -237,7 +245,7 @@ size_t crkdg_state_bytes(const crkdg_state* st) { return st ? st->S : 0; }
 
 size_t crkdg_workspace_bytes(const crkdg_state* st) {
   if (!st) return 0;
-  return (size_t)(2 * MAXS - 1) * slot_bytes(st) + SCRATCH;
+  return (size_t)(2 * MAXS - 1) * slot_bytes(st) + round_up(SCRATCH) + wave_partial_bytes(st);
 }
 
 int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream) {
@@ -486,14 +494,20 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
 }
 
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
-                      uint8_t* flags_dev, int64_t* counts, int ncounts) {
+                      uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl = 0.0,
+                      double* dt_dev = nullptr) {
   unsigned long long* counters =
       counts ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
   hipError_t e;
   {
     ProfScope ps(st, KC_LIMIT);
     e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, params, tau_lo, tau_hi,
-                     cur_ptr(st), flags_dev, counters, st->stream);
+                     cur_ptr(st), flags_dev, counters, dt_dev ? wave_partial_ptr(st) : nullptr,
+                     st->stream);
+  }
+  if (e == hipSuccess && dt_dev) {
+    ProfScope ps(st, KC_DT);
+    e = launch_wave_final(wave_partial_ptr(st), wave_blocks(st), cfl, nullptr, dt_dev, st->stream);
   }
   if (e != hipSuccess) return CRKDG_EHIP;
   if (counts) {
@@ -520,6 +534,16 @@ int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float ta
   if (!st->bound) return CRKDG_EUNBOUND;
   if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
   return limit_impl(st, M, params_dev, tau_lo, tau_hi, flags_dev, counts_host, 2);
+}
+
+int crkdg_limit_dt(crkdg_state* st, double M, const float* params_dev, float tau_lo,
+                   float tau_hi, uint8_t* flags_dev, double cfl, double* dt_dev) {
+  if (!st || !dt_dev || !isfinite(M) || M < 0.0 || !isfinite(cfl) || !(cfl > 0.0))
+    return CRKDG_EINVAL;
+  if (params_dev && !(tau_lo <= tau_hi)) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if (params_dev && (st->eq != EQ_EULER2 || st->k < 1)) return CRKDG_EUNSUPPORTED;
+  return limit_impl(st, M, params_dev, tau_lo, tau_hi, flags_dev, nullptr, 0, cfl, dt_dev);
 }
 
 int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev) {

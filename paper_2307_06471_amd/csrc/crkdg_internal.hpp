@@ -91,10 +91,15 @@ hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& 
                           const double* params, const double* aux, double t, void* u,
                           hipStream_t s);
 // mlp_params == NULL: TVB test; else learned indicator with the TVB fallback band
+// wave_partial (nullable): per-block max wave speed of the (limited) state,
+// one double per 256 cells
 hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, double M, const float* mlp_params, float tau_lo,
                         float tau_hi, void* u, uint8_t* flags, unsigned long long* counters,
-                        hipStream_t s);
+                        double* wave_partial, hipStream_t s);
+// dt = cfl / max(partial[0..n)) (and/or the max itself), one block
+hipError_t launch_wave_final(const double* partial, int n, double cfl, double* smax, double* dt,
+                             hipStream_t s);
 hipError_t launch_mlp_features(int k, int lay, const Geo& g, const BCDev& bc, double M,
                                const void* u, float* X, hipStream_t s);
 // MLP training kernels (crkdg_mlp.hip)

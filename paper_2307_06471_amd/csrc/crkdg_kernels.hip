@@ -900,6 +900,28 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
+// primitive quantities of a cell average (FP64), computed once per cell and
+// shared by the wave speed, the characteristic decomposition and the limited
+// reconstruction
+struct EulerPrim {
+  double ir, u, v, q2, p, c, ic, H;
+};
+__device__ __forceinline__ EulerPrim euler_prim(double gamma, const double* q) {
+  EulerPrim w;
+  w.ir = 1.0 / q[0];
+  w.u = q[1] * w.ir;
+  w.v = q[2] * w.ir;
+  w.q2 = w.u * w.u + w.v * w.v;
+  w.p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * w.u + q[2] * w.v));
+  w.c = sqrt(gamma * w.p * w.ir);
+  w.ic = 1.0 / w.c;
+  w.H = (q[3] + w.p) * w.ir;
+  return w;
+}
+__device__ __forceinline__ double euler_speed(const Geo& g, const EulerPrim& w) {
+  return (fabs(w.u) + w.c) * g.inv_dx + (fabs(w.v) + w.c) * g.inv_dy;
+}
+
 template <class EQ>
 __device__ __forceinline__ double cell_speed(const PhysDev& ph, const Geo& g, const double* q) {
   if constexpr (EQ::EULER) {
@@ -931,15 +953,23 @@ __global__ __launch_bounds__(256) void k_wave_partial(PhysDev ph, Geo g, const v
   if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(256) void k_wave_final(const double* __restrict__ partial, int n, double cfl,
-                                                    double* smax_out, double* dt_out) {
-  __shared__ double sh[256];
+__global__ __launch_bounds__(1024) void k_wave_final(const double* __restrict__ partial, int n, double cfl,
+                                                     double* smax_out, double* dt_out) {
+  __shared__ double sh[1024];
   double m = 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) {
-    const double w = partial[e];
-    if (w > m || w != w) m = w;
+  // eight independent loads in flight per thread, then a fixed-order tree
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * 1024) {
+    double w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * 1024;
+      w[q] = e < n ? partial[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (w[q] > m || w[q] != w[q]) m = w[q];
   }
-  m = block_max<256>(m, sh);
+  m = block_max<1024>(m, sh);
   if (threadIdx.x == 0) {
     if (smax_out) *smax_out = m;
     if (dt_out) *dt_out = cfl / m;
@@ -1124,14 +1154,8 @@ __device__ __forceinline__ double tvb(double a, double b, double c, double Mh2) 
 
 // left/right eigenvectors of the 2D Euler flux Jacobian in direction d at q
 // (L rows, R columns, row-major 4x4)
-__device__ void euler_eigvec(double gamma, const double* q, int d, double* L, double* Rm) {
-  const double ir = 1.0 / q[0];
-  const double u = q[1] * ir, v = q[2] * ir;
-  const double q2 = u * u + v * v;
-  const double p = (gamma - 1.0) * (q[3] - 0.5 * q[0] * q2);
-  const double c = sqrt(gamma * p * ir);
-  const double ic = 1.0 / c;  // one division; the others become products
-  const double H = (q[3] + p) * ir;
+__device__ void euler_eigvec(double gamma, const EulerPrim& w, int d, double* L, double* Rm) {
+  const double u = w.u, v = w.v, q2 = w.q2, c = w.c, ic = w.ic, H = w.H;
   const double b1 = (gamma - 1.0) * ic * ic, b2 = 0.5 * b1 * q2;
   const double un = d == 0 ? u : v, ut = d == 0 ? v : u;
   // in the rotated frame (normal, tangential); map back to (x, y) columns
@@ -1214,6 +1238,7 @@ struct LimitArgs {
   const float* P;       // MLP parameters (device; learned-indicator mode)
   float z_lo, z_hi;     // logit thresholds: z <= z_lo smooth, z >= z_hi troubled,
                         // else the TVB test decides
+  double* wave_partial; // if set: per-block max of the cell wave speeds (dt of the next step)
 };
 
 // MLP = false: the TVB minmod test decides for every cell.  MLP = true
@@ -1259,12 +1284,13 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, Limi
     for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
   };
   auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
+  EulerPrim wp{};
   if (in) {
     load_state<double, NC, NB, LAY>(u, g.N, cell, U);
     for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
     if constexpr (EQ::EULER) {
-      const double p = (ph.gamma - 1.0) * (avg[3] - 0.5 * (avg[1] * avg[1] + avg[2] * avg[2]) / avg[0]);
-      bad = !(avg[0] > 0.0) || !(p > 0.0);
+      wp = euler_prim(ph.gamma, avg);
+      bad = !(avg[0] > 0.0) || !(wp.p > 0.0);
     }
     for (int d = 0; d < DIM; ++d) {
       double qn[NC];
@@ -1293,7 +1319,7 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, Limi
       double ca[NC], cat[NC], cp[NC], cm[NC];
       if constexpr (EQ::EULER) {
         double L[16], Rm[16];
-        euler_eigvec(ph.gamma, avg, d, L, Rm);
+        euler_eigvec(ph.gamma, wp, d, L, Rm);
         for (int r = 0; r < NC; ++r) {
           ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
           for (int c = 0; c < NC; ++c) {
@@ -1348,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, Limi
         for (int c = 0; c < NC; ++c) sl[c] = V[c][sm1];
         if constexpr (EQ::EULER) {
           double L[16], Rm[16], lim[NC];
-          euler_eigvec(ph.gamma, avg, d, L, Rm);
+          euler_eigvec(ph.gamma, wp, d, L, Rm);
           for (int r = 0; r < NC; ++r) {
             double s1 = 0.0, s2 = 0.0, s3 = 0.0;
             for (int c = 0; c < NC; ++c) {
@@ -1404,6 +1430,19 @@ __global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, Limi
       if (cnt[1]) atomicAdd(&counters[1], (unsigned long long)cnt[1]);
       if (cnt[2]) atomicAdd(&counters[2], (unsigned long long)cnt[2]);
     }
+  }
+  // the limiter never changes a cell average, so the wave speeds of the
+  // limited state (the next step's dt) come from the averages already read
+  if (la.wave_partial) {
+    __shared__ double sh[256];
+    double spd = 0.0;
+    if constexpr (EQ::EULER) {
+      if (in) spd = euler_speed(g, wp);
+    } else {
+      if (in) spd = cell_speed<EQ>(ph, g, avg);
+    }
+    const double m = block_max<256>(spd, sh);
+    if (threadIdx.x == 0) la.wave_partial[blockIdx.x] = m;
   }
 }
 
@@ -1529,7 +1568,7 @@ struct RunWave {
       hipLaunchKernelGGL((k_wave_partial<EQ, K, LMIX>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
     else
       hipLaunchKernelGGL((k_wave_partial<EQ, K, L64>), dim3(nb), dim3(256), 0, s, ph, g, u, partial);
-    hipLaunchKernelGGL(k_wave_final, dim3(1), dim3(256), 0, s, partial, nb, cfl, smax, dt);
+    hipLaunchKernelGGL(k_wave_final, dim3(1), dim3(1024), 0, s, partial, nb, cfl, smax, dt);
     return hipGetLastError();
   }
 };
@@ -1627,6 +1666,11 @@ hipError_t launch_combine(long long n, double* out, const double* base, int nx,
   hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, s, n, a);
   return hipGetLastError();
 }
+hipError_t launch_wave_final(const double* partial, int n, double cfl, double* smax, double* dt,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_wave_final, dim3(1), dim3(1024), 0, s, partial, n, cfl, smax, dt);
+  return hipGetLastError();
+}
 hipError_t launch_wavespeed(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                             const void* u, double* partial, int nb, double cfl, double* smax,
                             double* dt, hipStream_t s) {
@@ -1657,14 +1701,14 @@ hipError_t launch_project(int eq, int k, int lay, const PhysDev& ph, const Geo& 
 hipError_t launch_limit(int eq, int k, int lay, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, double M, const float* mlp_params, float tau_lo,
                         float tau_hi, void* u, uint8_t* flags, unsigned long long* counters,
-                        hipStream_t s) {
+                        double* wave_partial, hipStream_t s) {
   // probabilities to logit thresholds (monotone, so the decisions agree)
   auto logit = [](float p) -> float {
     if (!(p > 0.0f)) return -INFINITY;
     if (!(p < 1.0f)) return INFINITY;
     return (float)log((double)p / (1.0 - (double)p));
   };
-  LimitArgs la{M, mlp_params, logit(tau_lo), logit(tau_hi)};
+  LimitArgs la{M, mlp_params, logit(tau_lo), logit(tau_hi), wave_partial};
   return dispatch<RunLimit>(eq, k, ph, g, bc, la, mlp_params != nullptr, u, lay, flags, counters, s);
 }
 hipError_t launch_mlp_features(int k, int lay, const Geo& g, const BCDev& bc, double M,

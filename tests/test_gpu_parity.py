@@ -368,3 +368,42 @@ def test_error_against_restricted_reference(K, r, ry, kc, kf):
     sb = solver(K, lmb, 1, "llf")
     with pytest.raises(K.CrkdgError):
         sc.crkdg_error_ref(sb, 0)
+
+
+def test_limit_dt_equals_limit_then_compute_dt(K):
+    """the fused limiter + next-step dt gives bitwise the state, flags and dt
+    of crkdg_limit followed by crkdg_compute_dt (TVB and learned modes)"""
+    import torch
+    cfg = W.config("c5", scale=32)  # 128 x 32, boundary tiles and a ragged last block
+    params, xi = W.shock_problem(2001, cfg["nx"], cfg["ny"])
+    ghost = W.post_shock_conserved(params[0])
+    rng = np.random.default_rng(4)
+    P = torch.from_numpy((0.4 * rng.standard_normal(O.N_MLP_PARAMS)).astype(np.float32)).cuda()
+    for precision in (K.FP64, K.FP32_MIXED):
+        for mlp in (False, True):
+            out = []
+            for fused in (False, True):
+                x0, x1, y0, y1 = cfg["box"]
+                lm = K.make_mesh(2, cfg["nx"] - 3, cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1,
+                                 bc=(2, 1, 1, 1), bc_state=[ghost] * 4, equation=K.EQ_EULER,
+                                 precision=precision)
+                s = K.Solver(lm, 2, K.FLUX_LLF, 3)
+                p2, xi2 = W.shock_problem(2001, cfg["nx"] - 3, cfg["ny"])
+                s.crkdg_project(K.IC_SHOCK, p2, aux=torch.from_numpy(xi2).cuda())
+                s.crkdg_limit(50.0)
+                s.crkdg_step(0.1 / s.crkdg_max_wavespeed())
+                flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+                dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+                if fused:
+                    s.crkdg_limit_dt(50.0, 0.1, dt, flags, params=P if mlp else None,
+                                     tau_lo=0.3, tau_hi=0.7)
+                else:
+                    if mlp:
+                        s.crkdg_limit_mlp(50.0, P, 0.3, 0.7, flags, count=False)
+                    else:
+                        s.crkdg_limit(50.0, flags, count=False)
+                    s.crkdg_compute_dt(0.1, dt)
+                out.append((s.crkdg_get_state(), flags.cpu().numpy(), dt.item()))
+            assert np.array_equal(out[0][0], out[1][0])
+            assert np.array_equal(out[0][1], out[1][1])
+            assert out[0][2] == out[1][2] and out[0][2] > 0.0
