@@ -208,7 +208,8 @@ def main():
 
     forms = {}
     plan = [("fp32-bulk + MLP", K.FP32_MIXED, mlp)] if mlp is not None else []
-    plan += [("fp64 + TVB", K.FP64, None), ("fp32-bulk + TVB", K.FP32_MIXED, None)]
+    plan += [("fp64 + TVB", K.FP64, None), ("fp32-bulk + TVB", K.FP32_MIXED, None),
+             ("fp32-inner + TVB", K.FP32_INNER, None)]
     for name, prec, ind in plan:
         forms[name] = run_form(K, W, args, prec, ind)
         log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
@@ -236,6 +237,11 @@ def main():
                        "roofline": plain["roofline"], "kernels": plain["kernels"]},
         "fp32_bulk_tvb": {"value": tvb32["value"], "ms_per_step": tvb32["ms_per_step"],
                           "kernels": tvb32["kernels"]},
+        "fp32_inner_tvb": {"value": forms["fp32-inner + TVB"]["value"],
+                           "ms_per_step": forms["fp32-inner + TVB"]["ms_per_step"],
+                           "kernels": forms["fp32-inner + TVB"]["kernels"],
+                           "form": "FP32 inner stages (FP32 increments over u^n), FP64 final "
+                                   "stage and limiter"},
         "speedup_vs_fp64_plain": head["value"] / plain["value"],
     }
     if mlp is not None:
@@ -300,7 +306,7 @@ def run_form(K, W, args, precision, mlp=None):
 
     dofs = s.ncells * s.nmodes * s.ncomp
     stages_final = 2  # scheme (eq:3): b = (1/4, 0, 3/4)
-    stage_bytes = s.ncells * s.nmodes * s.ncomp * (4 if precision == K.FP32_MIXED else 8)
+    stage_bytes = s.state_bytes  # stored stages use the state's layout
     kern = {}
     for cls, (tms, cnt) in prof.items():
         by = algorithmic_bytes(cls, s.state_bytes, stage_bytes, s.ncells, stages_final)
@@ -310,7 +316,7 @@ def run_form(K, W, args, precision, mlp=None):
     by = algorithmic_bytes(dom, s.state_bytes, stage_bytes, s.ncells, stages_final)
     achieved = by / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e9
     traffic = measured_traffic({"final": "final2", "inner": "inner", "limit": "limit"}.get(dom, dom),
-                               "fp32" if precision == K.FP32_MIXED else "fp64")
+                               {K.FP32_MIXED: "fp32", K.FP64: "fp64"}.get(precision, "fp32inner"))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_launch": by}
@@ -392,6 +398,7 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
 
     forms = (("fp64 + TVB", K.FP64, None, False),
              ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True),
+             ("fp32-inner + TVB", K.FP32_INNER, None, False),
              ("fp32-bulk + TVB", K.FP32_MIXED, None, False),
              ("fp32-bulk + MLP", K.FP32_MIXED, mlp, False))
     per_seed = {}

@@ -26,9 +26,19 @@
  *    phi_mode = P_m(xi) P_n(eta), mode = m + (k+1) n (1D: mode = m); mode 0 is
  *    the cell average.  Components: advection 1; 1D Euler (rho, rho w, E);
  *    2D Euler (rho, rho u, rho v, E), gamma from the mesh.
- *  - Mixed-precision layout (CRKDG_FP32_MIXED): the DOF buffer holds the
- *    cell averages avg[comp][cell] in FP64 followed by the higher modes
- *    hi[comp][mode-1][cell] in FP32.  Conversion happens in set/get_state.
+ *  - Precision forms (2D Euler, k >= 1):
+ *    CRKDG_FP32_MIXED ("FP32 bulk"): inner and final stages compute in FP32;
+ *    the cell averages, the face-flux sums of the final stage and the
+ *    limiter's tests stay FP64.  The DOF buffer holds the cell averages
+ *    avg[comp][cell] in FP64 followed by the higher modes
+ *    hi[comp][mode-1][cell] in FP32; conversion happens in set/get_state.
+ *    CRKDG_FP32_INNER: only the inner stages compute in FP32 (the
+ *    increments u^(i) - u^n accumulate in FP32; a stored stage is formed as
+ *    u^n + increment in FP64); the final stage and the limiter are FP64 and
+ *    the DOF buffer has the FP64 layout.  Section 3.3 (the
+ *    perturbed-RK theorem it cites): perturbing only the inner-stage
+ *    operator evaluations by O(eps) perturbs a step by O(eps dt^2), so this
+ *    form keeps the FP64 accuracy.
  *  - Errors: every int-returning call returns CRKDG_OK (0) or a negative code;
  *    crkdg_strerror maps it to text.  Kernel launch failures return
  *    CRKDG_EHIP.  Invalid arguments never reach a kernel.
@@ -53,7 +63,7 @@ extern "C" {
 enum { CRKDG_EQ_ADVECTION = 0, CRKDG_EQ_EULER = 1 };
 enum { CRKDG_FLUX_UPWIND = 0, CRKDG_FLUX_LLF = 1 };
 enum { CRKDG_BC_PERIODIC = 0, CRKDG_BC_TRANSMISSIVE = 1, CRKDG_BC_DIRICHLET = 2 };
-enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1 };
+enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1, CRKDG_FP32_INNER = 2 };
 enum { CRKDG_OP_LOC = 0, CRKDG_OP_DG = 1 };
 
 /* initial conditions / exact solutions known to the library */
@@ -78,7 +88,7 @@ typedef struct {
   int equation;             /* CRKDG_EQ_* */
   double adv[2];            /* advection velocity */
   double gamma;             /* ratio of specific heats (Euler) */
-  int precision;            /* CRKDG_FP64 | CRKDG_FP32_MIXED */
+  int precision;            /* CRKDG_FP64 | CRKDG_FP32_MIXED | CRKDG_FP32_INNER */
 } crkdg_mesh;
 
 typedef struct crkdg_state crkdg_state;

@@ -33,7 +33,7 @@ struct crkdg_state {
   size_t S;       // bytes of one state (device layout lay)
   size_t S_stage; // bytes of one stored stage state (layout lay_stage)
   int lay, lay_stage;
-  bool mixed;
+  int prec;  // Prec: P64, PBULK or PINNER
   // per-launch timing (measurement only)
   bool prof;
   int prof_max;
@@ -148,7 +148,9 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   if (!(mesh->x1 > mesh->x0) || (mesh->dim == 2 && !(mesh->y1 > mesh->y0))) return CRKDG_EINVAL;
   if (rk_stages < 1 || rk_stages > 4) return CRKDG_EINVAL;
   if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF) return CRKDG_EINVAL;
-  if (mesh->precision != CRKDG_FP64 && mesh->precision != CRKDG_FP32_MIXED) return CRKDG_EINVAL;
+  if (mesh->precision != CRKDG_FP64 && mesh->precision != CRKDG_FP32_MIXED &&
+      mesh->precision != CRKDG_FP32_INNER)
+    return CRKDG_EINVAL;
   for (int sd = 0; sd < 4; ++sd)
     if (mesh->bc[sd] < CRKDG_BC_PERIODIC || mesh->bc[sd] > CRKDG_BC_DIRICHLET) return CRKDG_EINVAL;
   int eq;
@@ -163,8 +165,8 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     return CRKDG_EINVAL;
   }
   if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN) return CRKDG_EUNSUPPORTED;
-  // the FP32-bulk form is built for 2D Euler, k = 1..3
-  if (mesh->precision == CRKDG_FP32_MIXED && (eq != EQ_EULER2 || k < 1)) return CRKDG_EUNSUPPORTED;
+  // the FP32 forms are built for 2D Euler, k = 1..3
+  if (mesh->precision != CRKDG_FP64 && (eq != EQ_EULER2 || k < 1)) return CRKDG_EUNSUPPORTED;
   crkdg_state* st = new (std::nothrow) crkdg_state();
   if (!st) return CRKDG_EINVAL;
   st->mesh = *mesh;
@@ -208,18 +210,18 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     case 3: set_tableau_internal(st, 3, E3_c, E3_A, E3_b); break;
     default: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
   }
-  st->mixed = mesh->precision == CRKDG_FP32_MIXED;
-  if (st->mixed) {
+  st->prec = mesh->precision == CRKDG_FP32_MIXED ? PBULK
+             : mesh->precision == CRKDG_FP32_INNER ? PINNER : P64;
+  // stored stages use the state's layout
+  if (st->prec == PBULK) {
     st->lay = LMIX;
-    st->lay_stage = LMIX;
     st->S = (size_t)st->nc * g.N * sizeof(double) + (size_t)st->nc * (st->nb - 1) * g.N * sizeof(float);
-    st->S_stage = st->S;
   } else {
     st->lay = L64;
-    st->lay_stage = L64;
     st->S = (size_t)st->nc * st->nb * g.N * sizeof(double);
-    st->S_stage = st->S;
   }
+  st->lay_stage = st->lay;
+  st->S_stage = st->S;
   st->bound = false;
   st->cur = 0;
   st->t = 0.0;
@@ -294,7 +296,7 @@ int crkdg_set_state(crkdg_state* st, const double* host) {
   if (!st || !host) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   hipError_t e;
-  if (!st->mixed) {
+  if (st->lay != LMIX) {
     e = hipMemcpyAsync(cur_ptr(st), host, st->S, hipMemcpyHostToDevice, st->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
   } else {
@@ -312,7 +314,7 @@ int crkdg_get_state(const crkdg_state* st, double* host) {
   if (!st || !host) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   hipError_t e;
-  if (!st->mixed) {
+  if (st->lay != LMIX) {
     e = hipMemcpyAsync(host, cur_ptr(st), st->S, hipMemcpyDeviceToHost, st->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
   } else {
@@ -407,9 +409,9 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
     // a stage with b_i == 0 is still needed by later stages only through the
     // register chain, so it is not stored
     ProfScope ps(st, KC_INNER);
-    e = launch_inner(st->eq, st->k, st->mixed, st->ph, st->geo, ia, st->stream);
+    e = launch_inner(st->eq, st->k, st->prec, st->ph, st->geo, ia, st->stream);
   } else if (s > 1) {
-    if (st->mixed) return CRKDG_EUNSUPPORTED;  // materialised path: FP64 layout only
+    if (st->prec != P64) return CRKDG_EUNSUPPORTED;  // materialised path: FP64 only
     // general tableau: materialise L_j = loc(u^(j)) and combine
     const long long n = (long long)(st->S / sizeof(double));
     for (int i = 1; i < s && e == hipSuccess; ++i) {
@@ -448,7 +450,7 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
   fa.ns = ns;
   {
     ProfScope ps(st, KC_FINAL);
-    e = launch_final(st->eq, st->k, st->mixed, st->ph, st->geo, st->bc, fa, st->stream);
+    e = launch_final(st->eq, st->k, st->prec, st->ph, st->geo, st->bc, fa, st->stream);
   }
   if (e != hipSuccess) return CRKDG_EHIP;
   st->cur ^= 1;
@@ -650,7 +652,7 @@ int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_
   if (!st || !in || !out || (op != CRKDG_OP_LOC && op != CRKDG_OP_DG)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   if (in == out) return CRKDG_EINVAL;
-  if (st->mixed) return CRKDG_EUNSUPPORTED;
+  if (st->lay != L64) return CRKDG_EUNSUPPORTED;
   hipError_t e;
   if (op == CRKDG_OP_LOC) {
     e = launch_loc(st->eq, st->k, st->ph, st->geo, (const double*)in, (double*)out, st->stream);
@@ -666,7 +668,7 @@ int crkdg_apply_op(crkdg_state* st, int op, const void* in, void* out, double t_
     fa.w[0] = 1.0;
     fa.tst[0] = t_bc;
     fa.dt = -1.0;
-    e = launch_final(st->eq, st->k, false, st->ph, st->geo, st->bc, fa, st->stream);
+    e = launch_final(st->eq, st->k, P64, st->ph, st->geo, st->bc, fa, st->stream);
   }
   return hip_rc(e);
 }
@@ -675,7 +677,7 @@ int crkdg_combine(crkdg_state* st, void* out, const void* base, int n, const dou
                   const void* const* X) {
   if (!st || !out || n < 0 || n > MAXS || (n > 0 && (!coef || !X))) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (st->mixed) return CRKDG_EUNSUPPORTED;
+  if (st->lay != L64) return CRKDG_EUNSUPPORTED;
   for (int j = 0; j < n; ++j)
     if (!X[j] || !isfinite(coef[j])) return CRKDG_EINVAL;
   const long long len = (long long)(st->S / sizeof(double));

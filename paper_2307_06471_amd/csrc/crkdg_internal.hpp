@@ -38,6 +38,15 @@ struct PhysDev {
 // one equation/dimension/degree selection
 enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2 };
 
+// compute precision of a state's step
+//  P64:    FP64 throughout (the plain method)
+//  PBULK:  FP32 inner and final stages, FP64 cell averages and face sums
+//  PINNER: FP32 inner stages (increments over u^n accumulated in FP32, each
+//          stored stage formed as u^n + increment in FP64), FP64 final stage
+//          (Section 3.3: perturbing only the inner-stage operator evaluations
+//          by O(eps) perturbs a step by O(eps dt^2))
+enum Prec { P64 = 0, PBULK = 1, PINNER = 2 };
+
 struct InnerArgs {
   const void* un;
   int lay_in;            // layout of u^n
@@ -64,10 +73,10 @@ struct FinalArgs {
 };
 
 // launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error.
-// mixed: compute type float (FP32 bulk) instead of double.
-hipError_t launch_inner(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+// prec: one of Prec (layouts and compute types follow from it).
+hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const InnerArgs& a, hipStream_t s);
-hipError_t launch_final(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, const FinalArgs& a, hipStream_t s);
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s);

@@ -302,26 +302,68 @@ struct Occ {
   static constexpr int final_ = F32 ? FINAL_OCC_F32 : FINAL_OCC_F64;
 };
 
-template <class EQ, int K>
+// LIN: layout of u^n; LOUT: layout of the stored stages; INC: accumulate
+// the increments u^(i) - u^n in the compute precision and store u^n + the
+// increment in FP64 (the FP32-inner form)
+template <class EQ, int K, int LIN, int LOUT, bool INC>
 __global__ __launch_bounds__(256, (Occ<EQ, K>::inner)) void k_inner(PhysDev ph, Geo g, InnerArgs a) {
   using R = typename EQ::Real;
-  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB, LAY = StepLayout<EQ>::value;
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   if (cell >= g.N) return;
   const EQ eq = make_eq<EQ>(ph);
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
   R u[NC][NB];
-  load_state<R, NC, NB, LAY>(a.un, g.N, cell, u);
-#pragma unroll 1
-  for (int i = 1; i < a.s; ++i) {
-    R acc[NC][NB];
-    load_state<R, NC, NB, LAY>(a.un, g.N, cell, acc);
-    loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[i]), R(g.inv_dx), R(g.inv_dy), acc);
+  load_state<R, NC, NB, LIN>(a.un, g.N, cell, u);
+  // INC: u^n in the compute precision stays in registers (the stages are
+  // evaluated at u^n + increment)
+  R un[INC ? NC : 1][INC ? NB : 1];
+  if constexpr (INC) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
-    if ((a.store_mask >> i) & 1) store_state<R, NC, NB, LAY>(a.stage[i], g.N, cell, u);
+      for (int b = 0; b < NB; ++b) un[c][b] = u[c][b];
+  }
+#pragma unroll 1
+  for (int i = 1; i < a.s; ++i) {
+    R acc[NC][NB];
+    if constexpr (INC) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[c][b] = R(0);
+    } else {
+      load_state<R, NC, NB, LIN>(a.un, g.N, cell, acc);
+    }
+    loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[i]), R(g.inv_dx), R(g.inv_dy), acc);
+    if constexpr (INC) {
+      // acc is the increment; the next stage is evaluated at u^n + acc, and a
+      // stored stage is u^n + acc formed in FP64 (one rounding)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) u[c][b] = un[c][b] + acc[c][b];
+      if ((a.store_mask >> i) & 1) {
+        static_assert(LIN == L64 && LOUT == L64, "FP64 state and stages");
+        const unsigned o8 = (unsigned)cell * 8u;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const auto rin = rsrc(byte_add(a.un, (long long)c * NB * g.N * 8));
+          const auto rout = rsrc(byte_add(a.stage[i], (long long)c * NB * g.N * 8));
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const unsigned so = (unsigned)(b * g.N * 8);
+            bstore<double>(bload<double>(rin, o8, so) + (double)acc[c][b], rout, o8, so);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
+      if ((a.store_mask >> i) & 1) store_state<R, NC, NB, LOUT>(a.stage[i], g.N, cell, u);
+    }
   }
 }
 
@@ -410,7 +452,7 @@ struct FinalTile {
 // 3.4: boundary data enter only here).  Uses the same trace functions as the
 // owner of the neighbour cell, so both tiles sharing a face see identical
 // traces and compute identical fluxes.
-template <class EQ, int K>
+template <class EQ, int K, int LAY>
 __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, const BCDev& bc,
                                            const void* __restrict__ S, int side, int ci, int cj,
                                            double tb, typename EQ::Real (&out)[EQ::NC][K + 1]) {
@@ -455,7 +497,7 @@ __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, cons
     }
   }
   R U[NC][NB];
-  load_state<R, NC, NB, StepLayout<EQ>::value>(S, g.N, (long long)nj * g.nx + ni, U);
+  load_state<R, NC, NB, LAY>(S, g.N, (long long)nj * g.nx + ni, U);
   switch (face) {
     case 0: trace_x<-1, EQ, K, R>(U, out); break;
     case 1: trace_x<+1, EQ, K, R>(U, out); break;
@@ -493,13 +535,14 @@ struct FinalSmem {
   static constexpr size_t BYTES = TRACE_BYTES > G_BYTES ? TRACE_BYTES : G_BYTES;
 };
 
-template <class EQ, int K>
+// LAY: layout of u^n, of the stored stages and of u^{n+1}
+template <class EQ, int K, int LAY>
 __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typename EQ::Real>::TY,
                              (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
                                                                  FinalArgs a) {
   using R = typename EQ::Real;
   constexpr int TX = FinalTile<R>::TX, TY = FinalTile<R>::TY, NT = TX * TY;
-  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q, LAY = StepLayout<EQ>::value;
+  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q;
   using SM = FinalSmem<R, NV, TX, TY>;
   // face points of the tile: x faces (TX + 1 per row, TY rows), then y faces
   constexpr int NXP = Q * (TX + 1) * TY, NFP = NXP + Q * TX * (TY + 1);
@@ -609,7 +652,7 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
     }
     if (hside >= 0) {
       R h[NC][Q];
-      halo_trace<EQ, K>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
+      halo_trace<EQ, K, LAY>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -1517,41 +1560,53 @@ template <template <class, int> class F, class... A>
 hipError_t dispatch(int eq, int k, A&&... args) {
   return dispatch_r<F, double>(eq, k, args...);
 }
-// FP32-bulk kernels exist for 2D Euler, k = 1..3
-template <template <class, int> class F, class... A>
-hipError_t dispatch_mixed(int eq, int k, A&&... args) {
+// the FP32 forms exist for 2D Euler, k = 1..3
+template <template <class, int> class F, class R, class... A>
+hipError_t dispatch_euler(int eq, int k, A&&... args) {
   if (eq != EQ_EULER2) return hipErrorInvalidValue;
   switch (k) {
-    case 1: return F<Euler2<float>, 1>::run(args...);
-    case 2: return F<Euler2<float>, 2>::run(args...);
-    case 3: return F<Euler2<float>, 3>::run(args...);
+    case 1: return F<Euler2<R>, 1>::run(args...);
+    case 2: return F<Euler2<R>, 2>::run(args...);
+    case 3: return F<Euler2<R>, 3>::run(args...);
     default: return hipErrorInvalidValue;
   }
+}
+template <template <class, int> class F, class... A>
+hipError_t dispatch_mixed(int eq, int k, A&&... args) {
+  return dispatch_euler<F, float>(eq, k, args...);
 }
 
 static unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <class EQ, int K>
-struct RunInner {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const InnerArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_inner<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, a);
-    return hipGetLastError();
-  }
-};
-template <class EQ, int K>
-struct RunFinal {
-  static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const FinalArgs& a,
-                        hipStream_t s) {
-    if constexpr (EQ::DIM == 2) {
-      using T = FinalTile<typename EQ::Real>;
-      dim3 grid(nblk(g.nx, T::TX), nblk(g.ny, T::TY));
-      hipLaunchKernelGGL((k_final2<EQ, K>), grid, dim3(T::TX * T::TY), 0, s, ph, g, bc, a);
-    } else {
-      hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
+template <int LIN, int LOUT, bool INC>
+struct InnerL {
+  template <class EQ, int K>
+  struct Run {
+    static hipError_t run(const PhysDev& ph, const Geo& g, const InnerArgs& a, hipStream_t s) {
+      hipLaunchKernelGGL((k_inner<EQ, K, LIN, LOUT, INC>), dim3(nblk(g.N, 256)), dim3(256), 0, s,
+                         ph, g, a);
+      return hipGetLastError();
     }
-    return hipGetLastError();
-  }
+  };
 };
+template <int LAY>
+struct FinalL {
+  template <class EQ, int K>
+  struct Run {
+    static hipError_t run(const PhysDev& ph, const Geo& g, const BCDev& bc, const FinalArgs& a,
+                          hipStream_t s) {
+      if constexpr (EQ::DIM == 2) {
+        using T = FinalTile<typename EQ::Real>;
+        dim3 grid(nblk(g.nx, T::TX), nblk(g.ny, T::TY));
+        hipLaunchKernelGGL((k_final2<EQ, K, LAY>), grid, dim3(T::TX * T::TY), 0, s, ph, g, bc, a);
+      } else {
+        hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
+      }
+      return hipGetLastError();
+    }
+  };
+};
+
 template <class EQ, int K>
 struct RunLoc {
   static hipError_t run(const PhysDev& ph, const Geo& g, const double* in, double* out,
@@ -1635,14 +1690,20 @@ struct RunLimit {
   }
 };
 
-hipError_t launch_inner(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const InnerArgs& a, hipStream_t s) {
-  return mixed ? dispatch_mixed<RunInner>(eq, k, ph, g, a, s) : dispatch<RunInner>(eq, k, ph, g, a, s);
+  switch (prec) {
+    case PBULK: return dispatch_mixed<InnerL<LMIX, LMIX, false>::template Run>(eq, k, ph, g, a, s);
+    case PINNER: return dispatch_mixed<InnerL<L64, L64, true>::template Run>(eq, k, ph, g, a, s);
+    default: return dispatch<InnerL<L64, L64, false>::template Run>(eq, k, ph, g, a, s);
+  }
 }
-hipError_t launch_final(int eq, int k, bool mixed, const PhysDev& ph, const Geo& g,
+hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, const FinalArgs& a, hipStream_t s) {
-  return mixed ? dispatch_mixed<RunFinal>(eq, k, ph, g, bc, a, s)
-               : dispatch<RunFinal>(eq, k, ph, g, bc, a, s);
+  switch (prec) {
+    case PBULK: return dispatch_mixed<FinalL<LMIX>::template Run>(eq, k, ph, g, bc, a, s);
+    default: return dispatch<FinalL<L64>::template Run>(eq, k, ph, g, bc, a, s);  // FP64 final stage
+  }
 }
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s) {

@@ -62,6 +62,11 @@ def _create(**kw):
     (dict(gamma=1.0), K.CRKDG_EINVAL),
     (dict(x1=0.0), K.CRKDG_EINVAL),
     (dict(bc=(7, 0, 0, 0)), K.CRKDG_EINVAL),
+    (dict(precision=3), K.CRKDG_EINVAL),
+    (dict(precision=K.FP32_INNER, equation=K.EQ_ADVECTION), K.CRKDG_EUNSUPPORTED),
+    (dict(precision=K.FP32_INNER, k=0), K.CRKDG_EUNSUPPORTED),
+    (dict(precision=K.FP32_MIXED, k=0), K.CRKDG_EUNSUPPORTED),
+    (dict(nx=1 << 15, ny=1 << 14), K.CRKDG_EINVAL),  # a component slab would reach 4 GiB
 ])
 def test_create_rejects_bad_arguments(kw, code):
     rc, _ = _create(**kw)
@@ -79,6 +84,16 @@ def test_create_sizes_and_unbound_errors():
     assert L.crkdg_current_dofs(h) is None
     assert L.crkdg_bind(h, C.c_void_p(0x1001), C.c_void_p(0x2000), None) == K.CRKDG_EINVAL
     L.crkdg_destroy(h)
+
+
+def test_state_sizes_of_the_precision_forms():
+    L = K.lib()
+    for prec, nbytes in ((K.FP64, 4 * 9 * 64 * 8), (K.FP32_INNER, 4 * 9 * 64 * 8),
+                         (K.FP32_MIXED, 4 * 64 * 8 + 4 * 8 * 64 * 4)):
+        rc, h = _create(precision=prec)
+        assert rc == 0
+        assert L.crkdg_state_bytes(h) == nbytes
+        L.crkdg_destroy(h)
 
 
 def test_set_tableau_validation():

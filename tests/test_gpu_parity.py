@@ -313,6 +313,65 @@ def test_mixed_density_wave_run(K, k, tab, stages):
         assert abs(s.crkdg_total(cc) - m0[cc]) < 1e-13 * max(1.0, abs(m0[cc]))
 
 
+def test_fp32_inner_density_wave_run(K):
+    """FP32 inner stages (stored as FP32 increments over u^n), FP64 final
+    stage: Section 3.3's perturbation argument says the inner-stage error
+    enters a step only at O(eps dt^2).  Same run as above (Q^2, scheme (eq:3),
+    48 x 40, 60 steps): far closer to the FP64 oracle than the FP32-bulk form,
+    and conservative to FP64 round-off."""
+    cfg = dict(W.config("c3"), nx=48, ny=40)
+    P = cfg["ic_params"]
+    k, tab = 2, "eq3"
+    errs = {}
+    for prec in (K.FP32_INNER, K.FP32_MIXED):
+        x0, x1, y0, y1 = cfg["box"]
+        lm = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(0, 0, 0, 0),
+                         equation=K.EQ_EULER, precision=prec)
+        om = O.Mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(0, 0, 0, 0),
+                    equation=O.EQ_EULER, flux=O.FLUX_LLF)
+        s = K.Solver(lm, k, K.FLUX_LLF, 3)
+        s.crkdg_project(K.IC_EULER_WAVE, P)
+        u = O.project(om, k, O.IC_EULER_WAVE, P)
+        m0 = [s.crkdg_total(c) for c in range(4)]
+        dt = cfg["cfl"] / O.max_wavespeed(om, k, u)
+        A, b, c = (np.array(v, float) for v in W.TABLEAU[tab])
+        for n in range(60):
+            s.crkdg_step(dt)
+            u = O.step_crkdg(om, k, (A, b, c), n * dt, dt, u)
+        errs[prec] = l2_rel(s.crkdg_get_state(), u)
+        if prec == K.FP32_INNER:
+            for cc in range(4):
+                assert abs(s.crkdg_total(cc) - m0[cc]) < 1e-13 * max(1.0, abs(m0[cc]))
+    print(f"[fp32-inner] rel L2 vs FP64 oracle: inner {errs[K.FP32_INNER]:.2e}, "
+          f"bulk {errs[K.FP32_MIXED]:.2e}", flush=True)
+    assert errs[K.FP32_INNER] < 1e-7
+    assert errs[K.FP32_INNER] < 0.1 * errs[K.FP32_MIXED]
+
+
+def test_fp32_inner_shock_step_matches_oracle(K):
+    """one step of the shock workload (128 x 32, Dirichlet inflow, limiter
+    after) in the FP32-inner form against the FP64 oracle"""
+    import torch
+    cfg = W.config("c5", scale=32)
+    params, xi = W.shock_problem(2000, cfg["nx"], cfg["ny"])
+    ghost = W.post_shock_conserved(params[0])
+    x0, x1, y0, y1 = cfg["box"]
+    lm = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(2, 1, 1, 1),
+                     bc_state=[ghost] * 4, equation=K.EQ_EULER, precision=K.FP32_INNER)
+    om = O.Mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1, bc=(2, 1, 1, 1),
+                bc_state=[ghost] * 4, equation=O.EQ_EULER, flux=O.FLUX_LLF)
+    s = K.Solver(lm, 2, K.FLUX_LLF, 3)
+    s.crkdg_project(K.IC_SHOCK, params, aux=torch.from_numpy(xi).cuda())
+    s.crkdg_limit(50.0)
+    u = s.crkdg_get_state()
+    dt = cfg["cfl"] / O.max_wavespeed(om, 2, u)
+    s.crkdg_step(dt)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    ref = O.step_crkdg(om, 2, (A, b, c), 0.0, dt, u)
+    got = s.crkdg_get_state()
+    assert l2_rel(got, ref) < 1e-8
+
+
 def test_mixed_shock_step_and_limiter(K):
     cfg = W.config("c5", scale=32)  # 128 x 32
     params, xi = W.shock_problem(2000, cfg["nx"], cfg["ny"])
