@@ -1,0 +1,51 @@
+"""Host-side logic of the benchmark and of the profile summaries (no GPU)."""
+import os
+import subprocess
+import sys
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2307_06471_amd import profsummary as PS  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_of_the_step_kernels():
+    S, N = 160, 1000  # FP32-bulk Q2 state bytes per cell x cells
+    state = S * N
+    # scheme (eq:3): final-stage states u^n and u^(3); the stored stage has the state's layout
+    assert bench.algorithmic_bytes("inner", state, state, N, 2) == 2 * state
+    assert bench.algorithmic_bytes("final", state, state, N, 2) == 3 * state
+    assert bench.algorithmic_bytes("limit", state, state, N, 2) == state + N
+    assert bench.algorithmic_bytes("dt", state, state, N, 2) == ((N + 255) // 256) * 8
+    assert bench.algorithmic_bytes("other", state, state, N, 2) is None
+
+
+def test_traffic_summary_round_trip_and_source_gate(tmp_path):
+    p = tmp_path / "k_final2_fp32_traffic.txt"
+    p.write_text("# HBM traffic per launch of k\n\n  a command line: with colons\n"
+                 f"kernel source hash: {PS.kernel_source_hash()}\n"
+                 "traffic_bytes_per_launch: 123456\n")
+    d = PS.read_traffic(str(p))
+    assert d["traffic_bytes_per_launch"] == "123456"
+    assert d["kernel source hash"] == PS.kernel_source_hash()
+    assert PS.read_traffic(str(tmp_path / "missing.txt")) is None
+    h = PS.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0 and h == PS.kernel_source_hash()
+
+
+def test_committed_traffic_summaries_parse():
+    for tag in ("fp32", "fp64"):
+        d = PS.read_traffic(os.path.join(ROOT, "profiles", f"k_final2_{tag}_traffic.txt"))
+        assert d is not None
+        assert float(d["traffic_bytes_per_launch"]) > 0
+        assert float(d["fetch_factor"]) > 0 and float(d["write_factor"]) > 0
