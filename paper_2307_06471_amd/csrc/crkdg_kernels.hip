@@ -29,6 +29,9 @@
 #include "dg_core.hpp"
 #include "mlp_core.hpp"
 
+#ifndef LIMIT_OCC
+#define LIMIT_OCC 4
+#endif
 #ifndef INNER_OCC_F32
 #define INNER_OCC_F32 2
 #endif
@@ -315,10 +318,13 @@ __global__ __launch_bounds__(256, (Occ<EQ, K>::inner)) void k_inner(PhysDev ph, 
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
   R u[NC][NB];
   load_state<R, NC, NB, LIN>(a.un, g.N, cell, u);
-  // INC: u^n in the compute precision stays in registers (the stages are
-  // evaluated at u^n + increment)
-  R un[INC ? NC : 1][INC ? NB : 1];
-  if constexpr (INC) {
+  // u^n in the compute precision stays in registers when KEEP (every stage
+  // starts from it; re-reading it after a stage's arithmetic mostly misses
+  // the L2 and doubles the kernel's HBM reads); the FP64 form re-reads it,
+  // since another 72 registers would halve its occupancy
+  constexpr bool KEEP = INC || sizeof(R) == 4;
+  R un[KEEP ? NC : 1][KEEP ? NB : 1];
+  if constexpr (KEEP) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -332,6 +338,11 @@ __global__ __launch_bounds__(256, (Occ<EQ, K>::inner)) void k_inner(PhysDev ph, 
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[c][b] = R(0);
+    } else if constexpr (KEEP) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
     } else {
       load_state<R, NC, NB, LIN>(a.un, g.N, cell, acc);
     }
@@ -925,20 +936,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   __syncthreads();
   return r;
 }
+// maximum over the block (a NaN anywhere gives NaN): lane exchanges within
+// each wavefront, then the NT / 64 wavefront maxima through sh
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
 #pragma unroll
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if (t < o) {
-      const double w = sh[t + o];
-      if (w > sh[t] || w != w) sh[t] = w;
-    }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o);
+    if (w > v || w != w) v = w;
   }
-  const double r = sh[0];
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) {
+    const double w = sh[k];
+    if (w > r || w != w) r = w;
+  }
   __syncthreads();
   return r;
 }
@@ -1221,6 +1236,35 @@ __device__ void euler_eigvec(double gamma, const EulerPrim& w, int d, double* L,
     }
 }
 
+// A sufficient condition for physical_points from the modal coefficients:
+// every basis function is at most 1 in magnitude at the Gauss points, so
+// rho_q >= avg - sum |modes| (likewise E), |m_q| <= |avg| + sum |modes|, and
+// rho_q E_q - |m_q|^2 / 2 >= rho_lo E_lo - (mx_hi^2 + my_hi^2) / 2.  The
+// relative margin keeps the rounding of these few operations from turning a
+// failing cell into a passing one; cells that do not clear it take the exact
+// test, so the decisions are those of physical_points.  avg: the cell
+// averages; rabs[c]: the sum of |mode| over the higher modes of component c.
+__device__ __forceinline__ bool surely_physical_sums(const double (&avg)[4], const double (&rabs)[4]) {
+  const double rlo = avg[0] - rabs[0], elo = avg[3] - rabs[3];
+  const double mx = fabs(avg[1]) + rabs[1], my = fabs(avg[2]) + rabs[2];
+  const double lhs = rlo * elo, rhs = 0.5 * (mx * mx + my * my);
+  return rlo > 0.0 && elo > 0.0 && lhs - rhs > 1e-10 * lhs;
+}
+template <int K>
+__device__ __forceinline__ bool surely_physical(const double (&U)[4][(K + 1) * (K + 1)]) {
+  constexpr int NB = (K + 1) * (K + 1);
+  double avg[4], r[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 1; b < NB; ++b) t += fabs(U[c][b]);
+    avg[c] = U[c][0];
+    r[c] = t;
+  }
+  return surely_physical_sums(avg, r);
+}
+
 // density and pressure positive at the operator's volume and face points
 template <int K>
 __device__ bool physical_points(double gamma, const double (&U)[4][(K + 1) * (K + 1)]) {
@@ -1284,208 +1328,363 @@ struct LimitArgs {
   double* wave_partial; // if set: per-block max of the cell wave speeds (dt of the next step)
 };
 
+// one mode of component c of a cell, as double
+template <int NC, int NB, int LAY>
+__device__ __forceinline__ double load_mode(const void* __restrict__ p, long long N, int c, int b,
+                                            unsigned cell) {
+  if constexpr (LAY == L64) {
+    return bload<double>(rsrc(byte_add(p, (long long)c * NB * N * 8)), cell * 8u,
+                         (unsigned)(b * N * 8));
+  } else if constexpr (LAY == LMIX) {
+    if (b == 0) return bload<double>(rsrc(p), cell * 8u, (unsigned)(c * N * 8));
+    return (double)bload<float>(
+        rsrc(byte_add(p, (long long)NC * N * 8 + (long long)c * (NB - 1) * N * 4)), cell * 4u,
+        (unsigned)((b - 1) * N * 4));
+  } else {
+    return (double)bload<float>(rsrc(byte_add(p, (long long)c * NB * N * 4)), cell * 4u,
+                                (unsigned)(b * N * 4));
+  }
+}
+
+// mode index of degree deg along direction d (mode m + (k+1) n)
+template <int DIM, int Q>
+__device__ __forceinline__ constexpr int dir_mode(int d, int deg) {
+  return DIM == 1 ? deg : (d == 0 ? deg : deg * Q);
+}
+
+// cell averages of the two neighbours of cell (i, j) in direction d, with the
+// ghost rule of a boundary they lie beyond; dp = right - own, dm = own - left
+template <int NC, int NB, int LAY>
+__device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
+                                                 const void* __restrict__ u, int i, int j, int d,
+                                                 const double (&avg)[NC], double (&dp)[NC],
+                                                 double (&dm)[NC]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int s = k ? -1 : 1;
+    int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
+    const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
+    double qa[NC];
+    bool ghost = false;
+    if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
+      const int type = bc.type[side];
+      if (type == CRKDG_BC_TRANSMISSIVE) {
+        ghost = true;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qa[c] = avg[c];
+      } else if (type == CRKDG_BC_DIRICHLET) {
+        ghost = true;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
+      } else {  // periodic: one step across the domain
+        ni += ni < 0 ? g.nx : (ni >= g.nx ? -g.nx : 0);
+        nj += nj < 0 ? g.ny : (nj >= g.ny ? -g.ny : 0);
+      }
+    }
+    if (!ghost) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (k == 0)
+        dp[c] = qa[c] - avg[c];
+      else
+        dm[c] = avg[c] - qa[c];
+    }
+  }
+}
+
+// the TVB minmod troubled-cell test in direction d (characteristic variables
+// for Euler): a / at are the cell's forward / backward trace-average jumps
+template <class EQ>
+__device__ __forceinline__ bool tvb_troubled_dir(const PhysDev& ph, double Mh2, const EulerPrim& wp,
+                                                 int d, const double (&a)[EQ::NC],
+                                                 const double (&at)[EQ::NC],
+                                                 const double (&dp)[EQ::NC],
+                                                 const double (&dm)[EQ::NC]) {
+  constexpr int NC = EQ::NC;
+  double ca[NC], cat[NC], cp[NC], cm[NC];
+  if constexpr (EQ::EULER) {
+    double L[16], Rm[16];
+    euler_eigvec(ph.gamma, wp, d, L, Rm);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        ca[r] += L[r * 4 + c] * a[c];
+        cat[r] += L[r * 4 + c] * at[c];
+        cp[r] += L[r * 4 + c] * dp[c];
+        cm[r] += L[r * 4 + c] * dm[c];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[c]; cm[c] = dm[c];
+    }
+  }
+  bool tr = false;
+#pragma unroll
+  for (int r = 0; r < NC; ++r)
+    if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r]) tr = true;
+  return tr;
+}
+
+// limited P1 slope in direction d from the slope mode sl (characteristic
+// minmod for Euler, mapped back with the right eigenvectors)
+template <class EQ>
+__device__ __forceinline__ void tvb_slope_dir(const PhysDev& ph, double Mh2, const EulerPrim& wp,
+                                              int d, const double (&sl)[EQ::NC],
+                                              const double (&dp)[EQ::NC],
+                                              const double (&dm)[EQ::NC], double (&ns)[EQ::NC]) {
+  constexpr int NC = EQ::NC;
+  if constexpr (EQ::EULER) {
+    double L[16], Rm[16], lim[NC];
+    euler_eigvec(ph.gamma, wp, d, L, Rm);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        s1 += L[r * 4 + c] * sl[c];
+        s2 += L[r * 4 + c] * dp[c];
+        s3 += L[r * 4 + c] * dm[c];
+      }
+      lim[r] = tvb(s1, s2, s3, Mh2);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < NC; ++r) s += Rm[c * 4 + r] * lim[r];
+      ns[c] = s;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ns[c] = tvb(sl[c], dp[c], dm[c], Mh2);
+  }
+}
+
+// The limiter in two passes over a block of 256 cells.  The first pass reads
+// of each cell only what the troubled-cell decision needs (averages, the
+// trace-average jumps, the sum of |higher modes| for the positivity bound,
+// the neighbour averages) and decides: smooth cells that surely pass the
+// positivity test are done.  The rest (troubled cells, cells inside the
+// learned indicator's uncertainty band, cells whose positivity needs the
+// point test) go into a queue in LDS, and the second pass gives them to the
+// block's first lanes, so that the heavy work (the band's TVB test, the point
+// positivity test, the limited reconstruction and the store) runs on as few
+// wavefronts as there are such cells rather than on every wavefront that
+// holds one.  Each queued cell is processed the same whichever lane takes it.
+//
 // MLP = false: the TVB minmod test decides for every cell.  MLP = true
 // (2D Euler only): the learned indicator decides outside its uncertainty band
 // and the FP64 TVB test inside it; the network runs once per wavefront on
 // the matrix cores, so every lane takes part even past the last cell.
+//
+// Flags per cell: 1 troubled (limited), 2 positivity-limited, 4 reduced to
+// its average, 8 decided by the TVB test inside the uncertainty band.
 template <class EQ, int K, int LAY, bool MLP>
-__global__ __launch_bounds__(256) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
+__global__ __launch_bounds__(256, LIMIT_OCC) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
                                                void* __restrict__ u,
                                                uint8_t* __restrict__ flags,
                                                unsigned long long* __restrict__ counters) {
   constexpr int NC = EQ::NC, DIM = EQ::DIM, Q = K + 1, NB = Sizes<K, DIM>::NB;
-  constexpr bool USE_MLP = MLP && EQ::EULER && DIM == 2 && K >= 1;
-  __shared__ unsigned int cnt[3];
-  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  constexpr bool EUL = EQ::EULER;
+  constexpr bool USE_MLP = MLP && EUL && DIM == 2 && K >= 1;
+  __shared__ unsigned int cnt[4];  // limited, non-physical averages, band; [3]: queue length
+  __shared__ unsigned short queue[256];
+  if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
-  const bool in = cell < g.N;
+  // crkdg_create keeps the cell count far below 2^32
+  const unsigned cell = blockIdx.x * 256u + threadIdx.x;
+  const bool in = cell < (unsigned)g.N;
   const double M = la.M;
-  uint8_t flag = 0;
-  bool bad = false;
-  const int i = in ? (int)(cell % g.nx) : 0, j = in ? (int)(cell / g.nx) : 0;
-  double U[NC][NB];
-  double avg[NC];
-  double dp[2][NC], dm[2][NC];
-  // neighbour averages in direction d, side s (ghost rule of the boundary)
-  auto nbr_avg = [&](int d, int s, double* qa) {
-    int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
-    const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
-    if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
-      const int type = bc.type[side];
-      if (type == CRKDG_BC_TRANSMISSIVE) {
-        for (int c = 0; c < NC; ++c) qa[c] = avg[c];
-        return;
-      }
-      if (type == CRKDG_BC_DIRICHLET) {
-        for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
-        return;
-      }
-      ni = (ni + g.nx) % g.nx;
-      nj = (nj + g.ny) % g.ny;
-    }
-    for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
-  };
-  auto mode_of = [&](int d, int deg) { return DIM == 1 ? deg : (d == 0 ? deg : deg * Q); };
-  EulerPrim wp{};
-  if (in) {
-    load_state<double, NC, NB, LAY>(u, g.N, cell, U);
-    for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
-    if constexpr (EQ::EULER) {
-      wp = euler_prim(ph.gamma, avg);
-      bad = !(avg[0] > 0.0) || !(wp.p > 0.0);
-    }
-    for (int d = 0; d < DIM; ++d) {
-      double qn[NC];
-      nbr_avg(d, +1, qn);
-      for (int c = 0; c < NC; ++c) dp[d][c] = qn[c] - avg[c];
-      nbr_avg(d, -1, qn);
-      for (int c = 0; c < NC; ++c) dm[d][c] = avg[c] - qn[c];
-    }
-  }
-  // the TVB minmod troubled-cell test (characteristic variables for Euler)
-  auto tvb_test = [&]() {
-    bool tr = false;
-    for (int d = 0; d < DIM; ++d) {
-      const double h = d == 0 ? g.dx : g.dy;
-      const double Mh2 = M * h * h;
-      double a[NC], at[NC];
-      for (int c = 0; c < NC; ++c) {
-        a[c] = 0.0;
-        at[c] = 0.0;
-        for (int deg = 1; deg <= K; ++deg) {
-          const double v = U[c][mode_of(d, deg)];
-          a[c] += v;
-          at[c] += (deg % 2) ? v : -v;
-        }
-      }
-      double ca[NC], cat[NC], cp[NC], cm[NC];
-      if constexpr (EQ::EULER) {
-        double L[16], Rm[16];
-        euler_eigvec(ph.gamma, wp, d, L, Rm);
-        for (int r = 0; r < NC; ++r) {
-          ca[r] = cat[r] = cp[r] = cm[r] = 0.0;
-          for (int c = 0; c < NC; ++c) {
-            ca[r] += L[r * 4 + c] * a[c];
-            cat[r] += L[r * 4 + c] * at[c];
-            cp[r] += L[r * 4 + c] * dp[d][c];
-            cm[r] += L[r * 4 + c] * dm[d][c];
-          }
-        }
-      } else {
-        for (int c = 0; c < NC; ++c) {
-          ca[c] = a[c]; cat[c] = at[c]; cp[c] = dp[d][c]; cm[c] = dm[d][c];
-        }
-      }
-      for (int r = 0; r < NC; ++r)
-        if (tvb(ca[r], cp[r], cm[r], Mh2) != ca[r] || tvb(cat[r], cp[r], cm[r], Mh2) != cat[r])
-          tr = true;
-    }
-    return tr;
-  };
-  bool troubled = false;
-  bool fallback = false;
-  if constexpr (USE_MLP) {
-    __shared__ MlpWaveSmem sm[4];
-    __shared__ MlpWeightsSmem ws;
-    mlp_stage_weights(la.P, ws);
-    float x[MLP_IN];
+  const double Mh2[2] = {M * g.dx * g.dx, M * g.dy * g.dy};
+  bool bad = false, troubled = false, band = false, heavy = false;
+  double spd = 0.0;
+  {
+    double avg[NC], a[2][NC], at[2][NC], rabs[NC], dp[2][NC], dm[2][NC];
+    EulerPrim wp{};
 #pragma unroll
-    for (int e = 0; e < MLP_IN; ++e) x[e] = 0.0f;
-    if (in && !bad) cell_features<NB, Q>(U, dp, dm, M * g.dx * g.dx, M * g.dy * g.dy, x);
-    __syncthreads();  // the staged weights
-    const float z = mlp_infer_wave(la.P, ws, x, sm[threadIdx.x >> 6]);
-    if (in && !bad) {
-      if (z >= la.z_hi) {
-        troubled = true;
-      } else if (z > la.z_lo) {
-        fallback = true;
-        troubled = tvb_test();
-      }
+    for (int c = 0; c < NC; ++c) {
+      avg[c] = 0.0;
+      rabs[c] = 0.0;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) a[d][c] = at[d][c] = dp[d][c] = dm[d][c] = 0.0;
     }
-  } else {
-    if (in && K >= 1 && !bad) troubled = tvb_test();
-  }
-  if (in) {
-    auto reconstruct = [&](double (&V)[NC][NB]) {
-      double ns[2][NC];
-      for (int d = 0; d < DIM; ++d) {
-        const double h = d == 0 ? g.dx : g.dy;
-        const double Mh2 = M * h * h;
-        const int sm1 = mode_of(d, 1);
-        double sl[NC];
-        for (int c = 0; c < NC; ++c) sl[c] = V[c][sm1];
-        if constexpr (EQ::EULER) {
-          double L[16], Rm[16], lim[NC];
-          euler_eigvec(ph.gamma, wp, d, L, Rm);
-          for (int r = 0; r < NC; ++r) {
-            double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            for (int c = 0; c < NC; ++c) {
-              s1 += L[r * 4 + c] * sl[c];
-              s2 += L[r * 4 + c] * dp[d][c];
-              s3 += L[r * 4 + c] * dm[d][c];
-            }
-            lim[r] = tvb(s1, s2, s3, Mh2);
-          }
-          for (int c = 0; c < NC; ++c) {
-            double s = 0.0;
-            for (int r = 0; r < NC; ++r) s += Rm[c * 4 + r] * lim[r];
-            ns[d][c] = s;
-          }
-        } else {
-          for (int c = 0; c < NC; ++c) ns[d][c] = tvb(sl[c], dp[d][c], dm[d][c], Mh2);
-        }
-      }
+    int i = 0, j = 0;
+    if (in) {
+      i = (int)(cell % (unsigned)g.nx);
+      j = (int)(cell / (unsigned)g.nx);
+#pragma unroll
       for (int c = 0; c < NC; ++c) {
-        for (int b = 1; b < NB; ++b) V[c][b] = 0.0;
-        for (int d = 0; d < DIM; ++d) V[c][mode_of(d, 1)] = ns[d][c];
+        avg[c] = load_mode<NC, NB, LAY>(u, g.N, c, 0, cell);
+#pragma unroll
+        for (int b = 1; b < NB; ++b) {
+          const double v = load_mode<NC, NB, LAY>(u, g.N, c, b, cell);
+          rabs[c] += fabs(v);
+        }
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int deg = 1; deg <= K; ++deg) {
+            const double v = load_mode<NC, NB, LAY>(u, g.N, c, dir_mode<DIM, Q>(d, deg), cell);
+            a[d][c] += v;
+            at[d][c] += (deg % 2) ? v : -v;
+          }
       }
-    };
-    bool changed = false;
-    if (fallback) flag |= 8;
-    if (troubled) {
-      reconstruct(U);
-      flag |= 1;
-      changed = true;
+      if constexpr (EUL) {
+        wp = euler_prim(ph.gamma, avg);
+        bad = !(avg[0] > 0.0) || !(wp.p > 0.0);
+        spd = euler_speed(g, wp);
+      } else {
+        spd = cell_speed<EQ>(ph, g, avg);
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
     }
-    if constexpr (EQ::EULER) {
-      if (!bad && K >= 1 && !physical_points<K>(ph.gamma, U)) {
-        if (!troubled) reconstruct(U);
-        flag |= 2;
-        changed = true;
-        if (!physical_points<K>(ph.gamma, U)) {
-          for (int c = 0; c < NC; ++c)
-            for (int b = 1; b < NB; ++b) U[c][b] = 0.0;
-          flag |= 4;
+    if constexpr (USE_MLP) {
+      __shared__ MlpWaveSmem sm[4];
+      __shared__ MlpWeightsSmem ws;
+      mlp_stage_weights(la.P, ws);
+      float x[MLP_IN];
+#pragma unroll
+      for (int e = 0; e < MLP_IN; ++e) x[e] = 0.0f;
+      if (in && !bad) cell_features_jumps(a, at, dp, dm, Mh2[0], Mh2[1], x);
+      __syncthreads();  // the staged weights
+      const float z = mlp_infer_wave(la.P, ws, x, sm[threadIdx.x >> 6]);
+      if (in && !bad) {
+        if (z >= la.z_hi)
+          troubled = true;
+        else if (z > la.z_lo)
+          band = true;
+      }
+    } else if constexpr (K >= 1) {
+      if (in && !bad)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+          troubled = tvb_troubled_dir<EQ>(ph, Mh2[d], wp, d, a[d], at[d], dp[d], dm[d]) || troubled;
+    }
+    if constexpr (K >= 1) {
+      heavy = in && !bad && (troubled || band);
+      if constexpr (EUL) heavy = heavy || (in && !bad && !surely_physical_sums(avg, rabs));
+    }
+  }
+  // queue the heavy cells (one LDS atomic per wavefront)
+  const unsigned long long hm = __ballot(heavy);
+  if (hm) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int leader = __ffsll((long long)hm) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[3], (unsigned)__popcll(hm));
+    base = (unsigned)__shfl((int)base, leader);
+    if (heavy) {
+      const unsigned rank = (unsigned)__popcll(hm & ((1ull << lane) - 1ull));
+      queue[base + rank] = (unsigned short)(threadIdx.x | (troubled ? 0x100u : 0u) | (band ? 0x200u : 0u));
+    }
+  }
+  if (in && !heavy && flags) flags[cell] = 0;
+  if (counters) {
+    if (bad) atomicAdd(&cnt[1], 1u);
+    if (band) atomicAdd(&cnt[2], 1u);
+  }
+  // the limiter never changes a cell average, so the wave speeds of the
+  // limited state (the next step's dt) come from the averages already read;
+  // the reduction's barriers also publish the queue
+  if (la.wave_partial) {
+    __shared__ double sh[4];
+    const double m = block_max<256>(spd, sh);
+    if (threadIdx.x == 0) la.wave_partial[blockIdx.x] = m;
+  } else {
+    __syncthreads();
+  }
+  // second pass: the queued cells on the block's first lanes
+  if (K >= 1 && threadIdx.x < cnt[3]) {
+    const unsigned e = queue[threadIdx.x];
+    const unsigned qc = blockIdx.x * 256u + (e & 0xffu);
+    const bool tr0 = (e & 0x100u) != 0, bnd = (e & 0x200u) != 0;
+    const int i = (int)(qc % (unsigned)g.nx), j = (int)(qc / (unsigned)g.nx);
+    double avg[NC], sl[2][NC], a[2][NC], at[2][NC];
+    bool phys = true;  // the unlimited polynomial passes the point positivity test
+    {
+      double U[NC][NB];
+      load_state<double, NC, NB, LAY>(u, g.N, qc, U);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        avg[c] = U[c][0];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          sl[d][c] = d < DIM ? U[c][dir_mode<DIM, Q>(d, 1)] : 0.0;
+          double s = 0.0, st = 0.0;
+#pragma unroll
+          for (int deg = 1; deg <= K; ++deg) {
+            const double v = d < DIM ? U[c][dir_mode<DIM, Q>(d, deg)] : 0.0;
+            s += v;
+            st += (deg % 2) ? v : -v;
+          }
+          a[d][c] = s;
+          at[d][c] = st;
         }
       }
+      if constexpr (EUL)
+        if (!tr0) phys = surely_physical<K>(U) || physical_points<K>(ph.gamma, U);
     }
-    if (changed) store_state<double, NC, NB, LAY>(u, g.N, cell, U, avg);
-    if (flags) flags[cell] = flag;
+    EulerPrim wp{};
+    if constexpr (EUL) wp = euler_prim(ph.gamma, avg);
+    double dp[2][NC], dm[2][NC];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
+    bool tr = tr0;
+    if (bnd) {
+      tr = false;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        tr = tvb_troubled_dir<EQ>(ph, Mh2[d], wp, d, a[d], at[d], dp[d], dm[d]) || tr;
+    }
+    uint8_t f = bnd ? 8 : 0;
+    if (tr)
+      f |= 1;
+    else if (!phys)
+      f |= 2;
+    if (tr || !phys) {
+      double V[NC][NB];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        V[c][0] = avg[c];
+#pragma unroll
+        for (int b = 1; b < NB; ++b) V[c][b] = 0.0;
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        double ns[NC];
+        tvb_slope_dir<EQ>(ph, Mh2[d], wp, d, sl[d], dp[d], dm[d], ns);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) V[c][dir_mode<DIM, Q>(d, 1)] = ns[c];
+      }
+      if constexpr (EUL) {
+        if (!surely_physical<K>(V) && !physical_points<K>(ph.gamma, V)) {
+          f |= 2 | 4;
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int b = 1; b < NB; ++b) V[c][b] = 0.0;
+        }
+      }
+      store_state<double, NC, NB, LAY>(u, g.N, qc, V, avg);
+    }
+    if (flags) flags[qc] = f;
+    if (counters && (f & 7)) atomicAdd(&cnt[0], 1u);
   }
   if (counters) {
-    if (flag & 7) atomicAdd(&cnt[0], 1u);
-    if (bad) atomicAdd(&cnt[1], 1u);
-    if (flag & 8) atomicAdd(&cnt[2], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
       if (cnt[0]) atomicAdd(&counters[0], (unsigned long long)cnt[0]);
       if (cnt[1]) atomicAdd(&counters[1], (unsigned long long)cnt[1]);
       if (cnt[2]) atomicAdd(&counters[2], (unsigned long long)cnt[2]);
     }
-  }
-  // the limiter never changes a cell average, so the wave speeds of the
-  // limited state (the next step's dt) come from the averages already read
-  if (la.wave_partial) {
-    __shared__ double sh[256];
-    double spd = 0.0;
-    if constexpr (EQ::EULER) {
-      if (in) spd = euler_speed(g, wp);
-    } else {
-      if (in) spd = cell_speed<EQ>(ph, g, avg);
-    }
-    const double m = block_max<256>(spd, sh);
-    if (threadIdx.x == 0) la.wave_partial[blockIdx.x] = m;
   }
 }
 

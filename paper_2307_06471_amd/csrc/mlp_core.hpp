@@ -71,9 +71,9 @@ struct MlpWaveSmem {
       __bf16 x[64][16];   // features, padded 12 -> 16
       __bf16 h1[64][32];  // first hidden layer
     };
-    float h2[64][36];     // second hidden layer, written once x and h1 are read
-                          // (rows of 144 B: 16-byte aligned, consecutive rows
-                          // start 4 banks apart)
+    float h2[32][36];     // second hidden layer, one half of the rows at a time,
+                          // written once x and h1 are read (rows of 144 B:
+                          // 16-byte aligned, consecutive rows 4 banks apart)
   };
 };
 // W1 and W2 in bf16, already in the matrix cores' B-operand order: lane l
@@ -145,6 +145,8 @@ __device__ __forceinline__ float mlp_infer_wave(const float* __restrict__ P,
     a1[h] = *reinterpret_cast<const bf16x8*>(&sm.h1[h * 32 + n][16 + kb]);
   }
   wave_lds_fence();
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  float z = 0.0f;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     f32x16 c = {};
@@ -153,17 +155,20 @@ __device__ __forceinline__ float mlp_infer_wave(const float* __restrict__ P,
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int r = (j >> 2) * 8 + (l >> 5) * 4 + (j & 3);
-      sm.h2[h * 32 + r][n] = relu_f(c[j] + b2);
+      sm.h2[r][n] = relu_f(c[j] + b2);
     }
-  }
-  wave_lds_fence();
-  typedef float f32x4 __attribute__((ext_vector_type(4)));
-  float z = P[MLP_OB3];
+    wave_lds_fence();
+    // lane l's row is row l % 32 of half l / 32
+    if ((l >> 5) == h) {
+      z = P[MLP_OB3];
 #pragma unroll
-  for (int q = 0; q < MLP_H2 / 4; ++q) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(&sm.h2[l][4 * q]);
+      for (int q = 0; q < MLP_H2 / 4; ++q) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(&sm.h2[n][4 * q]);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) z = z + P[MLP_OW3 + 4 * q + e] * v[e];
+        for (int e = 0; e < 4; ++e) z = z + P[MLP_OW3 + 4 * q + e] * v[e];
+      }
+    }
+    wave_lds_fence();  // the half is read before the next one overwrites it
   }
   return z;
 }
@@ -171,31 +176,55 @@ __device__ __forceinline__ float mlp_infer_wave(const float* __restrict__ P,
 // 12 stencil features of one cell (computed in FP64, returned in FP32): for
 // q in {density, energy} and direction d in {x, y}, with a / at the forward /
 // backward trace-average jumps, dp / dm the differences of neighbouring cell
-// averages and s = |dp| + |dm| + M h_d^2 + 1e-300:  a/s, at/s, (dp - dm)/s
-template <int NB, int Q>
-__device__ __forceinline__ void cell_features(const double (&U)[4][NB], const double (&dp)[2][4],
-                                              const double (&dm)[2][4], double Mh2x, double Mh2y,
-                                              float (&x)[MLP_IN]) {
+// averages and s = |dp| + |dm| + M h_d^2 + 1e-300:  a/s, at/s, (dp - dm)/s.
+// a[d][c] and at[d][c] are the jumps of component c in direction d.
+__device__ __forceinline__ void cell_features_jumps(const double (&a)[2][4], const double (&at)[2][4],
+                                                    const double (&dp)[2][4], const double (&dm)[2][4],
+                                                    double Mh2x, double Mh2y, float (&x)[MLP_IN]) {
 #pragma unroll
   for (int qi = 0; qi < 2; ++qi) {
     const int c = qi ? 3 : 0;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
-      double a = 0.0, at = 0.0;
-#pragma unroll
-      for (int deg = 1; deg < Q; ++deg) {
-        const double v = U[c][d == 0 ? deg : deg * Q];
-        a += v;
-        at += (deg % 2) ? v : -v;
-      }
       const double s = fabs(dp[d][c]) + fabs(dm[d][c]) + (d == 0 ? Mh2x : Mh2y) + 1e-300;
       const double is = 1.0 / s;  // one division; FP64 products, then rounded to FP32
       float* xo = x + (qi * 2 + d) * 3;
-      xo[0] = (float)(a * is);
-      xo[1] = (float)(at * is);
+      xo[0] = (float)(a[d][c] * is);
+      xo[1] = (float)(at[d][c] * is);
       xo[2] = (float)((dp[d][c] - dm[d][c]) * is);
     }
   }
+}
+
+// the jumps along the cell's centre lines from its modes (mode m + Q n):
+// u(+1) - avg = sum of the modes of degree 1..Q-1 in that direction, and
+// avg - u(-1) = the same sum with the even degrees negated
+template <int NB, int Q>
+__device__ __forceinline__ void trace_jumps(const double (&U)[4][NB], double (&a)[2][4],
+                                            double (&at)[2][4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      double s = 0.0, st = 0.0;
+#pragma unroll
+      for (int deg = 1; deg < Q; ++deg) {
+        const double v = U[c][d == 0 ? deg : deg * Q];
+        s += v;
+        st += (deg % 2) ? v : -v;
+      }
+      a[d][c] = s;
+      at[d][c] = st;
+    }
+}
+
+template <int NB, int Q>
+__device__ __forceinline__ void cell_features(const double (&U)[4][NB], const double (&dp)[2][4],
+                                              const double (&dm)[2][4], double Mh2x, double Mh2y,
+                                              float (&x)[MLP_IN]) {
+  double a[2][4], at[2][4];
+  trace_jumps<NB, Q>(U, a, at);
+  cell_features_jumps(a, at, dp, dm, Mh2x, Mh2y, x);
 }
 
 }  // namespace crk
