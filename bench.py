@@ -172,6 +172,19 @@ def train_indicator(K, ML):
         "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
 
 
+def save_indicator(path, P, lo, hi, info):
+    """a trained indicator as .npz: parameters, band, training report (JSON)"""
+    np.savez(path, P=np.asarray(P, dtype=np.float32), lo=lo, hi=hi,
+             info=np.array(json.dumps(info)))
+
+
+def load_indicator(path):
+    z = np.load(path)  # numeric and text arrays only (no pickles)
+    info = json.loads(str(z["info"]))
+    info["loaded_from"] = os.path.basename(path)
+    return z["P"].astype(np.float32), float(z["lo"]), float(z["hi"]), info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +199,9 @@ def main():
                     help="profiling runs only: skip the learned indicator (training and form)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (traffic counter calibration)")
+    ap.add_argument("--indicator", default=None,
+                    help="profiling runs: .npz of a trained indicator, loaded if the file "
+                         "exists, else written after training")
     args = ap.parse_args()
     if args.equal_error_scale < 2:
         ap.error("--equal-error-scale must be at least 2 (the reference is twice as fine)")
@@ -201,7 +217,13 @@ def main():
 
     mlp = None
     if not args.no_mlp:
-        P, lo, hi, mlp_info = train_indicator(K, ML)
+        if args.indicator and os.path.exists(args.indicator):
+            Pn, lo, hi, mlp_info = load_indicator(args.indicator)
+            P = torch.from_numpy(Pn).cuda()
+        else:
+            P, lo, hi, mlp_info = train_indicator(K, ML)
+            if args.indicator:
+                save_indicator(args.indicator, P.cpu().numpy(), lo, hi, mlp_info)
         log(f"indicator trained: {mlp_info['samples']} samples, band ({lo:.4g}, {hi:.4g}), "
             f"validation {mlp_info['validation']}")
         mlp = (P, lo, hi)

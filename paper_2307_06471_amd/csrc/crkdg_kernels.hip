@@ -29,8 +29,18 @@
 #include "dg_core.hpp"
 #include "mlp_core.hpp"
 
-#ifndef LIMIT_OCC
-#define LIMIT_OCC 4
+// Tuning (measured on the 4096 x 1024 Q2 shock workload): occupancy targets
+// in wavefronts per SIMD for __launch_bounds__, and whether the FP64 inner
+// kernel keeps u^n in registers (off: at one wavefront per SIMD it loses
+// what it saves in re-reads).
+#ifndef LIMIT_OCC_TVB
+#define LIMIT_OCC_TVB 3
+#endif
+#ifndef LIMIT_OCC_MLP
+#define LIMIT_OCC_MLP 4
+#endif
+#ifndef INNER_KEEP_F64
+#define INNER_KEEP_F64 0
 #endif
 #ifndef INNER_OCC_F32
 #define INNER_OCC_F32 2
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(256, (Occ<EQ, K>::inner)) void k_inner(PhysDev ph, 
   // starts from it; re-reading it after a stage's arithmetic mostly misses
   // the L2 and doubles the kernel's HBM reads); the FP64 form re-reads it,
   // since another 72 registers would halve its occupancy
-  constexpr bool KEEP = INC || sizeof(R) == 4;
+  constexpr bool KEEP = INC || sizeof(R) == 4 || INNER_KEEP_F64;
   R un[KEEP ? NC : 1][KEEP ? NB : 1];
   if constexpr (KEEP) {
 #pragma unroll
@@ -1487,7 +1497,7 @@ __device__ __forceinline__ void tvb_slope_dir(const PhysDev& ph, double Mh2, con
 // Flags per cell: 1 troubled (limited), 2 positivity-limited, 4 reduced to
 // its average, 8 decided by the TVB test inside the uncertainty band.
 template <class EQ, int K, int LAY, bool MLP>
-__global__ __launch_bounds__(256, LIMIT_OCC) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
+__global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
                                                void* __restrict__ u,
                                                uint8_t* __restrict__ flags,
                                                unsigned long long* __restrict__ counters) {

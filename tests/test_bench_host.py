@@ -3,6 +3,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -49,3 +51,15 @@ def test_committed_traffic_summaries_parse():
         assert d is not None
         assert float(d["traffic_bytes_per_launch"]) > 0
         assert float(d["fetch_factor"]) > 0 and float(d["write_factor"]) > 0
+
+
+def test_indicator_file_round_trip(tmp_path):
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal(1505).astype(np.float32)
+    info = {"tau_lo": 0.2, "validation": {"fn_rate": 0.01}}
+    f = str(tmp_path / "ind.npz")
+    bench.save_indicator(f, P, 0.2, 0.9, info)
+    P2, lo, hi, info2 = bench.load_indicator(f)
+    assert np.array_equal(P, P2) and P2.dtype == np.float32
+    assert (lo, hi) == (0.2, 0.9)
+    assert info2["validation"] == info["validation"] and info2["loaded_from"] == "ind.npz"
