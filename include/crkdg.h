@@ -141,6 +141,18 @@ int crkdg_step(crkdg_state* st, double dt);
  * host synchronisation.  The internal time is not advanced. */
 int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
 
+/* One step of the original RKDG method that the paper compares against
+ * (Section 2.1, equation (rkdg)), in the Shu--Osher SSP form of order 2 or 3
+ * (Section 3.2.1 gives the order-2 form): every stage applies the DG
+ * operator with face fluxes and boundary data at its stage time and, when
+ * M >= 0, the TVB limiter of crkdg_limit (no flags); M < 0 skips the limiter.
+ * FP64 state only (CRKDG_EUNSUPPORTED otherwise).  dt_dev (device double,
+ * nullable) overrides dt, as in crkdg_step_dev: then the internal time is not
+ * advanced and time-dependent boundary data are CRKDG_EUNSUPPORTED;
+ * otherwise dt must be finite and > 0 and the time advances by dt.  Uses
+ * the workspace's first stage slot; stream-ordered, no sync. */
+int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const double* dt_dev);
+
 /* dt = cfl / max_K [ (|u|+c)/dx + (|v|+c)/dy ] from the FP64 cell averages
  * (advection: |a|/dx + |b|/dy), written to device memory (one double).
  * Stream-ordered, no sync.  The paper gives CFL numbers only (Section 4);

@@ -62,6 +62,7 @@ def _sig():
         "crkdg_project": (C.c_int, [vp, C.c_int, dp, C.c_int, vp]),
         "crkdg_step": (C.c_int, [vp, C.c_double]),
         "crkdg_step_dev": (C.c_int, [vp, vp]),
+        "crkdg_step_rkdg": (C.c_int, [vp, C.c_int, C.c_double, C.c_double, vp]),
         "crkdg_compute_dt": (C.c_int, [vp, C.c_double, vp]),
         "crkdg_max_wavespeed": (C.c_int, [vp, dp]),
         "crkdg_limit": (C.c_int, [vp, C.c_double, vp, C.POINTER(C.c_int64)]),
@@ -237,6 +238,13 @@ class Solver:
         s = C.c_double()
         _check(lib().crkdg_max_wavespeed(self.h, C.byref(s)), "crkdg_max_wavespeed")
         return s.value
+
+    def crkdg_step_rkdg(self, order, dt, M=-1.0, dt_tensor=None):
+        """one original-RKDG step (SSP order 2 or 3, limiter every stage if
+        M >= 0); dt_tensor: device double that overrides dt"""
+        p = None if dt_tensor is None else C.c_void_p(dt_tensor.data_ptr())
+        _check(lib().crkdg_step_rkdg(self.h, int(order), float(M), float(dt), p),
+               "crkdg_step_rkdg")
 
     def crkdg_limit(self, M, flags=None, count=True):
         n = C.c_int64(-1)

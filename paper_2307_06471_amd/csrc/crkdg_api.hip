@@ -473,6 +473,73 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev) {
   return step_impl(st, 0.0, dt_dev);
 }
 
+// forward declaration (defined with the limiter entry points below)
+static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
+                      uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl,
+                      double* dt_dev, void* target);
+
+// The original RKDG in the Shu--Osher SSP form (Section 2.1; the comparison
+// scheme of Section 4): every stage applies the DG operator with face fluxes
+// and, when M >= 0, the limiter.  Each stage is one final-stage launch whose
+// update starts from bw1 u^n + bw2 u^(i-1) (FinalArgs::base2), so no separate
+// combination pass.  Buffers: u^(1) in stage slot 1, u^(2) (order 3) or
+// u^{n+1} (order 2) in the second state buffer; the order-3 result is
+// written over u^n (each cell reads its own u^n before writing it, and the
+// neighbour data come from u^(2) only).
+int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const double* dt_dev) {
+  if (!st) return CRKDG_EINVAL;
+  if (!st->bound) return CRKDG_EUNBOUND;
+  if ((order != 2 && order != 3) || isnan(M)) return CRKDG_EINVAL;
+  if (!dt_dev && (!isfinite(dt) || !(dt > 0.0))) return CRKDG_EINVAL;
+  if (st->prec != P64) return CRKDG_EUNSUPPORTED;
+  if (dt_dev && st->bc.exact > 0) return CRKDG_EUNSUPPORTED;  // stage times need dt on the host
+  char* u0 = cur_ptr(st);
+  char* un = nxt_ptr(st);
+  char* s1 = stage_ptr(st, 1);
+  const double h = dt_dev ? 0.0 : dt;  // stage times of boundary data
+  auto pass = [&](const void* base2, double bw1, double bw2, const void* stage, double w,
+                  double t_bc, void* out) {
+    FinalArgs fa{};
+    fa.base = u0;
+    fa.lay_base = st->lay;
+    fa.base2 = base2;
+    fa.bw1 = bw1;
+    fa.bw2 = bw2;
+    fa.out = out;
+    fa.dt = dt;
+    fa.dt_ptr = dt_dev;
+    fa.ns = 1;
+    fa.st[0] = stage;
+    fa.lay[0] = st->lay;
+    fa.w[0] = w;
+    fa.tst[0] = t_bc;
+    ProfScope ps(st, KC_FINAL);
+    return launch_final(st->eq, st->k, st->prec, st->ph, st->geo, st->bc, fa, st->stream) ==
+                   hipSuccess
+               ? CRKDG_OK
+               : CRKDG_EHIP;
+  };
+  auto limit = [&](void* u) {
+    return M < 0.0 ? CRKDG_OK
+                   : limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u);
+  };
+  const double t = st->t;
+  int rc = pass(nullptr, 1.0, 0.0, u0, 1.0, t, s1);  // u^(1) = u^n - dt DG(u^n)
+  if (!rc) rc = limit(s1);
+  if (order == 2) {  // u^{n+1} = u^n / 2 + (u^(1) - dt DG(u^(1))) / 2
+    if (!rc) rc = pass(s1, 0.5, 0.5, s1, 0.5, t + h, un);
+    if (!rc) rc = limit(un);
+    if (!rc) st->cur ^= 1;
+  } else {  // u^(2) = 3/4 u^n + 1/4 (u^(1) - dt DG(u^(1))), then the third stage
+    if (!rc) rc = pass(s1, 0.75, 0.25, s1, 0.25, t + h, un);
+    if (!rc) rc = limit(un);
+    if (!rc) rc = pass(un, 1.0 / 3.0, 2.0 / 3.0, un, 2.0 / 3.0, t + 0.5 * h, u0);
+    if (!rc) rc = limit(u0);
+  }
+  if (!rc && !dt_dev) st->t += dt;
+  return rc;
+}
+
 int crkdg_compute_dt(crkdg_state* st, double cfl, double* dt_dev) {
   if (!st || !dt_dev || !isfinite(cfl) || !(cfl > 0.0)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
@@ -497,14 +564,15 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
 
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
                       uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl = 0.0,
-                      double* dt_dev = nullptr) {
+                      double* dt_dev = nullptr, void* target = nullptr) {
   unsigned long long* counters =
       counts ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
   hipError_t e;
   {
     ProfScope ps(st, KC_LIMIT);
     e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, params, tau_lo, tau_hi,
-                     cur_ptr(st), flags_dev, counters, dt_dev ? wave_partial_ptr(st) : nullptr,
+                     target ? target : cur_ptr(st), flags_dev, counters,
+                     dt_dev ? wave_partial_ptr(st) : nullptr,
                      st->stream);
   }
   if (e == hipSuccess && dt_dev) {

@@ -647,6 +647,15 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 #pragma unroll
           for (int b = 0; b < NB; ++b) acc[c][b] = U[c][b];
       }
+      if (s == 0 && a.base2) {  // base2 is st[0]
+        const R w1 = R(a.bw1), w2 = R(a.bw2);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[c][b] = w1 * acc[c][b] + w2 * U[c][b];
+          a0[c] = a.bw1 * a0[c] + a.bw2 * load_avg<NC, NB, LAY>(S, g.N, c, cell);
+        }
+      }
       const R vs = R(0.5 * dt * w);
       volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), acc);
       R t[NC][Q];
@@ -813,6 +822,12 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
     if (active) {
       R U[NC][NB];
       load_state<R, NC, NB, L64>(S, g.N, i, U);
+      if (s == 0 && a.base2) {  // base2 is st[0]
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[c][b] = R(a.bw1) * acc[c][b] + R(a.bw2) * U[c][b];
+      }
       volume_acc<EQ, K, R>(eq, U, dt * w * R(g.inv_dx), R(0), acc);
       trace_x<+1, EQ, K, R>(U, tR);
       trace_x<-1, EQ, K, R>(U, tL);

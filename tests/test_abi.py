@@ -116,3 +116,22 @@ def test_set_tableau_validation():
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5):
         assert len(K.strerror(code)) >= 2
+
+
+def test_rkdg_step_argument_checks():
+    """the original-RKDG entry point rejects its arguments before touching
+    device memory (the bound pointers below are never dereferenced)"""
+    L = K.lib()
+    assert L.crkdg_step_rkdg(None, 3, 50.0, 0.1, None) == K.CRKDG_EINVAL
+    rc, h = _create()
+    assert L.crkdg_step_rkdg(h, 3, 50.0, 0.1, None) == K.CRKDG_EUNBOUND
+    assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+    for order, M, dt in ((1, 50.0, 0.1), (4, 50.0, 0.1), (3, float("nan"), 0.1),
+                         (3, 50.0, 0.0), (2, -1.0, float("inf")), (3, 50.0, -1.0)):
+        assert L.crkdg_step_rkdg(h, order, M, dt, None) == K.CRKDG_EINVAL, (order, M, dt)
+    L.crkdg_destroy(h)
+    for prec in (K.FP32_MIXED, K.FP32_INNER):
+        rc, h = _create(precision=prec)
+        assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+        assert L.crkdg_step_rkdg(h, 3, 50.0, 0.1, None) == K.CRKDG_EUNSUPPORTED
+        L.crkdg_destroy(h)

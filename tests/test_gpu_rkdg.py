@@ -1,0 +1,119 @@
+"""GPU parity of the original RKDG step (the paper's comparison scheme,
+Section 2.1, in the Shu--Osher SSP form of order 2 or 3; Section 3.2.1 writes
+the order-2 form) against the oracle's `or_step_rkdg_ssp`, which applies the
+DG operator in every stage and the TVB limiter after every stage.
+
+Tolerance: 1e-12 relative to the largest magnitude (FP64; the two sides
+differ in rounding order only).  With the limiter, the random states are
+chosen so that every TVB decision is far from its threshold (the oracle's
+margins are checked for the initial state).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2307_06471_amd import workloads as W
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2307_06471_amd import crkdg
+    return crkdg
+
+
+def pair(K, dim, nx, ny, k, equation, bc=(0, 0, 0, 0), box=(0.0, 1.0, 0.0, 1.0),
+         adv=(0.8, -0.6), bc_exact=0, flux="llf"):
+    eqo = O.EQ_EULER if equation == "euler" else O.EQ_ADVECTION
+    om = O.Mesh(dim, nx, ny, x0=box[0], x1=box[1], y0=box[2], y1=box[3], bc=bc, adv=adv,
+                bc_exact=bc_exact, equation=eqo,
+                flux=O.FLUX_LLF if flux == "llf" else O.FLUX_UPWIND)
+    lm = K.make_mesh(dim, nx, ny, x0=box[0], x1=box[1], y0=box[2], y1=box[3], bc=bc, adv=adv,
+                     bc_exact=bc_exact,
+                     equation=K.EQ_EULER if equation == "euler" else K.EQ_ADVECTION)
+    s = K.Solver(lm, k, K.FLUX_LLF if flux == "llf" else K.FLUX_UPWIND, 3)
+    return om, s
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("k", [1, 2])
+def test_euler_steps_no_limiter(K, order, k):
+    om, s = pair(K, 2, 70, 9, k, "euler", box=(0.0, 2.0, 0.0, 1.0))
+    u = W.random_euler_modes(np.random.default_rng(20 + k), (k + 1) ** 2, 70 * 9)
+    s.crkdg_set_state(u)
+    dt = 1e-3
+    for n in range(4):
+        s.crkdg_step_rkdg(order, dt)
+        u = O.step_rkdg_ssp(om, k, order, n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_advection_2d_transmissive(K, order):
+    k = 2
+    om, s = pair(K, 2, 45, 13, k, "advection", bc=(1, 1, 1, 1), flux="upwind")
+    u = np.random.default_rng(4).standard_normal((1, 9, 45 * 13))
+    s.crkdg_set_state(u)
+    for n in range(3):
+        s.crkdg_step_rkdg(order, 2e-3)
+        u = O.step_rkdg_ssp(om, k, order, n * 2e-3, 2e-3, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+def test_inflow_stage_times_1d(K):
+    """1D advection with inflow data sin(-t) on the left: the three stages
+    take their boundary data at t, t + dt and t + dt/2"""
+    N, k = 80, 2
+    L = 4 * np.pi
+    om, s = pair(K, 1, N, 1, k, "advection", bc=(2, 1, 0, 0), box=(0.0, L, 0.0, 1.0),
+                 adv=(1.0, 0.0), bc_exact=O.IC_ADV_SIN, flux="upwind")
+    s.crkdg_project(K.IC_ADV_SIN)
+    u = O.project(om, k, O.IC_ADV_SIN)
+    dt = 0.1 * L / N
+    for n in range(50):
+        s.crkdg_step_rkdg(3, dt)
+        u = O.step_rkdg_ssp(om, k, 3, n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_limiter_every_stage(K, order):
+    """TVB limiter after every stage; M = 0 troubles most cells"""
+    k, nx, ny = 2, 53, 29
+    om, s = pair(K, 2, nx, ny, k, "euler", bc=(1, 1, 1, 1))
+    u = W.random_euler_modes(np.random.default_rng(31), 9, nx * ny)
+    _, margin, _ = O.tvb_flags(om, k, 0.0, u)
+    assert (margin > 1e-9).all()
+    s.crkdg_set_state(u)
+    s.crkdg_step_rkdg(order, 5e-4, M=0.0)
+    ref = O.step_rkdg_ssp(om, k, order, 0.0, 5e-4, u, M=0.0)
+    assert rel_err(s.crkdg_get_state(), ref) < TOL
+
+
+def test_device_dt_and_conservation(K):
+    """dt read from device memory gives the same bits as the host dt, and
+    with periodic boundaries the step conserves the integral of every
+    component (the DG operator is conservative stage by stage)"""
+    import torch
+    k = 2
+    om, s = pair(K, 2, 64, 8, k, "euler")
+    _, s2 = pair(K, 2, 64, 8, k, "euler")
+    u = W.random_euler_modes(np.random.default_rng(8), 9, 64 * 8)
+    s.crkdg_set_state(u)
+    s2.crkdg_set_state(u)
+    before = [s.crkdg_total(c) for c in range(4)]
+    dt_dev = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.crkdg_step_rkdg(3, 1e-3, M=50.0)
+        s2.crkdg_step_rkdg(3, 0.0, M=50.0, dt_tensor=dt_dev)
+    a, b = s.crkdg_get_state(), s2.crkdg_get_state()
+    assert np.array_equal(a, b)
+    for c in range(4):
+        assert abs(s.crkdg_total(c) - before[c]) <= 1e-13 * max(1.0, abs(before[c]))
