@@ -32,12 +32,21 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final):
+def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final, scheme="crkdg"):
     """bytes a kernel class must move per launch (its inputs and outputs):
     inner: read u^n, write the stored stage state(s); final: read u^n and the
     stored stage states, write u^{n+1}; limiter: read the state, write one
     flag byte per cell; dt: the final max over the limiter's per-block
-    wave-speed maxima."""
+    wave-speed maxima.  Original RKDG (SSP order 3): three DG-operator passes
+    per step, the first reading u^n once (2 states moved), the others u^n and
+    the previous stage (3 states): 8/3 states per launch on average; its
+    limiter reads the state (no flags)."""
+    if scheme == "rkdg3":
+        if cls == "final":
+            return 8 * state_bytes / 3
+        if cls == "limit":
+            return state_bytes
+        return None
     if cls == "inner":
         return state_bytes + stage_bytes * (stages_final - 1)
     if cls == "final":
@@ -199,6 +208,8 @@ def main():
                     help="profiling runs only: skip the learned indicator (training and form)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (traffic counter calibration)")
+    ap.add_argument("--no-rkdg", action="store_true",
+                    help="profiling runs only: skip the original-RKDG form")
     ap.add_argument("--indicator", default=None,
                     help="profiling runs: .npz of a trained indicator, loaded if the file "
                          "exists, else written after training")
@@ -235,6 +246,10 @@ def main():
     for name, prec, ind in plan:
         forms[name] = run_form(K, W, args, prec, ind)
         log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
+    rk = None
+    if not args.no_rkdg:
+        rk = run_form(K, W, args, K.FP64, None, scheme="rkdg3")
+        log(f"fp64 RKDG SSP3 + TVB every stage: {rk['ms_per_step']:.3f} ms/step")
     head = forms["fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"]
     plain = forms["fp64 + TVB"]
     tvb32 = forms["fp32-bulk + TVB"]
@@ -266,6 +281,13 @@ def main():
                                    "stage and limiter"},
         "speedup_vs_fp64_plain": head["value"] / plain["value"],
     }
+    if rk is not None:
+        out["fp64_rkdg_ssp3"] = {
+            "value": rk["value"], "ms_per_step": rk["ms_per_step"], "roofline": rk["roofline"],
+            "kernels": rk["kernels"],
+            "form": "the original RKDG the paper compares against: SSP-RK3 (Shu-Osher), DG "
+                    "operator and TVB limiter (M=50) in every stage, FP64, same CFL"}
+        out["crkdg_over_rkdg_fp64"] = plain["value"] / rk["value"]
     if mlp is not None:
         out["mlp"] = mlp_info
     if not args.no_equal_error and mlp is not None:
@@ -293,7 +315,7 @@ def measured_traffic(kernel, precision_tag):
     return float(d["traffic_bytes_per_launch"])
 
 
-def run_form(K, W, args, precision, mlp=None):
+def run_form(K, W, args, precision, mlp=None, scheme="crkdg"):
     import torch
     s, cfg, params, xi = make_solver(K, W, args.scale, precision)
     stream = s.stream
@@ -304,6 +326,12 @@ def run_form(K, W, args, precision, mlp=None):
     P, lo, hi = mlp if mlp is not None else (None, 0.0, 0.0)
 
     def step():
+        if scheme == "rkdg3":
+            # the original RKDG: DG operator and limiter in each of three
+            # stages, then the next step's dt from the new averages
+            s.crkdg_step_rkdg(3, 0.0, M, dt_tensor=dt_dev)
+            s.crkdg_compute_dt(cfg["cfl"], dt_dev)
+            return
         # one step, then the limiter, which also leaves the next step's dt
         # (from the cell averages it reads; the limiter does not change them)
         s.crkdg_step_dev(dt_dev)
@@ -331,14 +359,15 @@ def run_form(K, W, args, precision, mlp=None):
     stage_bytes = s.state_bytes  # stored stages use the state's layout
     kern = {}
     for cls, (tms, cnt) in prof.items():
-        by = algorithmic_bytes(cls, s.state_bytes, stage_bytes, s.ncells, stages_final)
+        by = algorithmic_bytes(cls, s.state_bytes, stage_bytes, s.ncells, stages_final, scheme)
         kern[cls] = {"ms_per_launch": tms / cnt, "launches": cnt, "share": tms / ms,
                      "achieved_GBs": None if by is None else by / (tms / cnt * 1e-3) / 1e9}
     dom = max(prof, key=lambda c: prof[c][0])
-    by = algorithmic_bytes(dom, s.state_bytes, stage_bytes, s.ncells, stages_final)
+    by = algorithmic_bytes(dom, s.state_bytes, stage_bytes, s.ncells, stages_final, scheme)
     achieved = by / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e9
-    traffic = measured_traffic({"final": "final2", "inner": "inner", "limit": "limit"}.get(dom, dom),
-                               {K.FP32_MIXED: "fp32", K.FP64: "fp64"}.get(precision, "fp32inner"))
+    traffic = None if scheme != "crkdg" else measured_traffic(
+        {"final": "final2", "inner": "inner", "limit": "limit"}.get(dom, dom),
+        {K.FP32_MIXED: "fp32", K.FP64: "fp64"}.get(precision, "fp32inner"))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_launch": by}
@@ -352,8 +381,9 @@ def run_form(K, W, args, precision, mlp=None):
 def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0.1, 0.25),
                 samples=10):
     """the shock workload with cell counts divided by `scale`, run to T = 0.25
-    by FP64 + TVB, FP32-bulk + TVB and FP32-bulk + learned indicator, for each
-    seed; L1/L2 density errors of the cell averages against FP64 + TVB on the
+    by FP64 + TVB, the original RKDG (SSP-RK3, limiter every stage, FP64),
+    FP32-inner + TVB, FP32-bulk + TVB and FP32-bulk + learned indicator, for
+    each seed; L1/L2 density errors of the cell averages against FP64 + TVB on the
     2x finer mesh restricted to this one (same initial density function), at
     each checkpoint time (the runs land on them exactly).
 
@@ -369,7 +399,8 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
     coarse = W.config("c5", scale)
     grid = (coarse["nx"], coarse["ny"])  # the reference sees the same initial density field
 
-    def run(seed, scale_, precision, indicator, at_checkpoint, rates=False, perturb=False):
+    def run(seed, scale_, precision, indicator, at_checkpoint, rates=False, perturb=False,
+            scheme="crkdg"):
         s, cfg, params, xi = make_solver(K, W, scale_, precision, field_grid=grid, seed=seed)
         if perturb:
             u = s.crkdg_get_state()
@@ -391,14 +422,19 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
             dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), target - t)
             if nsteps_est is None:
                 nsteps_est = int(T / dt) + 1
-            s.crkdg_step(dt)
+            if scheme == "rkdg3":
+                s.crkdg_step_rkdg(3, dt, M)  # the limiter runs inside every stage
+            else:
+                s.crkdg_step(dt)
             t = t + dt if target - t - dt > 1e-14 else target
             n += 1
             sample = rates and n % max(1, nsteps_est // samples) == 0
             if sample:
                 clone.crkdg_set_state(s.crkdg_get_state())
                 clone.crkdg_limit(M, tflags)
-            if indicator is None:
+            if scheme == "rkdg3":
+                pass
+            elif indicator is None:
                 tot["flagged"] += s.crkdg_limit(M, flags if sample else None)
             else:
                 nf, nb = s.crkdg_limit_mlp(M, P, lo, hi, flags if sample else None)
@@ -418,11 +454,12 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
         torch.cuda.synchronize()
         return s, n, tot, time.perf_counter() - t0
 
-    forms = (("fp64 + TVB", K.FP64, None, False),
-             ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True),
-             ("fp32-inner + TVB", K.FP32_INNER, None, False),
-             ("fp32-bulk + TVB", K.FP32_MIXED, None, False),
-             ("fp32-bulk + MLP", K.FP32_MIXED, mlp, False))
+    forms = (("fp64 + TVB", K.FP64, None, False, "crkdg"),
+             ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True, "crkdg"),
+             ("fp64 RKDG SSP3 + TVB every stage", K.FP64, None, False, "rkdg3"),
+             ("fp32-inner + TVB", K.FP32_INNER, None, False, "crkdg"),
+             ("fp32-bulk + TVB", K.FP32_MIXED, None, False, "crkdg"),
+             ("fp32-bulk + MLP", K.FP32_MIXED, mlp, False, "crkdg"))
     per_seed = {}
     for seed in seeds:
         snaps = []
@@ -432,7 +469,7 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
             f"{tref:.1f} s")
         res = {}
         base_snaps = []
-        for name, prec, ind, pert in forms:
+        for name, prec, ind, pert, sch in forms:
             errs = []
             diffs = []
 
@@ -446,16 +483,17 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
                     ref.crkdg_set_state(snaps[ci])  # keep ref for the next checkpoint
 
             s, n, tot, el = run(seed, scale, prec, ind, at_cp, rates=ind is not None,
-                                perturb=pert)
+                                perturb=pert, scheme=sch)
             r = {"L1": [e[0] for e in errs], "L2": [e[1] for e in errs], "steps": n,
-                 "flagged_fraction": tot["flagged"] / tot["cells"]}
+                 "flagged_fraction": None if sch != "crkdg" else tot["flagged"] / tot["cells"],
+                 "seconds": round(el, 2)}
             if ind is not None:
                 r["fallback_fraction"] = tot["fallback"] / tot["cells"]
                 r["fn_rate_vs_tvb"] = tot["fn"] / max(1, tot["tvb_pos"])
                 r["fp_rate_vs_tvb"] = tot["fp"] / max(1, tot["sampled"] - tot["tvb_pos"])
             res[name] = r
             log(f"  {name}: L1 {['%.4e' % v for v in r['L1']]} L2 {['%.4e' % v for v in r['L2']]} "
-                f"flagged {r['flagged_fraction']:.4f}")
+                f"flagged {r['flagged_fraction']}")
             del s
         per_seed[str(seed)] = res
         del ref
@@ -466,7 +504,7 @@ def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0
 
     ratios = {name: {f"t={tc}": {"L1": mean_ratio(name, "L1", ci), "L2": mean_ratio(name, "L2", ci)}
                      for ci, tc in enumerate(checkpoints)}
-              for name, _, _, _ in forms[1:]}
+              for name, *_ in forms[1:]}
     cand = ratios["fp32-bulk + MLP"][f"t={T}"]
     return {"mesh": f"{coarse['nx']}x{coarse['ny']}",
             "reference": "FP64 + TVB on the 2x finer mesh, restricted; same initial density",

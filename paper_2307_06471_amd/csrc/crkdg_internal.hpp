@@ -63,7 +63,8 @@ struct FinalArgs {
   const void* base;      // u^n (NULL: zero), layout lay_base
   int lay_base;
   // optional second base: the update starts from bw1 * base + bw2 * base2
-  // (Shu--Osher stages of the original RKDG); base2 must equal st[0]
+  // (Shu--Osher stages of the original RKDG); base2 must be st[0], and in 2D
+  // the FP64 layout
   const void* base2;
   double bw1, bw2;
   void* out;             // u^{n+1}, layout lay_base

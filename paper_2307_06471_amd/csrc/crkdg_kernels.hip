@@ -557,7 +557,9 @@ struct FinalSmem {
 };
 
 // LAY: layout of u^n, of the stored stages and of u^{n+1}
-template <class EQ, int K, int LAY>
+// B2: the update starts from bw1 base + bw2 st[0] (stages of the original
+// RKDG; FinalArgs::base2 is st[0]), folded into the first stage's load
+template <class EQ, int K, int LAY, bool B2>
 __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typename EQ::Real>::TY,
                              (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
                                                                  FinalArgs a) {
@@ -647,13 +649,15 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 #pragma unroll
           for (int b = 0; b < NB; ++b) acc[c][b] = U[c][b];
       }
-      if (s == 0 && a.base2) {  // base2 is st[0]
-        const R w1 = R(a.bw1), w2 = R(a.bw2);
+      if constexpr (B2) {  // the update starts from bw1 base + bw2 st[0]
+        if (s == 0) {
+          const R w1 = R(a.bw1), w2 = R(a.bw2);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+          for (int c = 0; c < NC; ++c) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) acc[c][b] = w1 * acc[c][b] + w2 * U[c][b];
-          a0[c] = a.bw1 * a0[c] + a.bw2 * load_avg<NC, NB, LAY>(S, g.N, c, cell);
+            for (int b = 0; b < NB; ++b) acc[c][b] = w1 * acc[c][b] + w2 * U[c][b];
+            a0[c] = a.bw1 * a0[c] + a.bw2 * load_avg<NC, NB, LAY>(S, g.N, c, cell);
+          }
         }
       }
       const R vs = R(0.5 * dt * w);
@@ -814,6 +818,14 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
     GL[c][0] = GR[c][0] = 0.0;
   }
   if (active && a.base) load_state<R, NC, NB, L64>(a.base, g.N, i, acc);
+  if (active && a.base && a.base2) {  // bw1 base + bw2 base2
+    R U2[NC][NB];
+    load_state<R, NC, NB, L64>(a.base2, g.N, i, U2);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[c][b] = R(a.bw1) * acc[c][b] + R(a.bw2) * U2[c][b];
+  }
 #pragma unroll 1
   for (int s = 0; s < a.ns; ++s) {
     const void* __restrict__ S = a.st[s];
@@ -822,12 +834,6 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
     if (active) {
       R U[NC][NB];
       load_state<R, NC, NB, L64>(S, g.N, i, U);
-      if (s == 0 && a.base2) {  // base2 is st[0]
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) acc[c][b] = R(a.bw1) * acc[c][b] + R(a.bw2) * U[c][b];
-      }
       volume_acc<EQ, K, R>(eq, U, dt * w * R(g.inv_dx), R(0), acc);
       trace_x<+1, EQ, K, R>(U, tR);
       trace_x<-1, EQ, K, R>(U, tL);
@@ -1822,7 +1828,18 @@ struct FinalL {
       if constexpr (EQ::DIM == 2) {
         using T = FinalTile<typename EQ::Real>;
         dim3 grid(nblk(g.nx, T::TX), nblk(g.ny, T::TY));
-        hipLaunchKernelGGL((k_final2<EQ, K, LAY>), grid, dim3(T::TX * T::TY), 0, s, ph, g, bc, a);
+        if (a.base2 && (a.ns < 1 || a.base2 != a.st[0])) return hipErrorInvalidValue;
+        if constexpr (LAY == L64) {
+          if (a.base2) {
+            hipLaunchKernelGGL((k_final2<EQ, K, LAY, true>), grid, dim3(T::TX * T::TY), 0, s, ph,
+                               g, bc, a);
+            return hipGetLastError();
+          }
+        } else if (a.base2) {
+          return hipErrorInvalidValue;  // the original RKDG runs on the FP64 layout only
+        }
+        hipLaunchKernelGGL((k_final2<EQ, K, LAY, false>), grid, dim3(T::TX * T::TY), 0, s, ph, g,
+                           bc, a);
       } else {
         hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
       }

@@ -63,3 +63,10 @@ def test_indicator_file_round_trip(tmp_path):
     assert np.array_equal(P, P2) and P2.dtype == np.float32
     assert (lo, hi) == (0.2, 0.9)
     assert info2["validation"] == info["validation"] and info2["loaded_from"] == "ind.npz"
+
+
+def test_algorithmic_bytes_of_the_original_rkdg():
+    S, N = 288, 1000
+    assert bench.algorithmic_bytes("final", S * N, S * N, N, 2, "rkdg3") == 8 * S * N / 3
+    assert bench.algorithmic_bytes("limit", S * N, S * N, N, 2, "rkdg3") == S * N
+    assert bench.algorithmic_bytes("dt", S * N, S * N, N, 2, "rkdg3") is None
