@@ -21,6 +21,7 @@ FLUX_UPWIND, FLUX_LLF = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
+IC_DMR = 7  # double Mach reflection (Section 4)
 
 N_MLP_PARAMS = 12 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 
@@ -59,6 +60,9 @@ def lib():
             "or_crkdg_stages": (C.c_int, [mp, C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_double, dp, dp]),
             "or_limit_tvb": (C.c_int64, [mp, C.c_int, C.c_double, dp, u8]),
             "or_tvb_flags": (C.c_int64, [mp, C.c_int, C.c_double, dp, u8, dp]),
+            "or_limit_tvb_at": (C.c_int64, [mp, C.c_int, C.c_double, C.c_double, dp, u8]),
+            "or_tvb_flags_at": (C.c_int64, [mp, C.c_int, C.c_double, C.c_double, dp, u8, dp]),
+            "or_dmr_states": (None, [C.c_double, dp, dp, dp]),
             "or_euler_eig": (C.c_int, [mp, dp, C.c_int, dp, dp]),
             "or_max_wavespeed": (C.c_double, [mp, C.c_int, dp]),
             "or_errors": (C.c_int, [mp, C.c_int, dp, C.c_int, dp, dp, C.c_double, C.c_int, dp]),
@@ -235,19 +239,28 @@ def step_wrong_ssp(mesh, k, order, t, dt, u):
     return u
 
 
-def limit_tvb(mesh, k, M, u):
+def limit_tvb(mesh, k, M, u, t=0.0):
+    """t: time of time-dependent ghost data (double Mach reflection)"""
     u = np.array(u, dtype=np.float64, order="C")
     flags = np.zeros(mesh.ncells, dtype=np.uint8)
-    n = lib().or_limit_tvb(mesh.ref, k, M, _d(u), _u8(flags))
+    n = lib().or_limit_tvb_at(mesh.ref, k, M, t, _d(u), _u8(flags))
     return u, flags, n
 
 
-def tvb_flags(mesh, k, M, u):
+def tvb_flags(mesh, k, M, u, t=0.0):
     u = np.ascontiguousarray(u, dtype=np.float64)
     flags = np.zeros(mesh.ncells, dtype=np.uint8)
     margin = np.zeros(mesh.ncells)
-    n = lib().or_tvb_flags(mesh.ref, k, M, _d(u), _u8(flags), _d(margin))
+    n = lib().or_tvb_flags_at(mesh.ref, k, M, t, _d(u), _u8(flags), _d(margin))
     return flags, margin, n
+
+
+def dmr_states(gamma=1.4):
+    """double Mach reflection: (pre-shock, post-shock) conserved states and
+    the shock speed"""
+    pre, post, S = np.zeros(4), np.zeros(4), np.zeros(1)
+    lib().or_dmr_states(gamma, _d(pre), _d(post), _d(S))
+    return pre, post, float(S[0])
 
 
 def euler_eig(mesh, q, d):

@@ -201,6 +201,42 @@ static double wrap_centered(double d, double period) {
   return r - 0.5 * period;
 }
 
+/* Double Mach reflection (Section 4, example "Double Mach reflection"): a
+ * Mach 10 shock moving to the right into gas at rest, (rho, p) = (1.4, 1),
+ * through (1/6, 0) at 60 degrees to the x-axis; the reflecting wall occupies
+ * the bottom side from x = 1/6 on.  The paper fixes these settings and
+ * leaves the states to the classical test (Woodward--Colella); the
+ * post-shock state follows from the Rankine--Hugoniot conditions. */
+#define DMR_XWALL (1.0 / 6.0)
+#define DMR_MACH 10.0
+#define DMR_ANGLE (M_PI / 3.0)
+
+/* pre- and post-shock conserved states and the shock speed.  In the frame
+ * of the shock the gas enters with speed w1 = S and leaves with w2:
+ * mass rho1 w1 = rho2 w2, momentum p1 + rho1 w1^2 = p2 + rho2 w2^2, energy
+ * h1 + w1^2/2 = h2 + w2^2/2 with h = gamma p / ((gamma - 1) rho).  For a
+ * shock of Mach number M = S / c1 these give the density ratio
+ * (gamma + 1) M^2 / ((gamma - 1) M^2 + 2); the momentum balance then gives
+ * p2, and the gas behind the shock moves with S - w2 along the normal. */
+void or_dmr_states(double gamma, double pre[4], double post[4], double* shock_speed) {
+  double rho1 = 1.4, p1 = 1.0;
+  double c1 = sqrt(gamma * p1 / rho1);
+  double S = DMR_MACH * c1;
+  double ratio = (gamma + 1.0) * DMR_MACH * DMR_MACH /
+                 ((gamma - 1.0) * DMR_MACH * DMR_MACH + 2.0);
+  double rho2 = rho1 * ratio;
+  double w1 = S, w2 = S / ratio;
+  double p2 = p1 + rho1 * w1 * w1 - rho2 * w2 * w2;
+  double un = S - w2;
+  /* the shock normal points into the gas at rest: (sin 60, -cos 60) */
+  double nx = sin(DMR_ANGLE), ny = -cos(DMR_ANGLE);
+  double u2 = un * nx, v2 = un * ny;
+  pre[0] = rho1; pre[1] = 0.0; pre[2] = 0.0; pre[3] = p1 / (gamma - 1.0);
+  post[0] = rho2; post[1] = rho2 * u2; post[2] = rho2 * v2;
+  post[3] = p2 / (gamma - 1.0) + 0.5 * rho2 * (u2 * u2 + v2 * v2);
+  if (shock_speed) *shock_speed = S;
+}
+
 static void exact_state(const or_mesh* m, int ic, const double* P, const double* aux,
                         double x, double y, double t, double* q) {
   int nc = or_ncomp(m);
@@ -271,6 +307,15 @@ static void exact_state(const or_mesh* m, int ic, const double* P, const double*
       prim_to_cons(m, rho, 0.0, 0.0, 1.0, q);
       return;
     }
+    case OR_IC_DMR: {
+      /* the planar shock at time t: it has moved S t along its normal */
+      double pre[4], post[4], S;
+      or_dmr_states(m->gamma, pre, post, &S);
+      double nx = sin(DMR_ANGLE), ny = -cos(DMR_ANGLE);
+      double behind = nx * (x - DMR_XWALL) + ny * y < S * t;
+      for (int c = 0; c < nc; ++c) q[c] = behind ? post[c] : pre[c];
+      return;
+    }
     default:
       for (int c = 0; c < nc; ++c) q[c] = NAN;
   }
@@ -337,6 +382,13 @@ static void exterior_trace(const or_mesh* m, int k, const double* u, int i, int 
         double hx = cdx(m), hy = cdy(m);
         double x = m->x0 + (i + 0.5) * hx + 0.5 * hx * xi;
         double y = m->dim == 2 ? m->y0 + (j + 0.5) * hy + 0.5 * hy * eta : 0.0;
+        if (m->bc_exact == OR_IC_DMR && side == 2 && x >= DMR_XWALL) {
+          /* reflecting wall: the interior trace with its normal momentum
+           * mirrored */
+          for (int c = 0; c < nc; ++c) qe[c] = qi[c];
+          qe[2] = -qi[2];
+          return;
+        }
         exact_state(m, m->bc_exact, m->ic_params, NULL, x, y, t_bc, qe);
       } else {
         for (int c = 0; c < nc; ++c) qe[c] = m->bc_state[side][c];
@@ -566,20 +618,22 @@ int or_step_rkdg_ssp(const or_mesh* m, int k, int order, double t, double dt, do
   double* D = (double*)malloc(sizeof(double) * n);
   if (!u0 || !u1 || !D) { free(u0); free(u1); free(D); return -1; }
   memcpy(u0, u, sizeof(double) * n);
+  /* each stage is limited with boundary data at the time it approximates:
+   * t + dt, then (order 3) t + dt/2, then t + dt */
   int rc = or_apply(m, k, OR_OP_DG, t, u0, D);
   for (size_t e = 0; e < n; ++e) u1[e] = u0[e] - dt * D[e];
-  if (M >= 0.0 && or_limit_tvb(m, k, M, u1, NULL) < 0) rc = -3;
+  if (M >= 0.0 && or_limit_tvb_at(m, k, M, t + dt, u1, NULL) < 0) rc = -3;
   if (order == 2) {
     rc = rc ? rc : or_apply(m, k, OR_OP_DG, t + dt, u1, D);
     for (size_t e = 0; e < n; ++e) u[e] = 0.5 * u0[e] + 0.5 * (u1[e] - dt * D[e]);
   } else {
     rc = rc ? rc : or_apply(m, k, OR_OP_DG, t + dt, u1, D);
     for (size_t e = 0; e < n; ++e) u1[e] = 0.75 * u0[e] + 0.25 * (u1[e] - dt * D[e]);
-    if (M >= 0.0 && or_limit_tvb(m, k, M, u1, NULL) < 0) rc = -3;
+    if (M >= 0.0 && or_limit_tvb_at(m, k, M, t + 0.5 * dt, u1, NULL) < 0) rc = -3;
     rc = rc ? rc : or_apply(m, k, OR_OP_DG, t + 0.5 * dt, u1, D);
     for (size_t e = 0; e < n; ++e) u[e] = u0[e] / 3.0 + 2.0 / 3.0 * (u1[e] - dt * D[e]);
   }
-  if (!rc && M >= 0.0 && or_limit_tvb(m, k, M, u, NULL) < 0) rc = -3;
+  if (!rc && M >= 0.0 && or_limit_tvb_at(m, k, M, t + dt, u, NULL) < 0) rc = -3;
   free(u0); free(u1); free(D);
   return rc;
 }
@@ -702,9 +756,10 @@ int or_euler_eig(const or_mesh* m, const double* q, int d, double* L, double* R)
   return 0;
 }
 
-/* cell average of a neighbour across side (d, s), with the ghost rule */
+/* cell average of a neighbour across side (d, s), with the ghost rule; t is
+ * the time of boundary data that depend on it (double Mach reflection) */
 static void neighbour_avg(const or_mesh* m, int k, const double* u, int i, int j, int d, int s,
-                          double* qa) {
+                          double t, double* qa) {
   int nc = or_ncomp(m), nb = or_nmodes(m, k), N = ncells(m);
   int nyc = m->dim == 2 ? m->ny : 1;
   int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
@@ -717,6 +772,17 @@ static void neighbour_avg(const or_mesh* m, int k, const double* u, int i, int j
       nj = (nj + nyc) % nyc;
     } else if (bc == OR_BC_TRANSMISSIVE) {
       ni = i; nj = j;
+    } else if (m->bc_exact == OR_IC_DMR) {
+      /* the ghost cell's centre, mirrored across the boundary */
+      double hx = cdx(m), hy = cdy(m);
+      double xg = m->x0 + (ni + 0.5) * hx, yg = m->y0 + (nj + 0.5) * hy;
+      if (side == 2 && m->x0 + (i + 0.5) * hx >= DMR_XWALL) {
+        for (int c = 0; c < nc; ++c) qa[c] = u[(c * nb + 0) * N + j * m->nx + i];
+        qa[2] = -qa[2];  /* reflecting wall: normal momentum mirrored */
+      } else {
+        exact_state(m, OR_IC_DMR, NULL, NULL, xg, yg, t, qa);
+      }
+      return;
     } else {
       for (int c = 0; c < nc; ++c) qa[c] = m->bc_state[side][c];
       return;
@@ -731,7 +797,7 @@ static int mode_index(const or_mesh* m, int k, int d, int deg) {
 }
 
 /* the troubled-cell test for one cell; returns 1 if troubled */
-static int tvb_test(const or_mesh* m, int k, double M, const double* u, int cell,
+static int tvb_test(const or_mesh* m, int k, double M, double t, const double* u, int cell,
                     double* margin) {
   int nc = or_ncomp(m), nb = or_nmodes(m, k), N = ncells(m);
   int i = cell % m->nx, j = cell / m->nx;
@@ -751,9 +817,9 @@ static int tvb_test(const or_mesh* m, int k, double M, const double* u, int cell
         at[c] += (deg % 2 == 1) ? v : -v;
       }
     }
-    neighbour_avg(m, k, u, i, j, d, +1, qn);
+    neighbour_avg(m, k, u, i, j, d, +1, t, qn);
     for (int c = 0; c < nc; ++c) dp[c] = qn[c] - qb[c];
-    neighbour_avg(m, k, u, i, j, d, -1, qn);
+    neighbour_avg(m, k, u, i, j, d, -1, t, qn);
     for (int c = 0; c < nc; ++c) dm[c] = qb[c] - qn[c];
     if (m->equation == OR_EQ_EULER) {
       double L[16], R[16], ca[OR_MAXC], cat[OR_MAXC], cp[OR_MAXC], cm[OR_MAXC];
@@ -784,8 +850,8 @@ static int tvb_test(const or_mesh* m, int k, double M, const double* u, int cell
 
 /* limited P1 reconstruction of one cell, reading u0 (pre-limiting) and
  * writing into u; keeps the mean */
-static void tvb_reconstruct(const or_mesh* m, int k, double M, const double* u0, double* u,
-                            int cell) {
+static void tvb_reconstruct(const or_mesh* m, int k, double M, double t, const double* u0,
+                            double* u, int cell) {
   int nc = or_ncomp(m), nb = or_nmodes(m, k), N = ncells(m);
   int i = cell % m->nx, j = cell / m->nx;
   double newslope[2][OR_MAXC];
@@ -798,9 +864,9 @@ static void tvb_reconstruct(const or_mesh* m, int k, double M, const double* u0,
       qb[c] = u0[(c * nb) * N + cell];
       sl[c] = u0[(c * nb + sm) * N + cell];
     }
-    neighbour_avg(m, k, u0, i, j, d, +1, qn);
+    neighbour_avg(m, k, u0, i, j, d, +1, t, qn);
     for (int c = 0; c < nc; ++c) dp[c] = qn[c] - qb[c];
-    neighbour_avg(m, k, u0, i, j, d, -1, qn);
+    neighbour_avg(m, k, u0, i, j, d, -1, t, qn);
     for (int c = 0; c < nc; ++c) dm[c] = qb[c] - qn[c];
     if (m->equation == OR_EQ_EULER) {
       double L[16], R[16], cs[OR_MAXC], lim[OR_MAXC];
@@ -860,21 +926,30 @@ static int physical_at_points(const or_mesh* m, int k, const double* u, int cell
   return 1;
 }
 
-int64_t or_tvb_flags(const or_mesh* m, int k, double M, const double* u, uint8_t* flags,
-                     double* margin) {
+int64_t or_tvb_flags_at(const or_mesh* m, int k, double M, double t, const double* u,
+                        uint8_t* flags, double* margin) {
   int N = ncells(m);
   int64_t n = 0;
   for (int cell = 0; cell < N; ++cell) {
     double mg = INFINITY;
-    int t = k >= 1 ? tvb_test(m, k, M, u, cell, &mg) : 0;
-    if (flags) flags[cell] = (uint8_t)t;
+    int tr = k >= 1 ? tvb_test(m, k, M, t, u, cell, &mg) : 0;
+    if (flags) flags[cell] = (uint8_t)tr;
     if (margin) margin[cell] = mg;
-    n += t;
+    n += tr;
   }
   return n;
 }
 
+int64_t or_tvb_flags(const or_mesh* m, int k, double M, const double* u, uint8_t* flags,
+                     double* margin) {
+  return or_tvb_flags_at(m, k, M, 0.0, u, flags, margin);
+}
+
 int64_t or_limit_tvb(const or_mesh* m, int k, double M, double* u, uint8_t* flags) {
+  return or_limit_tvb_at(m, k, M, 0.0, u, flags);
+}
+
+int64_t or_limit_tvb_at(const or_mesh* m, int k, double M, double t, double* u, uint8_t* flags) {
   int N = ncells(m), nc = or_ncomp(m), nb = or_nmodes(m, k);
   size_t n = state_len(m, k);
   double* u0 = (double*)malloc(sizeof(double) * n);
@@ -891,12 +966,12 @@ int64_t or_limit_tvb(const or_mesh* m, int k, double M, double* u, uint8_t* flag
       cbad = !(qb[0] > 0.0) || !(pressure(m, qb) > 0.0);
       bad |= cbad;
     }
-    if (k >= 1 && !cbad && tvb_test(m, k, M, u0, cell, NULL)) {
-      tvb_reconstruct(m, k, M, u0, u, cell);
+    if (k >= 1 && !cbad && tvb_test(m, k, M, t, u0, cell, NULL)) {
+      tvb_reconstruct(m, k, M, t, u0, u, cell);
       fl |= 1;
     }
     if (m->equation == OR_EQ_EULER && !cbad && k >= 1 && !physical_at_points(m, k, u, cell)) {
-      if (!(fl & 1)) tvb_reconstruct(m, k, M, u0, u, cell);
+      if (!(fl & 1)) tvb_reconstruct(m, k, M, t, u0, u, cell);
       fl |= 2;
       if (!physical_at_points(m, k, u, cell)) {
         for (int c = 0; c < nc; ++c)
@@ -1004,9 +1079,9 @@ int or_mlp_features(const or_mesh* m, int k, double M, const double* u, double* 
           at += (deg % 2 == 1) ? v : -v;
         }
         double qn[OR_MAXC], qb = u[(c * nb) * N + cell];
-        neighbour_avg(m, k, u, i, j, d, +1, qn);
+        neighbour_avg(m, k, u, i, j, d, +1, 0.0, qn);
         double dp = qn[c] - qb;
-        neighbour_avg(m, k, u, i, j, d, -1, qn);
+        neighbour_avg(m, k, u, i, j, d, -1, 0.0, qn);
         double dm = qb - qn[c];
         double s = fabs(dp) + fabs(dm) + M * h * h + 1e-300;
         double* x = X + (size_t)cell * 12 + (qi * 2 + d) * 3;

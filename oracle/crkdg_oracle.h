@@ -52,7 +52,12 @@ enum {
   OR_IC_QUADRANT = 4,       /* params: xs, ys, then rho,u,v,p for NE, NW, SW, SE         */
   OR_IC_SHOCK = 5,          /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
                                aux: cell-centre noise field xi[ny][nx]                    */
-  OR_IC_ADV_SIN_1D_SHIFT = 6 /* 1D advection sin(x - a t) used as inflow data            */
+  OR_IC_ADV_SIN_1D_SHIFT = 6, /* 1D advection sin(x - a t) used as inflow data           */
+  OR_IC_DMR = 7             /* double Mach reflection: the planar Mach 10 shock through
+                               (1/6, 0) at 60 degrees, moved to time t (no params).  As
+                               bc_exact: Dirichlet sides take this solution at the face
+                               point, except the bottom side from x = 1/6 on, which is a
+                               reflecting wall (interior trace, normal momentum mirrored) */
 };
 
 typedef struct {
@@ -109,9 +114,19 @@ int    or_crkdg_stages(const or_mesh* m, int k, int s, const double* A, const do
  * 4 still non-physical (P0).  Returns the number of flagged cells, or -1 if
  * a cell average is non-physical. */
 int64_t or_limit_tvb(const or_mesh* m, int k, double M, double* u, uint8_t* flags);
+/* the same with time-dependent ghost data evaluated at time t (double Mach
+ * reflection: ghost cell average = the exact solution at the ghost cell's
+ * centre, or the cell's own average with the normal momentum mirrored at the
+ * reflecting wall); or_limit_tvb is this at t = 0 */
+int64_t or_limit_tvb_at(const or_mesh* m, int k, double M, double t, double* u, uint8_t* flags);
 /* troubled-cell indicator only, with decision margins (see or_limit_tvb) */
 int64_t or_tvb_flags(const or_mesh* m, int k, double M, const double* u, uint8_t* flags,
                      double* margin);
+int64_t or_tvb_flags_at(const or_mesh* m, int k, double M, double t, const double* u,
+                        uint8_t* flags, double* margin);
+/* double Mach reflection: pre- and post-shock conserved states (Rankine--
+ * Hugoniot) and the shock speed, for the given gamma */
+void   or_dmr_states(double gamma, double pre[4], double post[4], double* shock_speed);
 /* characteristic decomposition of the Euler Jacobian in direction d at a state */
 int    or_euler_eig(const or_mesh* m, const double* ubar, int d, double* L, double* R);
 
