@@ -73,8 +73,20 @@ enum {
   CRKDG_IC_EULER_WAVE = 2,  /* rho = 1 + 0.2 sin(pi(x + y - (u+v) t)); params: u, v, p      */
   CRKDG_IC_VORTEX = 3,      /* isentropic vortex; params: eps, xc, yc, Lx, Ly (exact at t) */
   CRKDG_IC_QUADRANT = 4,    /* params: xs, ys, then (rho,u,v,p) for NE, NW, SW, SE        */
-  CRKDG_IC_SHOCK = 5        /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
+  CRKDG_IC_SHOCK = 5,       /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
                                aux: cell-centre field xi[ny][nx] (device, FP64)          */
+  CRKDG_IC_DMR = 6          /* double Mach reflection (Section 4, example "Double Mach
+                               reflection"): a Mach 10 shock moving right into gas at rest
+                               (rho, p) = (1.4, 1), through (1/6, 0) at 60 degrees to the
+                               x-axis at t = 0, post-shock state from the Rankine--Hugoniot
+                               conditions; no params (2D Euler only).  As bc_exact (sides
+                               x-left, y-bottom, y-top Dirichlet, x-right transmissive):
+                               Dirichlet data are this moving shock at the face point and
+                               stage time, except on the bottom from x = 1/6 on, a
+                               reflecting wall (the cell's own trace with the normal
+                               momentum mirrored).  The limiter's ghost averages there are
+                               the same rules at the ghost cell's centre and the state's
+                               time (crkdg_get_time). */
 };
 
 typedef struct {
@@ -84,7 +96,8 @@ typedef struct {
   int bc[4];                /* x-left, x-right, y-bottom, y-top: CRKDG_BC_* */
   double bc_state[4][4];    /* conserved ghost state on Dirichlet sides */
   int bc_exact;             /* > 0: Dirichlet data = exact solution with this CRKDG_IC_*
-                               id, evaluated at the stage time t^n + c_i dt */
+                               id (CRKDG_IC_ADV_SIN or CRKDG_IC_DMR), evaluated at the
+                               stage time t^n + c_i dt */
   int equation;             /* CRKDG_EQ_* */
   double adv[2];            /* advection velocity */
   double gamma;             /* ratio of specific heats (Euler) */

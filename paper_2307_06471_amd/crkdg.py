@@ -24,6 +24,7 @@ BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MIXED, FP32_INNER = 0, 1, 2
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
+IC_DMR = 6  # double Mach reflection
 
 
 class crkdg_mesh(C.Structure):

@@ -131,6 +131,36 @@ int crkdg_gauss_rule(int n, double* x, double* w) {
   return CRKDG_OK;
 }
 
+// Double Mach reflection data (CRKDG_IC_DMR): the Mach 10 shock into gas at
+// rest (rho, p) = (1.4, 1) through (1/6, 0) at 60 degrees.  Post-shock state
+// from the normal-shock relations: pressure ratio (2 gamma M^2 - (gamma - 1))
+// / (gamma + 1), density ratio from the Rankine--Hugoniot (Hugoniot curve)
+// relation between the two, gas speed behind the shock S (1 - rho1 / rho2)
+// along the shock normal.  Layout as in DMR_NPARAM (crkdg_internal.hpp).
+static void dmr_params(double gamma, double* P) {
+  const double rho1 = 1.4, p1 = 1.0, mach = 10.0;
+  const double S = mach * sqrt(gamma * p1 / rho1);
+  const double pr = (2.0 * gamma * mach * mach - (gamma - 1.0)) / (gamma + 1.0);
+  const double dr = ((gamma + 1.0) * pr + (gamma - 1.0)) / ((gamma - 1.0) * pr + (gamma + 1.0));
+  const double rho2 = rho1 * dr, p2 = p1 * pr;
+  const double w = S * (1.0 - 1.0 / dr);
+  const double nx = 0.5 * sqrt(3.0), ny = -0.5;  // normal at 60 degrees, into the gas at rest
+  const double u2 = w * nx, v2 = w * ny;
+  for (int e = 0; e < NPARAM; ++e) P[e] = 0.0;
+  P[0] = 1.0 / 6.0;
+  P[1] = nx;
+  P[2] = ny;
+  P[3] = S;
+  P[4] = rho2;
+  P[5] = rho2 * u2;
+  P[6] = rho2 * v2;
+  P[7] = p2 / (gamma - 1.0) + 0.5 * rho2 * (u2 * u2 + v2 * v2);
+  P[8] = rho1;
+  P[9] = 0.0;
+  P[10] = 0.0;
+  P[11] = p1 / (gamma - 1.0);
+}
+
 int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out) {
   if (!mesh || !out) return CRKDG_EINVAL;
   if (k < 0 || k > 3) return CRKDG_EINVAL;
@@ -164,7 +194,13 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   } else {
     return CRKDG_EINVAL;
   }
-  if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN) return CRKDG_EUNSUPPORTED;
+  if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN && mesh->bc_exact != CRKDG_IC_DMR)
+    return CRKDG_EUNSUPPORTED;
+  if (mesh->bc_exact == CRKDG_IC_DMR &&
+      (eq != EQ_EULER2 || mesh->bc[0] != CRKDG_BC_DIRICHLET ||
+       mesh->bc[1] != CRKDG_BC_TRANSMISSIVE || mesh->bc[2] != CRKDG_BC_DIRICHLET ||
+       mesh->bc[3] != CRKDG_BC_DIRICHLET))
+    return CRKDG_EUNSUPPORTED;
   // the FP32 forms are built for 2D Euler, k = 1..3
   if (mesh->precision != CRKDG_FP64 && (eq != EQ_EULER2 || k < 1)) return CRKDG_EUNSUPPORTED;
   crkdg_state* st = new (std::nothrow) crkdg_state();
@@ -196,6 +232,8 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   if (mesh->dim == 1) st->bc.type[2] = st->bc.type[3] = CRKDG_BC_PERIODIC;
   st->bc.exact = mesh->bc_exact;
   memset(st->bc.params, 0, sizeof st->bc.params);
+  st->bc.t = 0.0;
+  if (mesh->bc_exact == CRKDG_IC_DMR) dmr_params(mesh->gamma, st->bc.params);
   // tableaus named by the paper: forward Euler, (eq:2), (eq:3), classical RK4
   static const double FE_A[1] = {0}, FE_b[1] = {1}, FE_c[1] = {0};
   static const double E2_A[4] = {0, 0, 0.5, 0}, E2_b[2] = {0, 1}, E2_c[2] = {0, 0.5};
@@ -357,14 +395,18 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
                   const double* aux_dev) {
   if (!st) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_SHOCK) return CRKDG_EINVAL;
+  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_DMR) return CRKDG_EINVAL;
   if (ic == CRKDG_IC_SHOCK && !aux_dev) return CRKDG_EINVAL;
   if ((ic == CRKDG_IC_EULER_WAVE || ic == CRKDG_IC_VORTEX || ic == CRKDG_IC_QUADRANT ||
-       ic == CRKDG_IC_SHOCK) && st->eq != EQ_EULER2)
+       ic == CRKDG_IC_SHOCK || ic == CRKDG_IC_DMR) && st->eq != EQ_EULER2)
     return CRKDG_EINVAL;
   double P[NPARAM];
   int rc = copy_params(st, params, nparams, P);
   if (rc) return rc;
+  if (ic == CRKDG_IC_DMR) {
+    if (nparams != 0) return CRKDG_EINVAL;
+    dmr_params(st->ph.gamma, P);
+  }
   double* Pd;
   rc = upload_params(st, P, &Pd);
   if (rc) return rc;
@@ -476,7 +518,7 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev) {
 // forward declaration (defined with the limiter entry points below)
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
                       uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl,
-                      double* dt_dev, void* target);
+                      double* dt_dev, void* target, double t_ghost);
 
 // The original RKDG in the Shu--Osher SSP form (Section 2.1; the comparison
 // scheme of Section 4): every stage applies the DG operator with face fluxes
@@ -519,22 +561,24 @@ int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const doubl
                ? CRKDG_OK
                : CRKDG_EHIP;
   };
-  auto limit = [&](void* u) {
+  // each stage is limited with ghost data at the time it approximates
+  auto limit = [&](void* u, double tl) {
     return M < 0.0 ? CRKDG_OK
-                   : limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u);
+                   : limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u,
+                                tl);
   };
   const double t = st->t;
   int rc = pass(nullptr, 1.0, 0.0, u0, 1.0, t, s1);  // u^(1) = u^n - dt DG(u^n)
-  if (!rc) rc = limit(s1);
+  if (!rc) rc = limit(s1, t + h);
   if (order == 2) {  // u^{n+1} = u^n / 2 + (u^(1) - dt DG(u^(1))) / 2
     if (!rc) rc = pass(s1, 0.5, 0.5, s1, 0.5, t + h, un);
-    if (!rc) rc = limit(un);
+    if (!rc) rc = limit(un, t + h);
     if (!rc) st->cur ^= 1;
   } else {  // u^(2) = 3/4 u^n + 1/4 (u^(1) - dt DG(u^(1))), then the third stage
     if (!rc) rc = pass(s1, 0.75, 0.25, s1, 0.25, t + h, un);
-    if (!rc) rc = limit(un);
+    if (!rc) rc = limit(un, t + 0.5 * h);
     if (!rc) rc = pass(un, 1.0 / 3.0, 2.0 / 3.0, un, 2.0 / 3.0, t + 0.5 * h, u0);
-    if (!rc) rc = limit(u0);
+    if (!rc) rc = limit(u0, t + h);
   }
   if (!rc && !dt_dev) st->t += dt;
   return rc;
@@ -564,13 +608,15 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
 
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
                       uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl = 0.0,
-                      double* dt_dev = nullptr, void* target = nullptr) {
+                      double* dt_dev = nullptr, void* target = nullptr, double t_ghost = NAN) {
   unsigned long long* counters =
       counts ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
   hipError_t e;
+  BCDev bc = st->bc;  // time-dependent ghost averages at the state's time
+  bc.t = isnan(t_ghost) ? st->t : t_ghost;
   {
     ProfScope ps(st, KC_LIMIT);
-    e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, st->bc, M, params, tau_lo, tau_hi,
+    e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, bc, M, params, tau_lo, tau_hi,
                      target ? target : cur_ptr(st), flags_dev, counters,
                      dt_dev ? wave_partial_ptr(st) : nullptr,
                      st->stream);
@@ -620,7 +666,9 @@ int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev) {
   if (!st || !X_dev || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
-  return hip_rc(launch_mlp_features(st->k, st->lay, st->geo, st->bc, M, cur_ptr(st), X_dev,
+  BCDev bc = st->bc;  // the limiter's ghost rules at the state's time
+  bc.t = st->t;
+  return hip_rc(launch_mlp_features(st->k, st->lay, st->geo, bc, M, cur_ptr(st), X_dev,
                                     st->stream));
 }
 

@@ -28,7 +28,13 @@ struct BCDev {
   double state[4][4];    // Dirichlet conserved states
   int exact;             // > 0: time-dependent Dirichlet data from this IC id
   double params[NPARAM]; // its parameters
+  double t;              // limiter: time of the time-dependent ghost averages
 };
+
+// double Mach reflection data in BCDev::params / projection parameters:
+// [0] x of the wall's start, [1..2] unit shock normal (into the gas at rest),
+// [3] shock speed, [4..7] post-shock and [8..11] pre-shock conserved states
+constexpr int DMR_NPARAM = 12;
 
 struct PhysDev {
   double gamma, ax, ay;

@@ -236,6 +236,14 @@ __device__ __forceinline__ double periodic_offset(double d, double L) {
   return r;
 }
 
+// double Mach reflection: the planar shock moved along its normal to time t
+// (P as in DMR_NPARAM)
+__device__ __forceinline__ void dmr_state(const double* P, double x, double y, double t,
+                                          double* q) {
+  const double* st = P[1] * (x - P[0]) + P[2] * y < P[3] * t ? P + 4 : P + 8;
+  for (int c = 0; c < 4; ++c) q[c] = st[c];
+}
+
 template <class EQ>
 __device__ void exact_state(int ic, const double* P, const double* aux, const Geo& g,
                             const PhysDev& ph, double x, double y, double t, double* q) {
@@ -299,6 +307,9 @@ __device__ void exact_state(int ic, const double* P, const double* aux, const Ge
       prim2cons(dim, ph.gamma, rho, 0.0, 0.0, 1.0, q);
       return;
     }
+    case CRKDG_IC_DMR:
+      dmr_state(P, x, y, t, q);
+      return;
     default:
       for (int c = 0; c < EQ::NC; ++c) q[c] = __builtin_nan("");
   }
@@ -473,7 +484,7 @@ struct FinalTile {
 // 3.4: boundary data enter only here).  Uses the same trace functions as the
 // owner of the neighbour cell, so both tiles sharing a face see identical
 // traces and compute identical fluxes.
-template <class EQ, int K, int LAY>
+template <class EQ, int K, int LAY, bool DMRB = false>
 __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, const BCDev& bc,
                                            const void* __restrict__ S, int side, int ci, int cj,
                                            double tb, typename EQ::Real (&out)[EQ::NC][K + 1]) {
@@ -482,15 +493,25 @@ __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, cons
   int ni = ci + (side == 0 ? -1 : side == 1 ? 1 : 0);
   int nj = cj + (side == 2 ? -1 : side == 3 ? 1 : 0);
   int face = side ^ 1;  // the neighbour's face: left side <- its right trace, ...
+  // double Mach reflection, bottom side: the reflecting wall takes the cell's
+  // own trace (below) with the normal momentum mirrored
+  constexpr bool dmr = DMRB && EQ::EULER && EQ::DIM == 2;
+  bool wall = false;
   if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
     const int type = bc.type[side];
-    if (type == CRKDG_BC_DIRICHLET) {
+    if (type == CRKDG_BC_DIRICHLET && !(dmr && side == 2)) {
       constexpr GTab<Q> T = Tab<Q>::t;
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
         double q[4];
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = bc.state[side][c];
+        if constexpr (dmr) {  // the moving shock at the face point and stage time
+          const double xc = g.x0 + (ci + 0.5) * g.dx, yc = g.y0 + (cj + 0.5) * g.dy;
+          const double x = side < 2 ? xc + (side == 0 ? -0.5 : 0.5) * g.dx : xc + 0.5 * g.dx * T.X[p];
+          const double y = side < 2 ? yc + 0.5 * g.dy * T.X[p] : yc + (side == 2 ? -0.5 : 0.5) * g.dy;
+          dmr_state(bc.params, x, y, tb, q);
+        }
         if constexpr (!EQ::EULER) {
           // time-dependent inflow data (advection): sin(pi(x - a t)) sin(pi(y - b t))
           // at the stage time
@@ -506,10 +527,11 @@ __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, cons
       }
       return;
     }
-    if (type == CRKDG_BC_TRANSMISSIVE) {
+    if (type == CRKDG_BC_TRANSMISSIVE || type == CRKDG_BC_DIRICHLET) {
       ni = ci;  // the exterior trace is the cell's own trace on this face
       nj = cj;
       face = side;
+      wall = type == CRKDG_BC_DIRICHLET;  // the DMR bottom side
     } else {  // periodic
       if (ni < 0) ni += g.nx;
       if (ni >= g.nx) ni -= g.nx;
@@ -524,6 +546,24 @@ __device__ __forceinline__ void halo_trace(const Geo& g, const PhysDev& ph, cons
     case 1: trace_x<+1, EQ, K, R>(U, out); break;
     case 2: trace_y<-1, EQ, K, R>(U, out); break;
     default: trace_y<+1, EQ, K, R>(U, out); break;
+  }
+  if constexpr (dmr) {
+    if (wall) {  // before the wall's start the bottom takes the shock data
+      constexpr GTab<Q> T = Tab<Q>::t;
+      const double xc = g.x0 + (ci + 0.5) * g.dx, yb = g.y0 + cj * g.dy;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        const double x = xc + 0.5 * g.dx * T.X[p];
+        if (x >= bc.params[0]) {
+          out[2][p] = -out[2][p];
+        } else {
+          double q[4];
+          dmr_state(bc.params, x, yb, tb, q);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) out[c][p] = (R)q[c];
+        }
+      }
+    }
   }
 }
 
@@ -558,8 +598,9 @@ struct FinalSmem {
 
 // LAY: layout of u^n, of the stored stages and of u^{n+1}
 // B2: the update starts from bw1 base + bw2 st[0] (stages of the original
-// RKDG; FinalArgs::base2 is st[0]), folded into the first stage's load
-template <class EQ, int K, int LAY, bool B2>
+// RKDG; FinalArgs::base2 is st[0]), folded into the first stage's load.
+// DMRB: double Mach reflection boundary data (bc.exact == CRKDG_IC_DMR)
+template <class EQ, int K, int LAY, bool B2, bool DMRB>
 __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typename EQ::Real>::TY,
                              (Occ<EQ, K>::final_)) void k_final2(PhysDev ph, Geo g, BCDev bc,
                                                                  FinalArgs a) {
@@ -686,7 +727,7 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
     }
     if (hside >= 0) {
       R h[NC][Q];
-      halo_trace<EQ, K, LAY>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
+      halo_trace<EQ, K, LAY, DMRB>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -1403,6 +1444,20 @@ __device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
         ghost = true;
 #pragma unroll
         for (int c = 0; c < NC; ++c) qa[c] = avg[c];
+      } else if (type == CRKDG_BC_DIRICHLET && NC == 4 && bc.exact == CRKDG_IC_DMR) {
+        // the ghost cell's centre at the limiter's time; the reflecting wall
+        // mirrors the cell's own average
+        ghost = true;
+        const double xg = g.x0 + (ni + 0.5) * g.dx, yg = g.y0 + (nj + 0.5) * g.dy;
+        if (side == 2 && g.x0 + (i + 0.5) * g.dx >= bc.params[0]) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) qa[c] = c == 2 ? -avg[c] : avg[c];
+        } else {
+          double q[4];
+          dmr_state(bc.params, xg, yg, bc.t, q);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) qa[c] = q[c];
+        }
       } else if (type == CRKDG_BC_DIRICHLET) {
         ghost = true;
 #pragma unroll
@@ -1730,31 +1785,11 @@ __global__ __launch_bounds__(256) void k_mlp_features(Geo g, BCDev bc, double M,
   const int i = (int)(cell % g.nx), j = (int)(cell / g.nx);
   double U[NC][NB];
   load_state<double, NC, NB, LAY>(u, g.N, cell, U);
-  double dp[2][4], dm[2][4];
-  for (int d = 0; d < 2; ++d)
-    for (int s = -1; s <= 1; s += 2) {
-      int ni = i + (d == 0 ? s : 0), nj = j + (d == 1 ? s : 0);
-      const int side = d == 0 ? (s < 0 ? 0 : 1) : (s < 0 ? 2 : 3);
-      double qa[NC];
-      if (ni < 0 || ni >= g.nx || nj < 0 || nj >= g.ny) {
-        const int type = bc.type[side];
-        if (type == CRKDG_BC_TRANSMISSIVE) {
-          for (int c = 0; c < NC; ++c) qa[c] = U[c][0];
-        } else if (type == CRKDG_BC_DIRICHLET) {
-          for (int c = 0; c < NC; ++c) qa[c] = bc.state[side][c];
-        } else {
-          ni = (ni + g.nx) % g.nx;
-          nj = (nj + g.ny) % g.ny;
-          for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
-        }
-      } else {
-        for (int c = 0; c < NC; ++c) qa[c] = load_avg<NC, NB, LAY>(u, g.N, c, (long long)nj * g.nx + ni);
-      }
-      for (int c = 0; c < NC; ++c) {
-        if (s > 0) dp[d][c] = qa[c] - U[c][0];
-        else dm[d][c] = U[c][0] - qa[c];
-      }
-    }
+  // the limiter's neighbour averages and ghost rules (time-dependent ghost
+  // data at the time in bc.t)
+  double avg[NC], dp[2][4], dm[2][4];
+  for (int c = 0; c < NC; ++c) avg[c] = U[c][0];
+  for (int d = 0; d < 2; ++d) limit_neighbours<NC, NB, LAY>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
   float x[MLP_IN];
   cell_features<NB, Q>(U, dp, dm, M * g.dx * g.dx, M * g.dy * g.dy, x);
 #pragma unroll
@@ -1829,17 +1864,29 @@ struct FinalL {
         using T = FinalTile<typename EQ::Real>;
         dim3 grid(nblk(g.nx, T::TX), nblk(g.ny, T::TY));
         if (a.base2 && (a.ns < 1 || a.base2 != a.st[0])) return hipErrorInvalidValue;
+        const dim3 blk(T::TX * T::TY);
+        const bool dmr = bc.exact == CRKDG_IC_DMR;
         if constexpr (LAY == L64) {
           if (a.base2) {
-            hipLaunchKernelGGL((k_final2<EQ, K, LAY, true>), grid, dim3(T::TX * T::TY), 0, s, ph,
-                               g, bc, a);
+            if constexpr (EQ::EULER) {
+              if (dmr) {
+                hipLaunchKernelGGL((k_final2<EQ, K, LAY, true, true>), grid, blk, 0, s, ph, g, bc, a);
+                return hipGetLastError();
+              }
+            }
+            hipLaunchKernelGGL((k_final2<EQ, K, LAY, true, false>), grid, blk, 0, s, ph, g, bc, a);
             return hipGetLastError();
           }
         } else if (a.base2) {
           return hipErrorInvalidValue;  // the original RKDG runs on the FP64 layout only
         }
-        hipLaunchKernelGGL((k_final2<EQ, K, LAY, false>), grid, dim3(T::TX * T::TY), 0, s, ph, g,
-                           bc, a);
+        if constexpr (EQ::EULER) {
+          if (dmr) {
+            hipLaunchKernelGGL((k_final2<EQ, K, LAY, false, true>), grid, blk, 0, s, ph, g, bc, a);
+            return hipGetLastError();
+          }
+        }
+        hipLaunchKernelGGL((k_final2<EQ, K, LAY, false, false>), grid, blk, 0, s, ph, g, bc, a);
       } else {
         hipLaunchKernelGGL((k_final1<EQ, K>), dim3(nblk(g.nx, B1)), dim3(B1), 0, s, ph, g, bc, a);
       }
