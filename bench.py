@@ -181,6 +181,61 @@ def train_indicator(K, ML):
         "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
 
 
+def dmr_run(K, k, nx, ny, precision, rkdg, T=0.2, M=50.0, cfl=0.1):
+    """the paper's double Mach reflection (Section 4): projection, one limiter
+    pass on the projected jump, then steps to T with dt = cfl / s_max from the
+    host (the moving-shock boundary data need each stage's time); the limiter
+    after every step (cRKDG) or inside every stage (RKDG).  Wall time covers
+    the whole run, host synchronisation included."""
+    import torch
+    lm = K.make_mesh(2, nx, ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, bc=(2, 1, 2, 2),
+                     bc_exact=K.IC_DMR, equation=K.EQ_EULER, gamma=1.4, precision=precision)
+    s = K.Solver(lm, k, K.FLUX_LLF, 3)
+    s.crkdg_project(K.IC_DMR)
+    s.crkdg_limit(M)
+    torch.cuda.synchronize()
+    t, n = 0.0, 0
+    t0 = time.perf_counter()
+    while t < T:
+        dt = min(cfl / s.crkdg_max_wavespeed(), T - t)
+        if rkdg:
+            s.crkdg_step_rkdg(3, dt, M=M)
+        else:
+            s.crkdg_step(dt)
+            s.crkdg_limit(M, count=False)
+        t += dt
+        n += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.crkdg_limit(M)  # raises if a cell average went non-physical
+    rho = s.crkdg_get_state()[0, 0]
+    dofs = s.ncells * s.nmodes * s.ncomp
+    return {"steps": n, "seconds": round(wall, 3), "ms_per_step": 1e3 * wall / n,
+            "dof_updates_per_s": dofs * n / wall, "rho_min": float(rho.min()),
+            "rho_max": float(rho.max())}, rho
+
+
+def dmr_study(K):
+    """1920 x 480 with Q1 and Q2 (the paper's fine runs): cRKDG and the
+    original RKDG in FP64, FP32-bulk cRKDG with Q2"""
+    out = {}
+    for k in (1, 2):
+        res = {}
+        rho = {}
+        forms = [("fp64 cRKDG", K.FP64, False), ("fp64 RKDG SSP3", K.FP64, True)]
+        if k == 2:
+            forms.append(("fp32-bulk cRKDG", K.FP32_MIXED, False))
+        for name, prec, rk in forms:
+            res[name], rho[name] = dmr_run(K, k, 1920, 480, prec, rk)
+            log(f"dmr Q{k} 1920x480 {name}: {res[name]}")
+        ref = rho["fp64 RKDG SSP3"]
+        for name in rho:
+            res[name]["rel_L1_density_vs_rkdg"] = float(np.abs(rho[name] - ref).sum() /
+                                                        np.abs(ref).sum())
+        out[f"Q{k}"] = res
+    return out
+
+
 def save_indicator(path, P, lo, hi, info):
     """a trained indicator as .npz: parameters, band, training report (JSON)"""
     np.savez(path, P=np.asarray(P, dtype=np.float32), lo=lo, hi=hi,
@@ -210,6 +265,8 @@ def main():
                     help="end with a plain 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--no-rkdg", action="store_true",
                     help="profiling runs only: skip the original-RKDG form")
+    ap.add_argument("--dmr", action="store_true",
+                    help="also run the double Mach reflection at 1920x480 (Q1, Q2) to t = 0.2")
     ap.add_argument("--indicator", default=None,
                     help="profiling runs: .npz of a trained indicator, loaded if the file "
                          "exists, else written after training")
@@ -294,6 +351,8 @@ def main():
         out["equal_error"] = equal_error(K, W, args.equal_error_scale, mlp)
         log(f"equal error: {out['equal_error']['verdict']} "
             f"{json.dumps(out['equal_error']['mean_error_ratio_vs_fp64_tvb'])}")
+    if args.dmr:
+        out["double_mach_reflection"] = dmr_study(K)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     if args.calibrate_copy:
