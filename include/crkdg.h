@@ -86,7 +86,9 @@ enum {
                                reflecting wall (the cell's own trace with the normal
                                momentum mirrored).  The limiter's ghost averages there are
                                the same rules at the ghost cell's centre and the state's
-                               time (crkdg_get_time). */
+                               time (crkdg_get_time).  The learned indicator
+                               (crkdg_limit_mlp, crkdg_mlp_features, crkdg_limit_dt with
+                               parameters) is CRKDG_EUNSUPPORTED on such a mesh. */
 };
 
 typedef struct {

@@ -648,7 +648,7 @@ int crkdg_limit_mlp(crkdg_state* st, double M, const float* params_dev, float ta
                     float tau_hi, uint8_t* flags_dev, int64_t* counts_host) {
   if (!st || !params_dev || !isfinite(M) || M < 0.0 || !(tau_lo <= tau_hi)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
+  if (st->eq != EQ_EULER2 || st->k < 1 || st->bc.exact == CRKDG_IC_DMR) return CRKDG_EUNSUPPORTED;
   return limit_impl(st, M, params_dev, tau_lo, tau_hi, flags_dev, counts_host, 2);
 }
 
@@ -658,14 +658,15 @@ int crkdg_limit_dt(crkdg_state* st, double M, const float* params_dev, float tau
     return CRKDG_EINVAL;
   if (params_dev && !(tau_lo <= tau_hi)) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (params_dev && (st->eq != EQ_EULER2 || st->k < 1)) return CRKDG_EUNSUPPORTED;
+  if (params_dev && (st->eq != EQ_EULER2 || st->k < 1 || st->bc.exact == CRKDG_IC_DMR))
+    return CRKDG_EUNSUPPORTED;
   return limit_impl(st, M, params_dev, tau_lo, tau_hi, flags_dev, nullptr, 0, cfl, dt_dev);
 }
 
 int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev) {
   if (!st || !X_dev || !isfinite(M) || M < 0.0) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (st->eq != EQ_EULER2 || st->k < 1) return CRKDG_EUNSUPPORTED;
+  if (st->eq != EQ_EULER2 || st->k < 1 || st->bc.exact == CRKDG_IC_DMR) return CRKDG_EUNSUPPORTED;
   BCDev bc = st->bc;  // the limiter's ghost rules at the state's time
   bc.t = st->t;
   return hip_rc(launch_mlp_features(st->k, st->lay, st->geo, bc, M, cur_ptr(st), X_dev,

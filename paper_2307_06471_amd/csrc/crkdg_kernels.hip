@@ -1426,7 +1426,7 @@ __device__ __forceinline__ constexpr int dir_mode(int d, int deg) {
 
 // cell averages of the two neighbours of cell (i, j) in direction d, with the
 // ghost rule of a boundary they lie beyond; dp = right - own, dm = own - left
-template <int NC, int NB, int LAY>
+template <int NC, int NB, int LAY, bool DMRB = false>
 __device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
                                                  const void* __restrict__ u, int i, int j, int d,
                                                  const double (&avg)[NC], double (&dp)[NC],
@@ -1444,7 +1444,7 @@ __device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
         ghost = true;
 #pragma unroll
         for (int c = 0; c < NC; ++c) qa[c] = avg[c];
-      } else if (type == CRKDG_BC_DIRICHLET && NC == 4 && bc.exact == CRKDG_IC_DMR) {
+      } else if (DMRB && NC == 4 && type == CRKDG_BC_DIRICHLET) {
         // the ghost cell's centre at the limiter's time; the reflecting wall
         // mirrors the cell's own average
         ghost = true;
@@ -1572,7 +1572,8 @@ __device__ __forceinline__ void tvb_slope_dir(const PhysDev& ph, double Mh2, con
 //
 // Flags per cell: 1 troubled (limited), 2 positivity-limited, 4 reduced to
 // its average, 8 decided by the TVB test inside the uncertainty band.
-template <class EQ, int K, int LAY, bool MLP>
+// DMRB: double Mach reflection ghost averages (bc.exact == CRKDG_IC_DMR)
+template <class EQ, int K, int LAY, bool MLP, bool DMRB>
 __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_limit(PhysDev ph, Geo g, BCDev bc, LimitArgs la,
                                                void* __restrict__ u,
                                                uint8_t* __restrict__ flags,
@@ -1630,7 +1631,7 @@ __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_li
         spd = cell_speed<EQ>(ph, g, avg);
       }
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
+      for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY, DMRB>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
     }
     if constexpr (USE_MLP) {
       __shared__ MlpWaveSmem sm[4];
@@ -1722,7 +1723,7 @@ __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_li
     if constexpr (EUL) wp = euler_prim(ph.gamma, avg);
     double dp[2][NC], dm[2][NC];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
+    for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY, DMRB>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
     bool tr = tr0;
     if (bnd) {
       tr = false;
@@ -1963,16 +1964,25 @@ struct RunLimit {
                         hipStream_t s) {
     if (counters) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counters, 3);
     const dim3 grid(nblk(g.N, 256));
+    const bool dmr = EQ::EULER && bc.exact == CRKDG_IC_DMR;
+    if (mlp && dmr) return hipErrorInvalidValue;  // the learned indicator has no DMR ghosts
     if (mlp) {
       if (lay == LMIX)
-        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, true, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
       else
-        hipLaunchKernelGGL((k_limit<EQ, K, L64, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+        hipLaunchKernelGGL((k_limit<EQ, K, L64, true, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+    } else if (dmr) {
+      if constexpr (EQ::EULER) {
+        if (lay == LMIX)
+          hipLaunchKernelGGL((k_limit<EQ, K, LMIX, false, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+        else
+          hipLaunchKernelGGL((k_limit<EQ, K, L64, false, true>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+      }
     } else {
       if (lay == LMIX)
-        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+        hipLaunchKernelGGL((k_limit<EQ, K, LMIX, false, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
       else
-        hipLaunchKernelGGL((k_limit<EQ, K, L64, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
+        hipLaunchKernelGGL((k_limit<EQ, K, L64, false, false>), grid, dim3(256), 0, s, ph, g, bc, la, u, flags, counters);
     }
     return hipGetLastError();
   }

@@ -135,3 +135,23 @@ def test_rkdg_step_argument_checks():
         assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
         assert L.crkdg_step_rkdg(h, 3, 50.0, 0.1, None) == K.CRKDG_EUNSUPPORTED
         L.crkdg_destroy(h)
+
+
+def test_double_mach_reflection_mesh_checks():
+    """CRKDG_IC_DMR boundary data need 2D Euler with inflow/outflow/Dirichlet
+    sides; the learned indicator is rejected there (no such ghost rules)"""
+    L = K.lib()
+    dmr = dict(x1=4.0, bc=(2, 1, 2, 2), bc_exact=K.IC_DMR)
+    rc, h = _create(**dmr)
+    assert rc == 0
+    assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+    fake = C.c_void_p(0x300000)
+    assert L.crkdg_limit_mlp(h, 50.0, fake, 0.2, 0.9, None, None) == K.CRKDG_EUNSUPPORTED
+    assert L.crkdg_mlp_features(h, 50.0, fake) == K.CRKDG_EUNSUPPORTED
+    assert L.crkdg_limit_dt(h, 50.0, fake, 0.2, 0.9, None, 0.1, fake) == K.CRKDG_EUNSUPPORTED
+    assert L.crkdg_step_dev(h, fake) == K.CRKDG_EUNSUPPORTED  # stage times need dt on the host
+    assert L.crkdg_project(h, K.IC_DMR, (C.c_double * 1)(1.0), 1, None) == K.CRKDG_EINVAL
+    L.crkdg_destroy(h)
+    for bad in (dict(bc=(2, 2, 2, 2)), dict(bc=(0, 1, 2, 2)), dict(equation=K.EQ_ADVECTION)):
+        rc, _ = _create(**{**dmr, **bad})
+        assert rc == K.CRKDG_EUNSUPPORTED, bad
