@@ -174,3 +174,67 @@ def test_full_size_sampled_parity(K, case):
           f"{checked}, identical flags {agree}", flush=True)
     if lim is not None:
         assert checked > 50 and agree >= 0.95 * checked
+
+
+def test_full_size_learned_indicator_parity(K):
+    """the benchmark's launch configuration of the headline form at full size
+    (4096 x 1024 Q2 shock, FP32-bulk state, dt from the device, crkdg_step_dev,
+    then crkdg_limit_dt with the learned indicator; a fixed random network
+    and band (0.35, 0.65) stand in for the trained one).  On sampled cells the
+    decision is the oracle's inference-precision network on the oracle's
+    features of the cell's 3 x 3 patch, and the FP64 TVB test inside the
+    band; compared where the probability is 2e-3 or more from a threshold
+    and, in the band, the TVB margin above 1e-9 of the averages' scale.
+    Limited states are compared where the decision equals the TVB test's."""
+    import torch
+    s, cfg, bc, bc_state = build(K, "c5", K.FP32_MIXED, 2000)
+    k, M, cfl = cfg["k"], cfg["limiter"][1], cfg["cfl"]
+    rng = np.random.default_rng(5)
+    P = 0.5 * rng.standard_normal(O.N_MLP_PARAMS)
+    P[-1] = 0.3
+    Pf = P.astype(np.float32)
+    Pd = torch.from_numpy(Pf).cuda()
+    lo, hi = 0.35, 0.65
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+    print(f"[fullsize] c5 learned indicator {cfg['nx']}x{cfg['ny']}", flush=True)
+    s.crkdg_compute_dt(cfl, dt_dev)
+    for _ in range(3):
+        s.crkdg_step_dev(dt_dev)
+        s.crkdg_limit_dt(M, cfl, dt_dev, flags, params=Pd, tau_lo=lo, tau_hi=hi)
+    s.crkdg_step_dev(dt_dev)
+    u1 = s.crkdg_get_state()
+    s.crkdg_limit_dt(M, cfl, dt_dev, flags, params=Pd, tau_lo=lo, tau_hi=hi)
+    u2 = s.crkdg_get_state()
+    fl = flags.cpu().numpy()
+    nx = cfg["nx"]
+    extra = []
+    for bit in (1, 8):
+        cells = np.nonzero(fl & bit)[0]
+        assert len(cells) > 0, bit
+        extra += [(int(c % nx), int(c // nx)) for c in rng.choice(cells, min(40, len(cells)),
+                                                                   replace=False)]
+    checked = states = 0
+    for (i, j) in sample_cells(cfg, rng, extra):
+        cell = j * nx + i
+        om, up, c = patch(cfg, bc, bc_state, u1, i, j)
+        X = O.mlp_features(om, k, M, up)[c:c + 1]
+        p = 1.0 / (1.0 + np.exp(-O.mlp_infer(Pf.astype(np.float64), X)[0]))
+        fo, margin, _ = O.tvb_flags(om, k, M, up)
+        band = lo < p < hi
+        scale = max(1.0, np.abs(up[:, 0]).max())
+        if min(abs(p - lo), abs(p - hi)) < 2e-3 or (band and margin[c] <= 1e-9 * scale):
+            continue
+        dec = int(fo[c] & 1) if band else int(p >= hi)
+        checked += 1
+        assert (fl[cell] & 1) == dec, (i, j, p, fl[cell])
+        assert ((fl[cell] & 8) != 0) == band, (i, j, p, fl[cell])
+        if dec == (fo[c] & 1):
+            lim, flo, _ = O.limit_tvb(om, k, M, up)
+            if (fl[cell] & 7) == (flo[c] & 7):
+                states += 1
+                e = np.abs(u2[:, :, cell] - lim[:, :, c]).max() / np.abs(lim[:, :, c]).max()
+                assert e < 1e-5, (i, j, e)
+    print(f"[fullsize] learned indicator: decisions checked {checked}, limited states "
+          f"checked {states}", flush=True)
+    assert checked > 150 and states > 50
