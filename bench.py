@@ -267,6 +267,8 @@ def main():
                     help="profiling runs only: skip the original-RKDG form")
     ap.add_argument("--dmr", action="store_true",
                     help="also run the double Mach reflection at 1920x480 (Q1, Q2) to t = 0.2")
+    ap.add_argument("--dmr-only", action="store_true",
+                    help="profiling runs: only the double Mach reflection study (prints its JSON)")
     ap.add_argument("--indicator", default=None,
                     help="profiling runs: .npz of a trained indicator, loaded if the file "
                          "exists, else written after training")
@@ -282,6 +284,10 @@ def main():
     from paper_2307_06471_amd import crkdg as K
     from paper_2307_06471_amd import mlp as ML
     from paper_2307_06471_amd import workloads as W
+
+    if args.dmr_only:
+        print(json.dumps({"double_mach_reflection": dmr_study(K)}), flush=True)
+        return
 
     mlp = None
     if not args.no_mlp:

@@ -70,3 +70,30 @@ def test_algorithmic_bytes_of_the_original_rkdg():
     assert bench.algorithmic_bytes("final", S * N, S * N, N, 2, "rkdg3") == 8 * S * N / 3
     assert bench.algorithmic_bytes("limit", S * N, S * N, N, 2, "rkdg3") == S * N
     assert bench.algorithmic_bytes("dt", S * N, S * N, N, 2, "rkdg3") is None
+
+
+def test_traffic_calibration_arithmetic(tmp_path):
+    """profsummary.traffic: per-dispatch mean of the kernel's counter, scaled
+    by (copy bytes) / (counter of the largest copy dispatch)"""
+    def csv(path, counter, rows):
+        with open(path, "w") as f:
+            f.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+            for name, grid, val in rows:
+                f.write(f'"{name}",{grid},{counter},{val}\n')
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    copy = 256 << 20
+    csv(fetch, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 512, 3.0),
+                              ("__amd_rocclr_copyBuffer", 131072, copy / 1024 / 2),
+                              ("void k_final2<A, 2, 1, false, false>(x)", 64, 1000.0),
+                              ("void k_final2<A, 2, 1, false, false>(x)", 64, 1200.0),
+                              ("void k_final2<A, 2, 1, true, false>(x)", 64, 9999.0)])
+    csv(write, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 131072, copy / 1024),
+                              ("void k_final2<A, 2, 1, false, false>(x)", 64, 500.0)])
+    out = tmp_path / "t.txt"
+    PS.traffic(str(fetch), str(write), "k_final2<A, 2, 1, false, false>", copy, str(out), "cmd")
+    d = PS.read_traffic(str(out))
+    assert float(d["fetch_factor"]) == 2.0 and float(d["write_factor"]) == 1.0
+    assert float(d["fetch_bytes_per_launch"]) == 1100.0 * 1024 * 2
+    assert float(d["write_bytes_per_launch"]) == 500.0 * 1024
+    assert float(d["traffic_bytes_per_launch"]) == 1100.0 * 2048 + 500.0 * 1024
+    assert d["fetch_dispatches"] == "2"
