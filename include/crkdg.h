@@ -140,7 +140,8 @@ void* crkdg_current_dofs(const crkdg_state* st);
  * stream-ordered; get_state syncs */
 int crkdg_set_state(crkdg_state* st, const double* host_dofs);
 int crkdg_get_state(const crkdg_state* st, double* host_dofs);
-/* time t^n used for time-dependent boundary data */
+/* time t^n used for time-dependent boundary data; crkdg_get_time reads the
+ * device copy back (and syncs) after crkdg_step_dev on such a mesh */
 int crkdg_set_time(crkdg_state* st, double t);
 double crkdg_get_time(const crkdg_state* st);
 
@@ -152,8 +153,12 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
 /* One cRKDG step of size dt (> 0, finite), Section 2.2 equation (crkdg); no
  * limiter.  Advances the internal time by dt. */
 int crkdg_step(crkdg_state* st, double dt);
-/* Same, with dt read from device memory (written by crkdg_compute_dt); no
- * host synchronisation.  The internal time is not advanced. */
+/* Same, with dt read from device memory (written by crkdg_compute_dt or
+ * crkdg_limit_dt); no host synchronisation.  Without time-dependent boundary
+ * data the internal time is not advanced.  With them (bc_exact), the time is
+ * kept in device memory (the library's workspace): the stages take their
+ * boundary data at t + c_i * (*dt_dev), the limiter's ghost averages at the
+ * advanced time, and crkdg_get_time reads it back (syncs). */
 int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
 
 /* One step of the original RKDG method that the paper compares against

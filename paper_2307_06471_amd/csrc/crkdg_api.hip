@@ -25,6 +25,9 @@ struct crkdg_state {
   bool subdiag;  // a_ij = 0 unless j == i - 1: inner stages need one accumulator
   // bound memory
   bool bound;
+  // time-dependent boundary data with dt in device memory: the step's time
+  // lives on the device (t_dev_ptr) and st->t is stale while this is set
+  bool t_dev_valid;
   char* dofs;
   char* work;
   hipStream_t stream;
@@ -66,6 +69,8 @@ int wave_blocks(const crkdg_state* st) { return (int)((st->geo.N + 255) / 256); 
 size_t wave_partial_bytes(const crkdg_state* st) {
   return round_up((size_t)wave_blocks(st) * sizeof(double));
 }
+// the device copy of the time (one double in the scratch area's free tail)
+double* t_dev_ptr(const crkdg_state* st) { return (double*)(scratch_ptr(st) + SCRATCH - 128); }
 double* wave_partial_ptr(const crkdg_state* st) {
   return (double*)(scratch_ptr(st) + round_up(SCRATCH));
 }
@@ -296,6 +301,7 @@ int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream) {
   st->stream = (hipStream_t)stream;
   st->bound = true;
   st->cur = 0;
+  st->t_dev_valid = false;
   return CRKDG_OK;
 }
 
@@ -369,10 +375,27 @@ int crkdg_get_state(const crkdg_state* st, double* host) {
 int crkdg_set_time(crkdg_state* st, double t) {
   if (!st || !isfinite(t)) return CRKDG_EINVAL;
   st->t = t;
+  st->t_dev_valid = false;
   return CRKDG_OK;
 }
 
-double crkdg_get_time(const crkdg_state* st) { return st ? st->t : NAN; }
+// bring the host time up to date with the device copy (syncs the stream)
+static int sync_time(crkdg_state* st) {
+  if (!st->t_dev_valid) return CRKDG_OK;
+  double t = 0.0;
+  hipError_t e = hipMemcpyAsync(&t, t_dev_ptr(st), sizeof t, hipMemcpyDeviceToHost, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  if (e != hipSuccess) return CRKDG_EHIP;
+  st->t = t;
+  st->t_dev_valid = false;
+  return CRKDG_OK;
+}
+
+double crkdg_get_time(const crkdg_state* st) {
+  if (!st) return NAN;
+  crkdg_state* w = const_cast<crkdg_state*>(st);
+  return sync_time(w) == CRKDG_OK ? w->t : NAN;
+}
 
 static int copy_params(crkdg_state* st, const double* params, int nparams, double* dst) {
   memset(dst, 0, sizeof(double) * NPARAM);
@@ -410,13 +433,15 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
   double* Pd;
   rc = upload_params(st, P, &Pd);
   if (rc) return rc;
+  if (int rs = sync_time(st)) return rs;
   hipError_t e = launch_project(st->eq, st->k, st->lay, st->ph, st->geo, ic, Pd, aux_dev, st->t,
                                 cur_ptr(st), st->stream);
   return hip_rc(e);
 }
 
 // one step with dt from the host (dt_dev == NULL) or from device memory
-static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
+static int step_impl(crkdg_state* st, double dt, const double* dt_dev,
+                     const double* t_dev = nullptr) {
   const void* un = cur_ptr(st);
   void* unew = nxt_ptr(st);
   hipError_t e = hipSuccess;
@@ -487,9 +512,11 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev) {
     fa.lay[ns] = lays[i];
     fa.w[ns] = st->b[i];
     fa.tst[ns] = st->t + st->c[i] * (dt_dev ? 0.0 : dt);
+    fa.cst[ns] = st->c[i];
     ++ns;
   }
   fa.ns = ns;
+  fa.t_ptr = t_dev;
   {
     ProfScope ps(st, KC_FINAL);
     e = launch_final(st->eq, st->k, st->prec, st->ph, st->geo, st->bc, fa, st->stream);
@@ -503,7 +530,9 @@ int crkdg_step(crkdg_state* st, double dt) {
   if (!st) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
   if (!isfinite(dt) || !(dt > 0.0)) return CRKDG_EINVAL;
-  int rc = step_impl(st, dt, nullptr);
+  int rc = sync_time(st);
+  if (rc) return rc;
+  rc = step_impl(st, dt, nullptr);
   if (rc == CRKDG_OK) st->t += dt;
   return rc;
 }
@@ -511,8 +540,17 @@ int crkdg_step(crkdg_state* st, double dt) {
 int crkdg_step_dev(crkdg_state* st, const double* dt_dev) {
   if (!st || !dt_dev) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (st->bc.exact > 0) return CRKDG_EUNSUPPORTED;  // stage times need dt on the host
-  return step_impl(st, 0.0, dt_dev);
+  if (st->bc.exact <= 0) return step_impl(st, 0.0, dt_dev);
+  // time-dependent boundary data: the stage times come from a device copy
+  // of the time, which then advances by *dt_dev on the device
+  double* td = t_dev_ptr(st);
+  if (!st->t_dev_valid) {
+    if (launch_time_set(td, st->t, st->stream) != hipSuccess) return CRKDG_EHIP;
+    st->t_dev_valid = true;
+  }
+  int rc = step_impl(st, 0.0, dt_dev, td);
+  if (rc) return rc;
+  return launch_time_add(td, dt_dev, st->stream) == hipSuccess ? CRKDG_OK : CRKDG_EHIP;
 }
 
 // forward declaration (defined with the limiter entry points below)
@@ -535,6 +573,7 @@ int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const doubl
   if (!dt_dev && (!isfinite(dt) || !(dt > 0.0))) return CRKDG_EINVAL;
   if (st->prec != P64) return CRKDG_EUNSUPPORTED;
   if (dt_dev && st->bc.exact > 0) return CRKDG_EUNSUPPORTED;  // stage times need dt on the host
+  if (int rs = sync_time(st)) return rs;
   char* u0 = cur_ptr(st);
   char* un = nxt_ptr(st);
   char* s1 = stage_ptr(st, 1);
@@ -614,6 +653,7 @@ static int limit_impl(crkdg_state* st, double M, const float* params, float tau_
   hipError_t e;
   BCDev bc = st->bc;  // time-dependent ghost averages at the state's time
   bc.t = isnan(t_ghost) ? st->t : t_ghost;
+  bc.t_ptr = isnan(t_ghost) && st->t_dev_valid ? t_dev_ptr(st) : nullptr;
   {
     ProfScope ps(st, KC_LIMIT);
     e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, bc, M, params, tau_lo, tau_hi,
@@ -669,6 +709,7 @@ int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev) {
   if (st->eq != EQ_EULER2 || st->k < 1 || st->bc.exact == CRKDG_IC_DMR) return CRKDG_EUNSUPPORTED;
   BCDev bc = st->bc;  // the limiter's ghost rules at the state's time
   bc.t = st->t;
+  bc.t_ptr = st->t_dev_valid ? t_dev_ptr(st) : nullptr;
   return hip_rc(launch_mlp_features(st->k, st->lay, st->geo, bc, M, cur_ptr(st), X_dev,
                                     st->stream));
 }

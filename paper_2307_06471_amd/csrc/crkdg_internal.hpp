@@ -29,6 +29,7 @@ struct BCDev {
   int exact;             // > 0: time-dependent Dirichlet data from this IC id
   double params[NPARAM]; // its parameters
   double t;              // limiter: time of the time-dependent ghost averages
+  const double* t_ptr;   // if set: that time is read from device memory instead
 };
 
 // double Mach reflection data in BCDev::params / projection parameters:
@@ -81,10 +82,17 @@ struct FinalArgs {
   double tst[MAXS];      // boundary-data time of each stage
   double dt;
   const double* dt_ptr;
+  // if set: the step's start time is in device memory and stage s's
+  // boundary data are taken at *t_ptr + cst[s] * dt (instead of tst[s])
+  const double* t_ptr;
+  double cst[MAXS];
 };
 
 // launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error.
 // prec: one of Prec (layouts and compute types follow from it).
+// device time of time-dependent boundary data: *t = v, or *t += *dt
+hipError_t launch_time_set(double* t, double v, hipStream_t s);
+hipError_t launch_time_add(double* t, const double* dt, hipStream_t s);
 hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const InnerArgs& a, hipStream_t s);
 hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g,

@@ -727,7 +727,8 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
     }
     if (hside >= 0) {
       R h[NC][Q];
-      halo_trace<EQ, K, LAY, DMRB>(g, ph, bc, S, hside, hci, hcj, a.tst[s], h);
+      const double tb = a.t_ptr ? *a.t_ptr + a.cst[s] * dt : a.tst[s];
+      halo_trace<EQ, K, LAY, DMRB>(g, ph, bc, S, hside, hci, hcj, tb, h);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -871,6 +872,7 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
   for (int s = 0; s < a.ns; ++s) {
     const void* __restrict__ S = a.st[s];
     const R w = a.w[s];
+    const double tb = a.t_ptr ? *a.t_ptr + a.cst[s] * dt : a.tst[s];
     R tL[NC][1], tR[NC][1], tRn[NC][1];
     if (active) {
       R U[NC][NB];
@@ -882,11 +884,11 @@ __global__ __launch_bounds__(B1) void k_final1(PhysDev ph, Geo g, BCDev bc, Fina
       for (int c = 0; c < NC; ++c) sR[c][tx + 1] = tR[c][0];
       if (tx == 0) {
         R h[NC][1];
-        neighbour_trace<EQ, K, 0>(g, ph, bc, S, i, 0, a.tst[s], tL, h);
+        neighbour_trace<EQ, K, 0>(g, ph, bc, S, i, 0, tb, tL, h);
 #pragma unroll
         for (int c = 0; c < NC; ++c) sR[c][0] = h[c][0];
       }
-      if (last_col) neighbour_trace<EQ, K, 1>(g, ph, bc, S, i, 0, a.tst[s], tR, tRn);
+      if (last_col) neighbour_trace<EQ, K, 1>(g, ph, bc, S, i, 0, tb, tR, tRn);
     }
     __syncthreads();
     if (active) {
@@ -1454,7 +1456,7 @@ __device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
           for (int c = 0; c < NC; ++c) qa[c] = c == 2 ? -avg[c] : avg[c];
         } else {
           double q[4];
-          dmr_state(bc.params, xg, yg, bc.t, q);
+          dmr_state(bc.params, xg, yg, bc.t_ptr ? *bc.t_ptr : bc.t, q);
 #pragma unroll
           for (int c = 0; c < NC; ++c) qa[c] = q[c];
         }
@@ -1988,6 +1990,16 @@ struct RunLimit {
   }
 };
 
+__global__ void k_time_set(double* t, double v) { *t = v; }
+__global__ void k_time_add(double* t, const double* dt) { *t += *dt; }
+hipError_t launch_time_set(double* t, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_set, dim3(1), dim3(1), 0, s, t, v);
+  return hipGetLastError();
+}
+hipError_t launch_time_add(double* t, const double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_add, dim3(1), dim3(1), 0, s, t, dt);
+  return hipGetLastError();
+}
 hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const InnerArgs& a, hipStream_t s) {
   switch (prec) {

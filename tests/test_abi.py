@@ -149,7 +149,6 @@ def test_double_mach_reflection_mesh_checks():
     assert L.crkdg_limit_mlp(h, 50.0, fake, 0.2, 0.9, None, None) == K.CRKDG_EUNSUPPORTED
     assert L.crkdg_mlp_features(h, 50.0, fake) == K.CRKDG_EUNSUPPORTED
     assert L.crkdg_limit_dt(h, 50.0, fake, 0.2, 0.9, None, 0.1, fake) == K.CRKDG_EUNSUPPORTED
-    assert L.crkdg_step_dev(h, fake) == K.CRKDG_EUNSUPPORTED  # stage times need dt on the host
     assert L.crkdg_project(h, K.IC_DMR, (C.c_double * 1)(1.0), 1, None) == K.CRKDG_EINVAL
     L.crkdg_destroy(h)
     for bad in (dict(bc=(2, 2, 2, 2)), dict(bc=(0, 1, 2, 2)), dict(equation=K.EQ_ADVECTION)):

@@ -126,3 +126,55 @@ def test_dmr_paper_run_480x120(K):
     diff = np.abs(out[False] - out[True]).sum() / np.abs(out[True]).sum()
     print(f"[dmr] cRKDG vs RKDG relative L1 density difference {diff:.4f}", flush=True)
     assert diff < 0.05
+
+
+def test_device_dt_path_equals_host_path(K):
+    """dt kept on the device (crkdg_compute_dt, then crkdg_step_dev and
+    crkdg_limit_dt per step): the moving-shock data take the device copy of
+    the time, and the run is bit for bit the host-dt run with the same dt
+    sequence (cfl / s_max of the limited state)"""
+    import torch
+    nx, ny, k = 96, 24, 2
+    a = gpu_solver(K, nx, ny, k)
+    b = gpu_solver(K, nx, ny, k)
+    for s in (a, b):
+        s.crkdg_limit(M_TVB)
+    for _ in range(30):
+        dt = 0.1 / a.crkdg_max_wavespeed()
+        a.crkdg_step(dt)
+        a.crkdg_limit(M_TVB)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    b.crkdg_compute_dt(0.1, dt_dev)
+    for _ in range(30):
+        b.crkdg_step_dev(dt_dev)
+        b.crkdg_limit_dt(M_TVB, 0.1, dt_dev)
+    assert b.crkdg_get_time() == a.crkdg_get_time() > 0.0
+    assert np.array_equal(a.crkdg_get_state(), b.crkdg_get_state())
+    # and a host step after device steps continues from the device time
+    for s in (a, b):
+        s.crkdg_step(1e-5)
+    assert b.crkdg_get_time() == a.crkdg_get_time()
+    assert np.array_equal(a.crkdg_get_state(), b.crkdg_get_state())
+
+
+def test_device_dt_inflow_stage_times(K):
+    """1D advection with inflow data sin(-t) (Section 3.4): device dt gives
+    the host-dt result bit for bit"""
+    import torch
+    N, k, L = 80, 2, 4 * np.pi
+    runs = []
+    for dev in (False, True):
+        lm = K.make_mesh(1, N, 1, x0=0.0, x1=L, bc=(2, 1, 0, 0), bc_exact=K.IC_ADV_SIN,
+                         equation=K.EQ_ADVECTION, adv=(1.0, 0.0))
+        s = K.Solver(lm, k, K.FLUX_UPWIND, 3)
+        s.crkdg_project(K.IC_ADV_SIN)
+        dt = 0.16 * L / N
+        dt_dev = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+        for _ in range(40):
+            if dev:
+                s.crkdg_step_dev(dt_dev)
+            else:
+                s.crkdg_step(dt)
+        runs.append((s.crkdg_get_time(), s.crkdg_get_state()))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
