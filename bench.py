@@ -183,10 +183,12 @@ def train_indicator(K, ML):
 
 def dmr_run(K, k, nx, ny, precision, rkdg, T=0.2, M=50.0, cfl=0.1):
     """the paper's double Mach reflection (Section 4): projection, one limiter
-    pass on the projected jump, then steps to T with dt = cfl / s_max from the
-    host (the moving-shock boundary data need each stage's time); the limiter
-    after every step (cRKDG) or inside every stage (RKDG).  Wall time covers
-    the whole run, host synchronisation included."""
+    pass on the projected jump, then steps to T with dt = cfl / s_max; the
+    limiter after every step (cRKDG) or inside every stage (RKDG).  Both keep
+    dt and the time on the device (cRKDG: crkdg_step_dev + crkdg_limit_dt;
+    RKDG: crkdg_step_rkdg with dt in device memory + crkdg_compute_dt), read
+    the time back every 256 steps and take host steps only to land on T.
+    Wall time covers the whole run, host synchronisation included."""
     import torch
     lm = K.make_mesh(2, nx, ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, bc=(2, 1, 2, 2),
                      bc_exact=K.IC_DMR, equation=K.EQ_EULER, gamma=1.4, precision=precision)
@@ -196,6 +198,19 @@ def dmr_run(K, k, nx, ny, precision, rkdg, T=0.2, M=50.0, cfl=0.1):
     torch.cuda.synchronize()
     t, n = 0.0, 0
     t0 = time.perf_counter()
+    chunk = 256
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.crkdg_compute_dt(cfl, dt_dev)
+    while t + 2 * chunk * float(dt_dev.item()) < T:
+        for _ in range(chunk):
+            if rkdg:
+                s.crkdg_step_rkdg(3, 0.0, M=M, dt_tensor=dt_dev)
+                s.crkdg_compute_dt(cfl, dt_dev)
+            else:
+                s.crkdg_step_dev(dt_dev)
+                s.crkdg_limit_dt(M, cfl, dt_dev)
+        n += chunk
+        t = s.crkdg_get_time()
     while t < T:
         dt = min(cfl / s.crkdg_max_wavespeed(), T - t)
         if rkdg:

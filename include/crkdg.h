@@ -167,10 +167,11 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
  * operator with face fluxes and boundary data at its stage time and, when
  * M >= 0, the TVB limiter of crkdg_limit (no flags); M < 0 skips the limiter.
  * FP64 state only (CRKDG_EUNSUPPORTED otherwise).  dt_dev (device double,
- * nullable) overrides dt, as in crkdg_step_dev: then the internal time is not
- * advanced and time-dependent boundary data are CRKDG_EUNSUPPORTED;
- * otherwise dt must be finite and > 0 and the time advances by dt.  Uses
- * the workspace's first stage slot; stream-ordered, no sync. */
+ * nullable) overrides dt, as in crkdg_step_dev (with time-dependent boundary
+ * data the time is kept and advanced in device memory, the stages' data and
+ * limiter ghosts read it there); otherwise dt must be finite and > 0 and the
+ * time advances by dt.  Uses the workspace's first stage slot; stream-ordered,
+ * no sync. */
 int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const double* dt_dev);
 
 /* dt = cfl / max_K [ (|u|+c)/dx + (|v|+c)/dy ] from the FP64 cell averages

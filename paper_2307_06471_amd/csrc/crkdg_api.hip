@@ -556,7 +556,8 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev) {
 // forward declaration (defined with the limiter entry points below)
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
                       uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl,
-                      double* dt_dev, void* target, double t_ghost);
+                      double* dt_dev, void* target, double t_ghost, const double* ghost_dt,
+                      double ghost_fac);
 
 // The original RKDG in the Shu--Osher SSP form (Section 2.1; the comparison
 // scheme of Section 4): every stage applies the DG operator with face fluxes
@@ -572,15 +573,25 @@ int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const doubl
   if ((order != 2 && order != 3) || isnan(M)) return CRKDG_EINVAL;
   if (!dt_dev && (!isfinite(dt) || !(dt > 0.0))) return CRKDG_EINVAL;
   if (st->prec != P64) return CRKDG_EUNSUPPORTED;
-  if (dt_dev && st->bc.exact > 0) return CRKDG_EUNSUPPORTED;  // stage times need dt on the host
-  if (int rs = sync_time(st)) return rs;
+  // time-dependent boundary data with dt on the device: the time lives in
+  // device memory (as in crkdg_step_dev); otherwise on the host
+  const bool tdev = dt_dev && st->bc.exact > 0;
+  double* td = t_dev_ptr(st);
+  if (tdev && !st->t_dev_valid) {
+    if (launch_time_set(td, st->t, st->stream) != hipSuccess) return CRKDG_EHIP;
+    st->t_dev_valid = true;
+  }
+  if (!tdev)
+    if (int rs = sync_time(st)) return rs;
   char* u0 = cur_ptr(st);
   char* un = nxt_ptr(st);
   char* s1 = stage_ptr(st, 1);
   const double h = dt_dev ? 0.0 : dt;  // stage times of boundary data
   auto pass = [&](const void* base2, double bw1, double bw2, const void* stage, double w,
-                  double t_bc, void* out) {
+                  double t_bc, double c, void* out) {
     FinalArgs fa{};
+    fa.t_ptr = tdev ? td : nullptr;
+    fa.cst[0] = c;
     fa.base = u0;
     fa.lay_base = st->lay;
     fa.base2 = base2;
@@ -600,25 +611,28 @@ int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const doubl
                ? CRKDG_OK
                : CRKDG_EHIP;
   };
-  // each stage is limited with ghost data at the time it approximates
-  auto limit = [&](void* u, double tl) {
-    return M < 0.0 ? CRKDG_OK
-                   : limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u,
-                                tl);
+  // each stage is limited with ghost data at the time it approximates, t + f dt
+  auto limit = [&](void* u, double f) {
+    if (M < 0.0) return (int)CRKDG_OK;
+    return tdev ? limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u, NAN,
+                             dt_dev, f)
+                : limit_impl(st, M, nullptr, 0.f, 0.f, nullptr, nullptr, 1, 0.0, nullptr, u,
+                             st->t + f * h, nullptr, 0.0);
   };
   const double t = st->t;
-  int rc = pass(nullptr, 1.0, 0.0, u0, 1.0, t, s1);  // u^(1) = u^n - dt DG(u^n)
-  if (!rc) rc = limit(s1, t + h);
+  int rc = pass(nullptr, 1.0, 0.0, u0, 1.0, t, 0.0, s1);  // u^(1) = u^n - dt DG(u^n)
+  if (!rc) rc = limit(s1, 1.0);
   if (order == 2) {  // u^{n+1} = u^n / 2 + (u^(1) - dt DG(u^(1))) / 2
-    if (!rc) rc = pass(s1, 0.5, 0.5, s1, 0.5, t + h, un);
-    if (!rc) rc = limit(un, t + h);
+    if (!rc) rc = pass(s1, 0.5, 0.5, s1, 0.5, t + h, 1.0, un);
+    if (!rc) rc = limit(un, 1.0);
     if (!rc) st->cur ^= 1;
   } else {  // u^(2) = 3/4 u^n + 1/4 (u^(1) - dt DG(u^(1))), then the third stage
-    if (!rc) rc = pass(s1, 0.75, 0.25, s1, 0.25, t + h, un);
-    if (!rc) rc = limit(un, t + 0.5 * h);
-    if (!rc) rc = pass(un, 1.0 / 3.0, 2.0 / 3.0, un, 2.0 / 3.0, t + 0.5 * h, u0);
-    if (!rc) rc = limit(u0, t + h);
+    if (!rc) rc = pass(s1, 0.75, 0.25, s1, 0.25, t + h, 1.0, un);
+    if (!rc) rc = limit(un, 0.5);
+    if (!rc) rc = pass(un, 1.0 / 3.0, 2.0 / 3.0, un, 2.0 / 3.0, t + 0.5 * h, 0.5, u0);
+    if (!rc) rc = limit(u0, 1.0);
   }
+  if (!rc && tdev) rc = launch_time_add(td, dt_dev, st->stream) == hipSuccess ? CRKDG_OK : CRKDG_EHIP;
   if (!rc && !dt_dev) st->t += dt;
   return rc;
 }
@@ -647,13 +661,17 @@ int crkdg_max_wavespeed(crkdg_state* st, double* smax) {
 
 static int limit_impl(crkdg_state* st, double M, const float* params, float tau_lo, float tau_hi,
                       uint8_t* flags_dev, int64_t* counts, int ncounts, double cfl = 0.0,
-                      double* dt_dev = nullptr, void* target = nullptr, double t_ghost = NAN) {
+                      double* dt_dev = nullptr, void* target = nullptr, double t_ghost = NAN,
+                      const double* ghost_dt = nullptr, double ghost_fac = 0.0) {
   unsigned long long* counters =
       counts ? (unsigned long long*)(scratch_ptr(st) + SCRATCH - 64) : nullptr;
   hipError_t e;
   BCDev bc = st->bc;  // time-dependent ghost averages at the state's time
   bc.t = isnan(t_ghost) ? st->t : t_ghost;
+  // with the time on the device: *t (+ ghost_fac * *ghost_dt within a step)
   bc.t_ptr = isnan(t_ghost) && st->t_dev_valid ? t_dev_ptr(st) : nullptr;
+  bc.dt_ptr = bc.t_ptr ? ghost_dt : nullptr;
+  bc.dt_fac = ghost_fac;
   {
     ProfScope ps(st, KC_LIMIT);
     e = launch_limit(st->eq, st->k, st->lay, st->ph, st->geo, bc, M, params, tau_lo, tau_hi,

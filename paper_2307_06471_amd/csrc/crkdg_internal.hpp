@@ -29,7 +29,9 @@ struct BCDev {
   int exact;             // > 0: time-dependent Dirichlet data from this IC id
   double params[NPARAM]; // its parameters
   double t;              // limiter: time of the time-dependent ghost averages
-  const double* t_ptr;   // if set: that time is read from device memory instead
+  const double* t_ptr;   // if set: that time is *t_ptr (+ dt_fac * *dt_ptr if
+  const double* dt_ptr;  // dt_ptr is set), read from device memory
+  double dt_fac;
 };
 
 // double Mach reflection data in BCDev::params / projection parameters:

@@ -1456,7 +1456,9 @@ __device__ __forceinline__ void limit_neighbours(const Geo& g, const BCDev& bc,
           for (int c = 0; c < NC; ++c) qa[c] = c == 2 ? -avg[c] : avg[c];
         } else {
           double q[4];
-          dmr_state(bc.params, xg, yg, bc.t_ptr ? *bc.t_ptr : bc.t, q);
+          const double tl =
+              bc.t_ptr ? *bc.t_ptr + (bc.dt_ptr ? bc.dt_fac * *bc.dt_ptr : 0.0) : bc.t;
+          dmr_state(bc.params, xg, yg, tl, q);
 #pragma unroll
           for (int c = 0; c < NC; ++c) qa[c] = q[c];
         }

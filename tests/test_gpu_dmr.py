@@ -178,3 +178,24 @@ def test_device_dt_inflow_stage_times(K):
         runs.append((s.crkdg_get_time(), s.crkdg_get_state()))
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_rkdg_device_dt_equals_host_dt(K):
+    """the original RKDG with dt in device memory on the moving-shock data:
+    stage data at t, t + dt, t + dt/2 and stage limiter ghosts at t + dt,
+    t + dt/2, t + dt from the device copy of the time, bit for bit the host
+    run with the same dt sequence"""
+    import torch
+    nx, ny, k = 96, 24, 1
+    a = gpu_solver(K, nx, ny, k)
+    b = gpu_solver(K, nx, ny, k)
+    for s in (a, b):
+        s.crkdg_limit(M_TVB)
+    for _ in range(20):
+        a.crkdg_step_rkdg(3, 0.1 / a.crkdg_max_wavespeed(), M=M_TVB)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        b.crkdg_compute_dt(0.1, dt_dev)
+        b.crkdg_step_rkdg(3, 0.0, M=M_TVB, dt_tensor=dt_dev)
+    assert b.crkdg_get_time() == a.crkdg_get_time() > 0.0
+    assert np.array_equal(a.crkdg_get_state(), b.crkdg_get_state())
