@@ -130,8 +130,8 @@ def train_indicator(K, ML):
     """train the learned troubled-cell indicator with the library's own kernels
     on runs labelled by the FP64 TVB test (M = 50): four-quadrant Riemann
     problems and planar-shock problems with seeds other than the benchmark's.
-    Round 1 learns from runs limited by the TVB test; round 2 adds runs
-    limited by the round-1 indicator (labels still from the TVB test on the
+    Pass 1 learns from runs limited by the TVB test; pass 2 adds runs
+    limited by the pass-1 indicator (labels still from the TVB test on the
     same states) and retrains on both, so the network sees the states it
     meets in use.  The decision band comes from held-out seeds."""
     t0 = time.perf_counter()
@@ -167,10 +167,10 @@ def train_indicator(K, ML):
     rv2 = ML.rates(P, *cat(va2), lo, hi)
     t2 = time.perf_counter()
     return P, lo, hi, {
-        "train": "round 1: four-quadrant Riemann problems (seeds 0-31, 128x128 Q2, to 0.25 "
+        "train": "pass 1: four-quadrant Riemann problems (seeds 0-31, 128x128 Q2, to 0.25 "
                  "domain crossings) + planar-shock problems (seeds 2100-2107 at 1024x256 to "
                  "T=0.25; seeds 2100-2103 at 4096x1024, 400 steps), limited by the TVB test; "
-                 "round 2: the same shock runs and quadrant seeds 0-15 limited by the round-1 "
+                 "pass 2: the same shock runs and quadrant seeds 0-15 limited by the pass-1 "
                  "indicator; labels always the FP64 TVB test, M=50",
         "validation_sets": "quadrant seeds 64-71; shock seeds 2200-2201 at 1024x256, 2200 at "
                            "4096x1024 (400 steps); both policies",
