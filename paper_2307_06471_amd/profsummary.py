@@ -3,6 +3,11 @@
   python -m paper_2307_06471_amd.profsummary stats <kernel_stats.csv> <out.txt> <title> <command>
       per-kernel calls, average and total duration (from --kernel-trace --stats)
 
+  python -m paper_2307_06471_amd.profsummary counters <counter_collection.csv>
+      "<kernel>;<kernel>;..." <out.txt> <command>
+      per-dispatch SQ/GRBM counter averages of the named kernels and the
+      VALU-instructions-per-wave, VALU-busy and memory-wait ratios
+
   python -m paper_2307_06471_amd.profsummary traffic <fetch counter_collection.csv>
       <write counter_collection.csv> <kernel substring> <copy_bytes> <out.txt> <command>
       HBM traffic of one kernel per launch: FETCH_SIZE and WRITE_SIZE (KiB per
@@ -84,6 +89,46 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, out, command):
         f.write("\n".join(lines) + "\n")
 
 
+def counters(csv_path, kernels, out, command, simds=1024, xcds=8):
+    """per-dispatch averages of the SQ/GRBM counters of one rocprofv3 --pmc
+    run for each kernel name given in full, and three ratios:
+      valu_insts_per_wave = SQ_INSTS_VALU / SQ_WAVES
+      valu_busy = 4 SQ_ACTIVE_INST_VALU / (simds * GRBM_GUI_ACTIVE / xcds)
+        (SQ_ACTIVE_INST_VALU counts in units of 4 cycles; GRBM_GUI_ACTIVE is
+        summed over the XCDs)
+      wait_fraction = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of the waves'
+        lifetime spent waiting for memory results)"""
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [f"# SQ counters per dispatch", "",
+             "command (repo root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):",
+             f"  {command}", "", f"kernel source hash: {kernel_source_hash()}", ""]
+    for k in kernels:
+        vals = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            if name.startswith("void "):
+                name = name[5:]
+            if name.split("(")[0].replace("crk::", "") != k:
+                continue
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if not vals:
+            raise SystemExit(f"no rows for kernel {k!r} in {csv_path}")
+        avg = {c: sum(v) / len(v) for c, v in vals.items()}
+        lines.append(f"{k}: dispatches {len(next(iter(vals.values())))}")
+        for c in sorted(avg):
+            lines.append(f"  {c}: {avg[c]:.6g}")
+        if "SQ_INSTS_VALU" in avg and "SQ_WAVES" in avg:
+            lines.append(f"  valu_insts_per_wave: {avg['SQ_INSTS_VALU'] / avg['SQ_WAVES']:.1f}")
+        if "SQ_ACTIVE_INST_VALU" in avg and "GRBM_GUI_ACTIVE" in avg:
+            busy = 4.0 * avg["SQ_ACTIVE_INST_VALU"] / (simds * avg["GRBM_GUI_ACTIVE"] / xcds)
+            lines.append(f"  valu_busy: {busy:.3f}")
+        if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+            lines.append(f"  wait_fraction: {avg['SQ_WAIT_INST_ANY'] / avg['SQ_WAVE_CYCLES']:.3f}")
+        lines.append("")
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def read_traffic(path):
     """the key: value lines of a traffic summary, or None"""
     if not os.path.exists(path):
@@ -101,5 +146,7 @@ if __name__ == "__main__":
         stats(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], sys.argv[7])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3].split(";"), sys.argv[4], sys.argv[5])
     else:
         raise SystemExit(__doc__)

@@ -97,3 +97,19 @@ def test_traffic_calibration_arithmetic(tmp_path):
     assert float(d["write_bytes_per_launch"]) == 500.0 * 1024
     assert float(d["traffic_bytes_per_launch"]) == 1100.0 * 2048 + 500.0 * 1024
     assert d["fetch_dispatches"] == "2"
+
+
+def test_counter_summary_ratios(tmp_path):
+    f = tmp_path / "c.csv"
+    with open(f, "w") as fh:
+        fh.write("Kernel_Name,Counter_Name,Counter_Value\n")
+        for c, v in (("SQ_WAVES", 100), ("SQ_INSTS_VALU", 50000), ("SQ_ACTIVE_INST_VALU", 2560),
+                     ("GRBM_GUI_ACTIVE", 80), ("SQ_WAIT_INST_ANY", 30), ("SQ_WAVE_CYCLES", 120)):
+            fh.write(f'"void crk::k_final2<A, 2, 1, false, false>(x, y)",{c},{v}\n')
+            fh.write(f'"void crk::k_final2<A, 2, 1, true, false>(x, y)",{c},{2 * v}\n')
+    out = tmp_path / "o.txt"
+    PS.counters(str(f), ["k_final2<A, 2, 1, false, false>"], str(out), "cmd", simds=16, xcds=8)
+    d = dict(l.strip().split(": ", 1) for l in open(out) if l.startswith("  ") and ": " in l)
+    assert float(d["valu_insts_per_wave"]) == 500.0
+    assert float(d["valu_busy"]) == 4 * 2560 / (16 * 80 / 8)
+    assert float(d["wait_fraction"]) == 0.25
