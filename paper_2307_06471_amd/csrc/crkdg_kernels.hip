@@ -167,6 +167,35 @@ __device__ __forceinline__ void store_state(void* __restrict__ p, long long N, l
   }
 }
 
+// the higher modes only (the limiter never changes a cell average)
+template <class T, int NC, int NB, int LAY>
+__device__ __forceinline__ void store_higher_modes(void* __restrict__ p, long long N, long long cell,
+                                                   const T (&u)[NC][NB]) {
+  const unsigned o8 = (unsigned)cell * 8u, o4 = (unsigned)cell * 4u;
+  if constexpr (LAY == L64) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 8));
+#pragma unroll
+      for (int b = 1; b < NB; ++b) bstore<double>((double)u[c][b], r, o8, (unsigned)(b * N * 8));
+    }
+  } else if constexpr (LAY == LMIX) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const auto rh = rsrc(byte_add(p, (long long)NC * N * 8 + (long long)c * (NB - 1) * N * 4));
+#pragma unroll
+      for (int b = 1; b < NB; ++b) bstore<float>((float)u[c][b], rh, o4, (unsigned)((b - 1) * N * 4));
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const auto r = rsrc(byte_add(p, (long long)c * NB * N * 4));
+#pragma unroll
+      for (int b = 1; b < NB; ++b) bstore<float>((float)u[c][b], r, o4, (unsigned)(b * N * 4));
+    }
+  }
+}
+
 // cell average of component c (mode 0), as double
 template <int NC, int NB, int LAY>
 __device__ __forceinline__ double load_avg(const void* __restrict__ p, long long N, int c,
@@ -1764,7 +1793,7 @@ __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_li
             for (int b = 1; b < NB; ++b) V[c][b] = 0.0;
         }
       }
-      store_state<double, NC, NB, LAY>(u, g.N, qc, V, avg);
+      store_higher_modes<double, NC, NB, LAY>(u, g.N, qc, V);
     }
     if (flags) flags[qc] = f;
     if (counters && (f & 7)) atomicAdd(&cnt[0], 1u);
