@@ -16,12 +16,13 @@ from . import build as _build
 
 _LIB = None
 
-EQ_ADVECTION, EQ_EULER = 0, 1
-FLUX_UPWIND, FLUX_LLF = 0, 1
+EQ_ADVECTION, EQ_EULER, EQ_BURGERS = 0, 1, 2
+FLUX_UPWIND, FLUX_LLF, FLUX_GODUNOV = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
 IC_DMR = 7  # double Mach reflection (Section 4)
+IC_BURGERS_SIN = 8  # 1D Burgers, u(x, 0) = sin x (Section 4.1.1)
 
 N_MLP_PARAMS = 12 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 

@@ -61,7 +61,7 @@ int or_gauss(int n, double* x, double* w) {
 }
 
 int or_ncomp(const or_mesh* m) {
-  if (m->equation == OR_EQ_ADVECTION) return 1;
+  if (m->equation == OR_EQ_ADVECTION || m->equation == OR_EQ_BURGERS) return 1;
   return m->dim + 2;
 }
 
@@ -124,6 +124,10 @@ static void phys_flux(const or_mesh* m, const double* q, int d, double* f) {
     f[0] = m->adv[d] * q[0];
     return;
   }
+  if (m->equation == OR_EQ_BURGERS) { /* Section 4.1.1, example 'ex:1dburgers' */
+    f[0] = 0.5 * q[0] * q[0];
+    return;
+  }
   double p = pressure(m, q);
   if (m->dim == 1) {
     double w = q[1] / q[0];
@@ -149,21 +153,41 @@ static void phys_flux(const or_mesh* m, const double* q, int d, double* f) {
 /* largest |eigenvalue| of d f_d / d u */
 static double spectral_radius(const or_mesh* m, const double* q, int d) {
   if (m->equation == OR_EQ_ADVECTION) return fabs(m->adv[d]);
+  if (m->equation == OR_EQ_BURGERS) return fabs(q[0]);
   double p = pressure(m, q);
   double c = sqrt(m->gamma * p / q[0]);
   return fabs(q[1 + d] / q[0]) + c;
 }
 
+/* Godunov flux of Burgers' equation (Section 4.1.1, example 'ex:1dburgers')
+ * between the left trace a and the right trace b: the exact Riemann solution
+ * at the face.  For the convex flux f(u) = u^2/2 that is the minimum of f over
+ * [a, b] when a <= b, the maximum of f(a), f(b) when a > b. */
+static double godunov_burgers(double a, double b) {
+  double fa = 0.5 * a * a, fb = 0.5 * b * b;
+  if (a <= b) {
+    if (a >= 0.0) return fa;
+    if (b <= 0.0) return fb;
+    return 0.0; /* the sonic point u = 0 lies in [a, b] */
+  }
+  return fa > fb ? fa : fb;
+}
+
 /* numerical flux f^ . nu on a face with outward normal nu = s e_d (s = +-1),
  * interior trace qi, exterior trace qe.  Lax--Friedrichs (Section 2.1) with
  * alpha the pointwise larger spectral radius of the two traces; the upwind
- * flux for linear advection. */
+ * flux for linear advection; the Godunov flux for Burgers' equation. */
 static void num_flux(const or_mesh* m, const double* qi, const double* qe, int d, double s,
                      double* F) {
   int nc = or_ncomp(m);
   if (m->flux == OR_FLUX_UPWIND && m->equation == OR_EQ_ADVECTION) {
     double an = s * m->adv[d];
     F[0] = an >= 0.0 ? an * qi[0] : an * qe[0];
+    return;
+  }
+  if (m->flux == OR_FLUX_GODUNOV) {
+    /* the left state of the face (in +x) is the interior one when nu = +e_x */
+    F[0] = s > 0.0 ? godunov_burgers(qi[0], qe[0]) : -godunov_burgers(qe[0], qi[0]);
     return;
   }
   double fi[OR_MAXC], fe[OR_MAXC];
@@ -316,6 +340,20 @@ static void exact_state(const or_mesh* m, int ic, const double* P, const double*
       for (int c = 0; c < nc; ++c) q[c] = behind ? post[c] : pre[c];
       return;
     }
+    case OR_IC_BURGERS_SIN: {
+      /* characteristics: u(x, t) = u0(x - u t) with u0 = sin.  g(u) = u -
+       * sin(x - u t) has g' = 1 + t cos(x - u t) >= 1 - t > 0 for t < 1, so
+       * Newton's method from u = sin(x) converges; iterate to a fixed point */
+      double u = sin(x);
+      for (int it = 0; it < 100; ++it) {
+        double g = u - sin(x - u * t), dg = 1.0 + t * cos(x - u * t);
+        double un = u - g / dg;
+        if (un == u) break;
+        u = un;
+      }
+      q[0] = u;
+      return;
+    }
     default:
       for (int c = 0; c < nc; ++c) q[c] = NAN;
   }
@@ -460,6 +498,9 @@ int or_apply(const or_mesh* m, int k, int op, double t_bc, const double* u, doub
   int nc = or_ncomp(m), nb = or_nmodes(m, k), N = ncells(m);
   if (k < 0 || k > 5 || nb > OR_MAXB) return -1;
   if (m->equation == OR_EQ_EULER && m->flux == OR_FLUX_UPWIND) return -2;
+  if ((m->flux == OR_FLUX_GODUNOV) != (m->equation == OR_EQ_BURGERS) ||
+      (m->equation == OR_EQ_BURGERS && m->dim != 1))
+    return -2;
   basis_tab* T = (basis_tab*)malloc(sizeof(basis_tab));
   if (!T) return -1;
   tabulate(m, k, T);

@@ -38,8 +38,8 @@
 extern "C" {
 #endif
 
-enum { OR_EQ_ADVECTION = 0, OR_EQ_EULER = 1 };
-enum { OR_FLUX_UPWIND = 0, OR_FLUX_LLF = 1 };
+enum { OR_EQ_ADVECTION = 0, OR_EQ_EULER = 1, OR_EQ_BURGERS = 2 /* 1D only */ };
+enum { OR_FLUX_UPWIND = 0, OR_FLUX_LLF = 1, OR_FLUX_GODUNOV = 2 /* Burgers only */ };
 enum { OR_BC_PERIODIC = 0, OR_BC_TRANSMISSIVE = 1, OR_BC_DIRICHLET = 2 };
 enum { OR_OP_LOC = 0, OR_OP_DG = 1 };
 
@@ -53,11 +53,13 @@ enum {
   OR_IC_SHOCK = 5,          /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
                                aux: cell-centre noise field xi[ny][nx]                    */
   OR_IC_ADV_SIN_1D_SHIFT = 6, /* 1D advection sin(x - a t) used as inflow data           */
-  OR_IC_DMR = 7             /* double Mach reflection: the planar Mach 10 shock through
+  OR_IC_DMR = 7,            /* double Mach reflection: the planar Mach 10 shock through
                                (1/6, 0) at 60 degrees, moved to time t (no params).  As
                                bc_exact: Dirichlet sides take this solution at the face
                                point, except the bottom side from x = 1/6 on, which is a
                                reflecting wall (interior trace, normal momentum mirrored) */
+  OR_IC_BURGERS_SIN = 8     /* 1D Burgers: u(x, 0) = sin(x); at time t (before the shock
+                               forms at t = 1) the solution of u = sin(x - u t)        */
 };
 
 typedef struct {
