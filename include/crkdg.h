@@ -10,7 +10,7 @@
  *     u^{n+1} = u^n - dt sum_i b_i DG(u^(i))                    (final stage)
  * where loc is the element-local projected derivative of equation (dxl) and
  * DG the DG operator of equation (DG operator) with a Lax--Friedrichs (or, for
- * linear advection, upwind) face flux.  Boundary data enter only the final
+ * linear advection, upwind; for Burgers' equation, Godunov) face flux.  Boundary data enter only the final
  * stage (Section 3.4).  A limiter is applied once per step, after the final
  * stage (Section 2.2, remark on limiters; Section 4.2).
  *
@@ -60,8 +60,12 @@ extern "C" {
 #define CRKDG_EHIP (-4)          /* HIP runtime or launch failure */
 #define CRKDG_EUNBOUND (-5)      /* state used before crkdg_bind */
 
-enum { CRKDG_EQ_ADVECTION = 0, CRKDG_EQ_EULER = 1 };
-enum { CRKDG_FLUX_UPWIND = 0, CRKDG_FLUX_LLF = 1 };
+/* CRKDG_EQ_BURGERS: u_t + (u^2/2)_x = 0 in 1D (Section 4.1.1, example
+ * 'ex:1dburgers'), with CRKDG_FLUX_GODUNOV only (the exact Riemann solution's
+ * flux at the face: min of u^2/2 over [uL, uR] if uL <= uR, else the larger
+ * of uL^2/2, uR^2/2) */
+enum { CRKDG_EQ_ADVECTION = 0, CRKDG_EQ_EULER = 1, CRKDG_EQ_BURGERS = 2 };
+enum { CRKDG_FLUX_UPWIND = 0, CRKDG_FLUX_LLF = 1, CRKDG_FLUX_GODUNOV = 2 };
 enum { CRKDG_BC_PERIODIC = 0, CRKDG_BC_TRANSMISSIVE = 1, CRKDG_BC_DIRICHLET = 2 };
 enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1, CRKDG_FP32_INNER = 2 };
 enum { CRKDG_OP_LOC = 0, CRKDG_OP_DG = 1 };
@@ -75,7 +79,7 @@ enum {
   CRKDG_IC_QUADRANT = 4,    /* params: xs, ys, then (rho,u,v,p) for NE, NW, SW, SE        */
   CRKDG_IC_SHOCK = 5,       /* params: theta, rho_s, un_s, p_s, x0, y0, rho_floor, amp;
                                aux: cell-centre field xi[ny][nx] (device, FP64)          */
-  CRKDG_IC_DMR = 6          /* double Mach reflection (Section 4, example "Double Mach
+  CRKDG_IC_DMR = 6,         /* double Mach reflection (Section 4, example "Double Mach
                                reflection"): a Mach 10 shock moving right into gas at rest
                                (rho, p) = (1.4, 1), through (1/6, 0) at 60 degrees to the
                                x-axis at t = 0, post-shock state from the Rankine--Hugoniot
@@ -89,6 +93,8 @@ enum {
                                time (crkdg_get_time).  The learned indicator
                                (crkdg_limit_mlp, crkdg_mlp_features, crkdg_limit_dt with
                                parameters) is CRKDG_EUNSUPPORTED on such a mesh. */
+  CRKDG_IC_BURGERS_SIN = 7  /* 1D Burgers: u(x, 0) = sin x; at time t < 1 (before the shock
+                               forms) the solution of u = sin(x - u t) (no params) */
 };
 
 typedef struct {
@@ -108,10 +114,16 @@ typedef struct {
 
 typedef struct crkdg_state crkdg_state;
 
-/* Create a handle (host only; no device work).  k = 0..3 polynomial degree
- * (Q^k on rectangles, P^k in 1D; Section 2.1).  flux: CRKDG_FLUX_*.
+/* Create a handle (host only; no device work).  k = 0..4 polynomial degree
+ * (Q^k on rectangles, P^k in 1D; Section 2.1); k = 4 for the scalar
+ * equations (advection, Burgers) only.  flux: CRKDG_FLUX_*.
  * rk_stages selects the paper's tableaus: 1 forward Euler, 2 scheme (eq:2),
- * 3 scheme (eq:3), 4 classical RK4 (Section 2.2 and Section 4).
+ * 3 scheme (eq:3), 4 classical RK4, 5 the fifth-order Runge--Kutta--Fehlberg
+ * method (six stages; Section 4 pairs it with k = 4).  RK4's tableau has
+ * only a subdiagonal, so its inner stages run as one element-local pass;
+ * Fehlberg's full tableau takes the materialised path (FP64 only: one pass
+ * per inner stage writing loc(u^(j)), then a combination pass).
+ * The workspace holds the stage states of max(4, stages) stages.
  * Returns CRKDG_EINVAL for bad sizes/arguments, including meshes whose
  * cells x max((k+1)^dim, 4) x 8 bytes reach 4 GiB (one component of one
  * state must stay below 4 GiB: 59.6 M cells for Q2, 33.5 M for Q3),
@@ -120,8 +132,11 @@ typedef struct crkdg_state crkdg_state;
 int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out);
 
 /* Replace the tableau by an explicit one (Section 2.1, equation (butcher)):
- * s <= 4 stages, A row-major s*s strictly lower triangular (a_ij = 0 for
- * j >= i), b and c of length s; host arrays, copied.  sum(b) need not be 1. */
+ * s <= 6 stages, A row-major s*s strictly lower triangular (a_ij = 0 for
+ * j >= i), b and c of length s; host arrays, copied.  sum(b) need not be 1.
+ * Before crkdg_bind any s is accepted and sizes the workspace
+ * (crkdg_workspace_bytes); after it, s may not exceed what the bound
+ * workspace holds (max(4, stages) at bind time): CRKDG_EINVAL. */
 int crkdg_set_tableau(crkdg_state* st, int s, const double* c, const double* A, const double* b);
 
 /* bytes of the DOF buffer and of the workspace for the chosen layout */
@@ -275,7 +290,7 @@ int crkdg_combine(crkdg_state* st, void* out_dev, const void* base_dev, int n,
 int crkdg_profile_begin(crkdg_state* st, int max_launches);
 int crkdg_profile_end(crkdg_state* st, double ms[8], int64_t counts[8]);
 
-/* Host-only: the library's own n-point Gauss--Legendre rule (n = 1..6). */
+/* Host-only: the library's own n-point Gauss--Legendre rule (n = 1..8). */
 int crkdg_gauss_rule(int n, double* x, double* w);
 
 void crkdg_destroy(crkdg_state* st);

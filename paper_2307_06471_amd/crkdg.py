@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "_lib", "libcrkdg.so")
 
 CRKDG_OK, CRKDG_EINVAL, CRKDG_EUNSUPPORTED, CRKDG_ENONPHYSICAL, CRKDG_EHIP, CRKDG_EUNBOUND = \
     0, -1, -2, -3, -4, -5
-EQ_ADVECTION, EQ_EULER = 0, 1
-FLUX_UPWIND, FLUX_LLF = 0, 1
+EQ_ADVECTION, EQ_EULER, EQ_BURGERS = 0, 1, 2
+FLUX_UPWIND, FLUX_LLF, FLUX_GODUNOV = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MIXED, FP32_INNER = 0, 1, 2
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
 IC_DMR = 6  # double Mach reflection
+IC_BURGERS_SIN = 7  # 1D Burgers, u(x, 0) = sin x
+RK_FEHLBERG5 = 5  # rk_stages value of the six-stage fifth-order Runge--Kutta--Fehlberg method
 
 
 class crkdg_mesh(C.Structure):
@@ -162,7 +164,7 @@ class Solver:
         self.mesh = mesh
         self.k = k
         self.dim = mesh.dim
-        self.ncomp = 1 if mesh.equation == EQ_ADVECTION else (4 if mesh.dim == 2 else 3)
+        self.ncomp = 1 if mesh.equation != EQ_EULER else (4 if mesh.dim == 2 else 3)
         self.nmodes = (k + 1) ** 2 if mesh.dim == 2 else k + 1
         self.ncells = mesh.nx * (mesh.ny if mesh.dim == 2 else 1)
         self.h = crkdg_create(mesh, k, flux, rk_stages)

@@ -22,6 +22,7 @@ struct crkdg_state {
   // tableau (Section 2.1, equation (butcher))
   int s;
   double A[MAXS][MAXS], b[MAXS], c[MAXS];
+  int ws;        // stages the workspace layout holds (>= s; fixed once bound)
   bool subdiag;  // a_ij = 0 unless j == i - 1: inner stages need one accumulator
   // bound memory
   bool bound;
@@ -56,14 +57,14 @@ size_t slot_bytes(const crkdg_state* st) {
   return round_up(st->S > st->S_stage ? st->S : st->S_stage);
 }
 char* slot_ptr(const crkdg_state* st, int slot) {
-  // work layout: [state B][stage 1..3][L 0..2][scratch]
+  // work layout: [state B][stage 1..ws-1][L 0..ws-2][scratch]
   return st->work + (size_t)slot * slot_bytes(st);
 }
 char* cur_ptr(const crkdg_state* st) { return st->cur ? slot_ptr(st, 0) : st->dofs; }
 char* nxt_ptr(const crkdg_state* st) { return st->cur ? st->dofs : slot_ptr(st, 0); }
-char* stage_ptr(const crkdg_state* st, int i) { return slot_ptr(st, i); }          // i = 1..3
-char* lbuf_ptr(const crkdg_state* st, int j) { return slot_ptr(st, MAXS + j); }    // j = 0..2
-char* scratch_ptr(const crkdg_state* st) { return slot_ptr(st, 2 * MAXS - 1); }
+char* stage_ptr(const crkdg_state* st, int i) { return slot_ptr(st, i); }         // i = 1..ws-1
+char* lbuf_ptr(const crkdg_state* st, int j) { return slot_ptr(st, st->ws + j); } // j = 0..ws-2
+char* scratch_ptr(const crkdg_state* st) { return slot_ptr(st, 2 * st->ws - 1); }
 // per-block wave-speed maxima written by the limiter (one double per 256 cells)
 int wave_blocks(const crkdg_state* st) { return (int)((st->geo.N + 255) / 256); }
 size_t wave_partial_bytes(const crkdg_state* st) {
@@ -78,6 +79,7 @@ double* wave_partial_ptr(const crkdg_state* st) {
 void set_tableau_internal(crkdg_state* st, int s, const double* c, const double* A,
                           const double* b) {
   st->s = s;
+  if (s > st->ws) st->ws = s;
   memset(st->A, 0, sizeof st->A);
   for (int i = 0; i < s; ++i) {
     st->b[i] = b[i];
@@ -128,7 +130,7 @@ const char* crkdg_strerror(int code) {
 }
 
 int crkdg_gauss_rule(int n, double* x, double* w) {
-  if (n < 1 || n > 6 || !x || !w) return CRKDG_EINVAL;
+  if (n < 1 || n > 8 || !x || !w) return CRKDG_EINVAL;
   for (int a = 0; a < n; ++a) {
     x[a] = crk::gl_x(n, a);
     w[a] = crk::gl_w(n, a);
@@ -168,7 +170,7 @@ static void dmr_params(double gamma, double* P) {
 
 int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_state** out) {
   if (!mesh || !out) return CRKDG_EINVAL;
-  if (k < 0 || k > 3) return CRKDG_EINVAL;
+  if (k < 0 || k > 4) return CRKDG_EINVAL;
   if (mesh->dim != 1 && mesh->dim != 2) return CRKDG_EINVAL;
   if (mesh->nx < 1 || mesh->ny < 1 || (mesh->dim == 1 && mesh->ny != 1)) return CRKDG_EINVAL;
   // device addressing uses 32-bit byte offsets within each component slab of
@@ -178,11 +180,12 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     const long long ncell = (long long)mesh->nx * mesh->ny;
     const long long nbm = mesh->dim == 2 ? (long long)(k + 1) * (k + 1) : (long long)(k + 1);
     const long long span = nbm > 4 ? nbm : 4;
-    if (k >= 0 && k <= 3 && ncell * span * 8 >= (1LL << 32)) return CRKDG_EINVAL;
+    if (ncell * span * 8 >= (1LL << 32)) return CRKDG_EINVAL;
   }
   if (!(mesh->x1 > mesh->x0) || (mesh->dim == 2 && !(mesh->y1 > mesh->y0))) return CRKDG_EINVAL;
-  if (rk_stages < 1 || rk_stages > 4) return CRKDG_EINVAL;
-  if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF) return CRKDG_EINVAL;
+  if (rk_stages < 1 || rk_stages > 5) return CRKDG_EINVAL;
+  if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF && flux != CRKDG_FLUX_GODUNOV)
+    return CRKDG_EINVAL;
   if (mesh->precision != CRKDG_FP64 && mesh->precision != CRKDG_FP32_MIXED &&
       mesh->precision != CRKDG_FP32_INNER)
     return CRKDG_EINVAL;
@@ -190,16 +193,23 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     if (mesh->bc[sd] < CRKDG_BC_PERIODIC || mesh->bc[sd] > CRKDG_BC_DIRICHLET) return CRKDG_EINVAL;
   int eq;
   if (mesh->equation == CRKDG_EQ_ADVECTION) {
+    if (flux == CRKDG_FLUX_GODUNOV) return CRKDG_EUNSUPPORTED;
     eq = mesh->dim == 1 ? EQ_ADV1 : EQ_ADV2;
   } else if (mesh->equation == CRKDG_EQ_EULER) {
     if (mesh->dim != 2) return CRKDG_EUNSUPPORTED;
     if (flux != CRKDG_FLUX_LLF) return CRKDG_EUNSUPPORTED;
     if (!(mesh->gamma > 1.0)) return CRKDG_EINVAL;
+    if (k > 3) return CRKDG_EUNSUPPORTED;  // k = 4 is built for the scalar equations
     eq = EQ_EULER2;
+  } else if (mesh->equation == CRKDG_EQ_BURGERS) {
+    if (mesh->dim != 1 || flux != CRKDG_FLUX_GODUNOV) return CRKDG_EUNSUPPORTED;
+    eq = EQ_BURGERS1;
   } else {
     return CRKDG_EINVAL;
   }
   if (mesh->bc_exact != 0 && mesh->bc_exact != CRKDG_IC_ADV_SIN && mesh->bc_exact != CRKDG_IC_DMR)
+    return CRKDG_EUNSUPPORTED;
+  if (mesh->bc_exact == CRKDG_IC_ADV_SIN && eq != EQ_ADV1 && eq != EQ_ADV2)
     return CRKDG_EUNSUPPORTED;
   if (mesh->bc_exact == CRKDG_IC_DMR &&
       (eq != EQ_EULER2 || mesh->bc[0] != CRKDG_BC_DIRICHLET ||
@@ -214,7 +224,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   st->k = k;
   st->flux = flux;
   st->eq = eq;
-  st->nc = mesh->equation == CRKDG_EQ_ADVECTION ? 1 : 4;
+  st->nc = mesh->equation == CRKDG_EQ_EULER ? 4 : 1;
   st->nb = mesh->dim == 2 ? (k + 1) * (k + 1) : k + 1;
   Geo& g = st->geo;
   g.nx = mesh->nx;
@@ -239,7 +249,9 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   memset(st->bc.params, 0, sizeof st->bc.params);
   st->bc.t = 0.0;
   if (mesh->bc_exact == CRKDG_IC_DMR) dmr_params(mesh->gamma, st->bc.params);
-  // tableaus named by the paper: forward Euler, (eq:2), (eq:3), classical RK4
+  // tableaus named by the paper: forward Euler, (eq:2), (eq:3), classical RK4,
+  // and Fehlberg's six-stage method advanced with its fifth-order weights
+  // (E. Fehlberg, NASA TR R-315, 1969)
   static const double FE_A[1] = {0}, FE_b[1] = {1}, FE_c[1] = {0};
   static const double E2_A[4] = {0, 0, 0.5, 0}, E2_b[2] = {0, 1}, E2_c[2] = {0, 0.5};
   static const double E3_A[9] = {0, 0, 0, 1.0 / 3.0, 0, 0, 0, 2.0 / 3.0, 0},
@@ -247,11 +259,23 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   static const double R4_A[16] = {0, 0, 0, 0, 0.5, 0, 0, 0, 0, 0.5, 0, 0, 0, 0, 1, 0},
                       R4_b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0},
                       R4_c[4] = {0, 0.5, 0.5, 1};
+  static const double F5_A[36] = {
+      0, 0, 0, 0, 0, 0,
+      1.0 / 4, 0, 0, 0, 0, 0,
+      3.0 / 32, 9.0 / 32, 0, 0, 0, 0,
+      1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0, 0,
+      439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0, 0,
+      -8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40, 0};
+  static const double F5_b[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50,
+                                 2.0 / 55},
+                      F5_c[6] = {0, 1.0 / 4, 3.0 / 8, 12.0 / 13, 1, 1.0 / 2};
+  st->ws = 4;
   switch (rk_stages) {
     case 1: set_tableau_internal(st, 1, FE_c, FE_A, FE_b); break;
     case 2: set_tableau_internal(st, 2, E2_c, E2_A, E2_b); break;
     case 3: set_tableau_internal(st, 3, E3_c, E3_A, E3_b); break;
-    default: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
+    case 4: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
+    default: set_tableau_internal(st, 6, F5_c, F5_A, F5_b); break;
   }
   st->prec = mesh->precision == CRKDG_FP32_MIXED ? PBULK
              : mesh->precision == CRKDG_FP32_INNER ? PINNER : P64;
@@ -274,6 +298,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
 
 int crkdg_set_tableau(crkdg_state* st, int s, const double* c, const double* A, const double* b) {
   if (!st || !c || !A || !b || s < 1 || s > MAXS) return CRKDG_EINVAL;
+  if (st->bound && s > st->ws) return CRKDG_EINVAL;  // the bound workspace holds ws stages
   for (int i = 0; i < s; ++i) {
     if (!isfinite(b[i]) || !isfinite(c[i])) return CRKDG_EINVAL;
     for (int j = 0; j < s; ++j) {
@@ -290,7 +315,7 @@ size_t crkdg_state_bytes(const crkdg_state* st) { return st ? st->S : 0; }
 
 size_t crkdg_workspace_bytes(const crkdg_state* st) {
   if (!st) return 0;
-  return (size_t)(2 * MAXS - 1) * slot_bytes(st) + round_up(SCRATCH) + wave_partial_bytes(st);
+  return (size_t)(2 * st->ws - 1) * slot_bytes(st) + round_up(SCRATCH) + wave_partial_bytes(st);
 }
 
 int crkdg_bind(crkdg_state* st, void* dofs_dev, void* work_dev, void* stream) {
@@ -418,7 +443,8 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
                   const double* aux_dev) {
   if (!st) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_DMR) return CRKDG_EINVAL;
+  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_BURGERS_SIN) return CRKDG_EINVAL;
+  if (ic == CRKDG_IC_BURGERS_SIN && st->eq != EQ_BURGERS1) return CRKDG_EINVAL;
   if (ic == CRKDG_IC_SHOCK && !aux_dev) return CRKDG_EINVAL;
   if ((ic == CRKDG_IC_EULER_WAVE || ic == CRKDG_IC_VORTEX || ic == CRKDG_IC_QUADRANT ||
        ic == CRKDG_IC_SHOCK || ic == CRKDG_IC_DMR) && st->eq != EQ_EULER2)
@@ -761,7 +787,9 @@ int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, doub
                 double out[3]) {
   if (!st || !out || comp < 0 || comp >= st->nc) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if (ic < CRKDG_IC_CONST || ic > CRKDG_IC_QUADRANT) return CRKDG_EINVAL;
+  if (ic < CRKDG_IC_CONST || (ic > CRKDG_IC_QUADRANT && ic != CRKDG_IC_BURGERS_SIN))
+    return CRKDG_EINVAL;
+  if (ic == CRKDG_IC_BURGERS_SIN && st->eq != EQ_BURGERS1) return CRKDG_EINVAL;
   double P[NPARAM];
   int rc = copy_params(st, params, nparams, P);
   if (rc) return rc;

@@ -8,7 +8,7 @@
 
 namespace crk {
 
-constexpr int MAXS = 4;        // stages of the largest tableau
+constexpr int MAXS = 6;        // stages of the largest tableau (Fehlberg's)
 constexpr int NPARAM = 24;     // initial-condition parameters passed to kernels
 
 // device layouts of a state
@@ -45,7 +45,7 @@ struct PhysDev {
 };
 
 // one equation/dimension/degree selection
-enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2 };
+enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2, EQ_BURGERS1 = 3 };
 
 // compute precision of a state's step
 //  P64:    FP64 throughout (the plain method)

@@ -236,6 +236,10 @@ struct MakeEq<Adv<R, D>> {
     return e;
   }
 };
+template <class R>
+struct MakeEq<Burgers1<R>> {
+  __device__ static Burgers1<R> make(const PhysDev&) { return Burgers1<R>{}; }
+};
 template <class EQ>
 __device__ __forceinline__ EQ make_eq(const PhysDev& ph) {
   return MakeEq<EQ>::make(ph);
@@ -287,6 +291,19 @@ __device__ void exact_state(int ic, const double* P, const double* aux, const Ge
       else
         q[0] = sin(M_PI * (x - ph.ax * t)) * sin(M_PI * (y - ph.ay * t));
       return;
+    case CRKDG_IC_BURGERS_SIN: {
+      // u = u0(x - u t), u0 = sin (characteristics, before the shock at t = 1):
+      // Newton's method on h(v) = v - sin(x - v t), h' = 1 + t cos(x - v t) >= 1 - t
+      double v = sin(x);
+      for (int it = 0; it < 50; ++it) {
+        const double ph_ = x - v * t;
+        const double dv = (v - sin(ph_)) / (1.0 + t * cos(ph_));
+        v -= dv;
+        if (fabs(dv) <= 1e-17) break;
+      }
+      q[0] = v;
+      return;
+    }
     case CRKDG_IC_EULER_WAVE: {
       const double u = P[0], v = P[1], p = P[2];
       const double rho = dim == 1 ? 1.0 + 0.2 * sin(M_PI * (x - u * t))
@@ -1091,6 +1108,8 @@ __device__ __forceinline__ double cell_speed(const PhysDev& ph, const Geo& g, co
     const double p = (ph.gamma - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
     const double c = sqrt(ph.gamma * p * ir);
     return (fabs(u) + c) * g.inv_dx + (fabs(v) + c) * g.inv_dy;
+  } else if constexpr (EQ::BURGERS) {
+    return fabs(q[0]) * g.inv_dx;
   } else {
     return fabs(ph.ax) * g.inv_dx + (EQ::DIM == 2 ? fabs(ph.ay) * g.inv_dy : 0.0);
   }
@@ -1837,21 +1856,29 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+// k = 0..4 for the scalar equations, 0..3 for Euler
 template <template <class, int> class F, class R, class... A>
 hipError_t dispatch_r(int eq, int k, A&&... args) {
-  switch (eq * 4 + k) {
-    case EQ_ADV1 * 4 + 0: return F<Adv<R, 1>, 0>::run(args...);
-    case EQ_ADV1 * 4 + 1: return F<Adv<R, 1>, 1>::run(args...);
-    case EQ_ADV1 * 4 + 2: return F<Adv<R, 1>, 2>::run(args...);
-    case EQ_ADV1 * 4 + 3: return F<Adv<R, 1>, 3>::run(args...);
-    case EQ_ADV2 * 4 + 0: return F<Adv<R, 2>, 0>::run(args...);
-    case EQ_ADV2 * 4 + 1: return F<Adv<R, 2>, 1>::run(args...);
-    case EQ_ADV2 * 4 + 2: return F<Adv<R, 2>, 2>::run(args...);
-    case EQ_ADV2 * 4 + 3: return F<Adv<R, 2>, 3>::run(args...);
-    case EQ_EULER2 * 4 + 0: return F<Euler2<R>, 0>::run(args...);
-    case EQ_EULER2 * 4 + 1: return F<Euler2<R>, 1>::run(args...);
-    case EQ_EULER2 * 4 + 2: return F<Euler2<R>, 2>::run(args...);
-    case EQ_EULER2 * 4 + 3: return F<Euler2<R>, 3>::run(args...);
+  switch (eq * 5 + k) {
+    case EQ_ADV1 * 5 + 0: return F<Adv<R, 1>, 0>::run(args...);
+    case EQ_ADV1 * 5 + 1: return F<Adv<R, 1>, 1>::run(args...);
+    case EQ_ADV1 * 5 + 2: return F<Adv<R, 1>, 2>::run(args...);
+    case EQ_ADV1 * 5 + 3: return F<Adv<R, 1>, 3>::run(args...);
+    case EQ_ADV1 * 5 + 4: return F<Adv<R, 1>, 4>::run(args...);
+    case EQ_ADV2 * 5 + 0: return F<Adv<R, 2>, 0>::run(args...);
+    case EQ_ADV2 * 5 + 1: return F<Adv<R, 2>, 1>::run(args...);
+    case EQ_ADV2 * 5 + 2: return F<Adv<R, 2>, 2>::run(args...);
+    case EQ_ADV2 * 5 + 3: return F<Adv<R, 2>, 3>::run(args...);
+    case EQ_ADV2 * 5 + 4: return F<Adv<R, 2>, 4>::run(args...);
+    case EQ_EULER2 * 5 + 0: return F<Euler2<R>, 0>::run(args...);
+    case EQ_EULER2 * 5 + 1: return F<Euler2<R>, 1>::run(args...);
+    case EQ_EULER2 * 5 + 2: return F<Euler2<R>, 2>::run(args...);
+    case EQ_EULER2 * 5 + 3: return F<Euler2<R>, 3>::run(args...);
+    case EQ_BURGERS1 * 5 + 0: return F<Burgers1<R>, 0>::run(args...);
+    case EQ_BURGERS1 * 5 + 1: return F<Burgers1<R>, 1>::run(args...);
+    case EQ_BURGERS1 * 5 + 2: return F<Burgers1<R>, 2>::run(args...);
+    case EQ_BURGERS1 * 5 + 3: return F<Burgers1<R>, 3>::run(args...);
+    case EQ_BURGERS1 * 5 + 4: return F<Burgers1<R>, 4>::run(args...);
     default: return hipErrorInvalidValue;
   }
 }

@@ -28,47 +28,9 @@ namespace crk {
 #endif
 
 // ---------------------------------------------------------------------------
-// Gauss--Legendre rules on [-1, 1] (closed forms for n <= 5, tabulated for n = 6)
+// Gauss--Legendre rules on [-1, 1] (closed forms for n <= 5, tabulated for
+// n = 6, computed at compile time for n >= 7)
 // ---------------------------------------------------------------------------
-constexpr double gl_x(int n, int a) {
-  switch (n) {
-    case 1: return 0.0;
-    case 2: { constexpr double r = 0.57735026918962576450914878050196; return a == 0 ? -r : r; }
-    case 3: { constexpr double r = 0.77459666924148337703585307995648;
-              return a == 0 ? -r : (a == 1 ? 0.0 : r); }
-    case 4: { constexpr double r1 = 0.33998104358485626480266575910324,
-                               r2 = 0.86113631159405257522394648889281;
-              return a == 0 ? -r2 : a == 1 ? -r1 : a == 2 ? r1 : r2; }
-    case 5: { constexpr double r1 = 0.53846931010568309103631442070021,
-                               r2 = 0.90617984593866399279762687829939;
-              return a == 0 ? -r2 : a == 1 ? -r1 : a == 2 ? 0.0 : a == 3 ? r1 : r2; }
-    case 6: { constexpr double r1 = 0.23861918608319690863050172168071,
-                               r2 = 0.66120938646626451366139959501991,
-                               r3 = 0.93246951420315202781230155449399;
-              return a == 0 ? -r3 : a == 1 ? -r2 : a == 2 ? -r1 : a == 3 ? r1 : a == 4 ? r2 : r3; }
-    default: return 0.0;
-  }
-}
-constexpr double gl_w(int n, int a) {
-  switch (n) {
-    case 1: return 2.0;
-    case 2: return 1.0;
-    case 3: return a == 1 ? 8.0 / 9.0 : 5.0 / 9.0;
-    case 4: { constexpr double w1 = 0.65214515486254614262693605077800,
-                               w2 = 0.34785484513745385737306394922200;
-              return (a == 1 || a == 2) ? w1 : w2; }
-    case 5: { constexpr double w0 = 0.56888888888888888888888888888889,
-                               w1 = 0.47862867049936646804129151483564,
-                               w2 = 0.23692688505618908751426404071992;
-              return a == 2 ? w0 : (a == 1 || a == 3) ? w1 : w2; }
-    case 6: { constexpr double w1 = 0.46791393457269104738987034398955,
-                               w2 = 0.36076157304813860756983351383772,
-                               w3 = 0.17132449237917034504029614217273;
-              return (a == 2 || a == 3) ? w1 : (a == 1 || a == 4) ? w2 : w3; }
-    default: return 0.0;
-  }
-}
-
 // Legendre polynomials by Bonnet's recursion and derivatives by
 // P'_{m+1} = (m+1) P_m + x P'_m
 constexpr double leg(int m, double x) {
@@ -87,6 +49,81 @@ constexpr double dleg(int m, double x) {
   return d;
 }
 
+// a-th root (ascending) of P_n for n >= 7: the roots are simple and at least
+// 2/n^2 apart, so a grid of 8 n^2 intervals brackets each one; bisection then
+// halves the bracket until it holds no double between its ends
+constexpr double gl_root(int n, int a) {
+  const int cells = 8 * n * n;
+  int seen = 0;
+  double lo = -1.0, flo = leg(n, -1.0);
+  for (int c = 1; c <= cells; ++c) {
+    const double hi = -1.0 + 2.0 * c / cells, fhi = leg(n, hi);
+    if ((flo < 0.0) != (fhi < 0.0)) {
+      if (seen == a) {
+        double l = lo, h = hi, fl = flo;
+        for (int it = 0; it < 80; ++it) {
+          const double m = 0.5 * (l + h);
+          if (m <= l || m >= h) break;
+          const double fm = leg(n, m);
+          if ((fm < 0.0) == (fl < 0.0)) {
+            l = m;
+            fl = fm;
+          } else {
+            h = m;
+          }
+        }
+        return 0.5 * (l + h);
+      }
+      ++seen;
+    }
+    lo = hi;
+    flo = fhi;
+  }
+  return 0.0;
+}
+constexpr double gl_x(int n, int a) {
+  switch (n) {
+    case 1: return 0.0;
+    case 2: { constexpr double r = 0.57735026918962576450914878050196; return a == 0 ? -r : r; }
+    case 3: { constexpr double r = 0.77459666924148337703585307995648;
+              return a == 0 ? -r : (a == 1 ? 0.0 : r); }
+    case 4: { constexpr double r1 = 0.33998104358485626480266575910324,
+                               r2 = 0.86113631159405257522394648889281;
+              return a == 0 ? -r2 : a == 1 ? -r1 : a == 2 ? r1 : r2; }
+    case 5: { constexpr double r1 = 0.53846931010568309103631442070021,
+                               r2 = 0.90617984593866399279762687829939;
+              return a == 0 ? -r2 : a == 1 ? -r1 : a == 2 ? 0.0 : a == 3 ? r1 : r2; }
+    case 6: { constexpr double r1 = 0.23861918608319690863050172168071,
+                               r2 = 0.66120938646626451366139959501991,
+                               r3 = 0.93246951420315202781230155449399;
+              return a == 0 ? -r3 : a == 1 ? -r2 : a == 2 ? -r1 : a == 3 ? r1 : a == 4 ? r2 : r3; }
+    default: return gl_root(n, a);
+  }
+}
+constexpr double gl_w(int n, int a) {
+  switch (n) {
+    case 1: return 2.0;
+    case 2: return 1.0;
+    case 3: return a == 1 ? 8.0 / 9.0 : 5.0 / 9.0;
+    case 4: { constexpr double w1 = 0.65214515486254614262693605077800,
+                               w2 = 0.34785484513745385737306394922200;
+              return (a == 1 || a == 2) ? w1 : w2; }
+    case 5: { constexpr double w0 = 0.56888888888888888888888888888889,
+                               w1 = 0.47862867049936646804129151483564,
+                               w2 = 0.23692688505618908751426404071992;
+              return a == 2 ? w0 : (a == 1 || a == 3) ? w1 : w2; }
+    case 6: { constexpr double w1 = 0.46791393457269104738987034398955,
+                               w2 = 0.36076157304813860756983351383772,
+                               w3 = 0.17132449237917034504029614217273;
+              return (a == 2 || a == 3) ? w1 : (a == 1 || a == 4) ? w2 : w3; }
+    default: {
+      // w_a = 2 / ((1 - x_a^2) P_n'(x_a)^2)
+      const double x = gl_root(n, a), d = dleg(n, x);
+      return 2.0 / ((1.0 - x * x) * d * d);
+    }
+  }
+}
+
 // tables for one degree: P[m][a] = P_m(x_a), D[m][a] = P'_m(x_a), W[a]
 template <int Q>
 struct GTab {
@@ -102,8 +139,8 @@ constexpr GTab<Q> make_tab() {
     t.X[a] = gl_x(Q, a);
     t.W[a] = gl_w(Q, a);
     for (int m = 0; m < Q; ++m) {
-      t.P[m][a] = leg(m, gl_x(Q, a));
-      t.D[m][a] = dleg(m, gl_x(Q, a));
+      t.P[m][a] = leg(m, t.X[a]);
+      t.D[m][a] = dleg(m, t.X[a]);
     }
   }
   return t;
@@ -130,7 +167,7 @@ template <class R>
 struct Euler2 {
   using Real = R;
   static constexpr int NC = 4, DIM = 2;
-  static constexpr bool EULER = true;
+  static constexpr bool EULER = true, BURGERS = false;
   R gm1, gam;
 
   __device__ __forceinline__ void flux2(const R (&q)[4], R (&f)[4], R (&g)[4]) const {
@@ -200,7 +237,7 @@ template <class R, int DIM_>
 struct Adv {
   using Real = R;
   static constexpr int NC = 1, DIM = DIM_;
-  static constexpr bool EULER = false;
+  static constexpr bool EULER = false, BURGERS = false;
   R ax, ay;
   int upwind;
 
@@ -227,6 +264,43 @@ struct Adv {
       F[0] = a >= R(0) ? a * qL[0] : a * qR[0];
     else
       F[0] = R(0.5) * (a * qL[0] + a * qR[0] - fabs(a) * (qR[0] - qL[0]));
+  }
+};
+
+// Burgers' equation u_t + (u^2/2)_x = 0 in 1D (Section 4.1.1, example
+// 'ex:1dburgers') with the Godunov flux: the flux of the exact Riemann
+// solution at the face.  For the convex f(u) = u^2/2 and left/right traces
+// a, b: a <= b (rarefaction, or a contact at a = b) gives f at the point of
+// [a, b] closest to the sonic point 0; a > b (shock) gives the larger of
+// f(a) and f(b), the upwind side of the shock.
+template <class R>
+struct Burgers1 {
+  using Real = R;
+  static constexpr int NC = 1, DIM = 1;
+  static constexpr bool EULER = false, BURGERS = true;
+
+  __device__ __forceinline__ static R godunov(R a, R b) {
+    if (a <= b) {
+      const R u = fmin(fmax(a, R(0)), b);
+      return R(0.5) * u * u;
+    }
+    return R(0.5) * fmax(a * a, b * b);
+  }
+  __device__ __forceinline__ void flux2(const R (&q)[1], R (&f)[1], R (&g)[1]) const {
+    f[0] = R(0.5) * q[0] * q[0];
+    g[0] = R(0);
+  }
+  template <int D>
+  __device__ __forceinline__ void nflux_only(const R (&q)[1], R (&f)[1]) const {
+    f[0] = R(0.5) * q[0] * q[0];
+  }
+  template <int D>
+  __device__ __forceinline__ void num_flux(const R (&qL)[1], const R (&qR)[1], R (&F)[1]) const {
+    F[0] = godunov(qL[0], qR[0]);
+  }
+  __device__ __forceinline__ void num_flux_d(const R (&qL)[1], const R (&qR)[1], bool,
+                                             R (&F)[1]) const {
+    F[0] = godunov(qL[0], qR[0]);
   }
 };
 

@@ -30,14 +30,49 @@ def test_library_exports_every_declared_symbol():
         assert n in K.EXPORTS, n
 
 
-@pytest.mark.parametrize("n", range(1, 7))
+def _gauss_50_digits(n):
+    """nodes and weights by Newton's method on P_n in 50-digit decimal
+    arithmetic, started from numpy's rule"""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+
+    def leg(m, z):
+        p0, p1 = Decimal(1), z
+        if m == 0:
+            return p0
+        for j in range(1, m):
+            p0, p1 = p1, ((2 * j + 1) * z * p1 - j * p0) / (j + 1)
+        return p1
+
+    def dleg(z):  # (1 - z^2) P_n' = n (P_{n-1} - z P_n)
+        return n * (leg(n - 1, z) - z * leg(n, z)) / (1 - z * z)
+
+    xs, ws = [], []
+    for x0 in np.polynomial.legendre.leggauss(n)[0]:
+        z = Decimal(repr(float(x0)))
+        for _ in range(8):
+            if n > 1:
+                z -= leg(n, z) / dleg(z)
+        d = dleg(z) if n > 1 else Decimal(1)
+        xs.append(z)
+        ws.append(2 / ((1 - z * z) * d * d))
+    return xs, ws
+
+
+@pytest.mark.parametrize("n", range(1, 9))
 def test_library_gauss_rules(n):
+    """n <= 6 are closed forms and tables, n = 7, 8 roots of P_n found at
+    compile time: nodes within 2e-16, weights within 5e-15 relative of a
+    50-digit reference, and exact on polynomials of degree <= 2n - 1"""
     x, w = K.crkdg_gauss_rule(n)
-    xr, wr = np.polynomial.legendre.leggauss(n)
-    assert np.abs(x - xr).max() < 1e-15 and np.abs(w - wr).max() < 1e-15
-    for p in range(2 * n):  # exact for polynomials of degree <= 2n - 1
+    xs, ws = _gauss_50_digits(n)
+    from decimal import Decimal
+    for a in range(n):
+        assert abs(Decimal(repr(float(x[a]))) - xs[a]) < Decimal("2e-16"), a
+        assert abs(Decimal(repr(float(w[a]))) - ws[a]) < Decimal("5e-15") * ws[a], a
+    for p in range(2 * n):
         exact = 0.0 if p % 2 else 2.0 / (p + 1)
-        assert abs((w * x**p).sum() - exact) < 3e-16
+        assert abs((w * x**p).sum() - exact) < 1e-15
 
 
 def _create(**kw):
@@ -52,12 +87,21 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(k=4), K.CRKDG_EINVAL),
+    (dict(k=5), K.CRKDG_EINVAL),
+    (dict(k=4), K.CRKDG_EUNSUPPORTED),  # k = 4 is built for the scalar equations
     (dict(k=-1), K.CRKDG_EINVAL),
     (dict(nx=0), K.CRKDG_EINVAL),
-    (dict(stages=5), K.CRKDG_EINVAL),
+    (dict(stages=6), K.CRKDG_EINVAL),
     (dict(stages=0), K.CRKDG_EINVAL),
     (dict(flux=K.FLUX_UPWIND), K.CRKDG_EUNSUPPORTED),
+    (dict(flux=K.FLUX_GODUNOV), K.CRKDG_EUNSUPPORTED),
+    (dict(flux=3), K.CRKDG_EINVAL),
+    (dict(equation=K.EQ_ADVECTION, flux=K.FLUX_GODUNOV), K.CRKDG_EUNSUPPORTED),
+    (dict(equation=K.EQ_BURGERS, flux=K.FLUX_GODUNOV), K.CRKDG_EUNSUPPORTED),  # 2D
+    (dict(equation=K.EQ_BURGERS, dim=1, ny=1, flux=K.FLUX_LLF), K.CRKDG_EUNSUPPORTED),
+    (dict(equation=K.EQ_BURGERS, dim=1, ny=1, flux=K.FLUX_GODUNOV, bc=(2, 1, 0, 0),
+          bc_exact=K.IC_ADV_SIN), K.CRKDG_EUNSUPPORTED),
+    (dict(equation=3), K.CRKDG_EINVAL),
     (dict(dim=1, ny=1), K.CRKDG_EUNSUPPORTED),
     (dict(gamma=1.0), K.CRKDG_EINVAL),
     (dict(x1=0.0), K.CRKDG_EINVAL),
@@ -109,8 +153,44 @@ def test_set_tableau_validation():
     A_nan = A_ok.copy()
     A_nan[2, 0] = np.nan
     assert L.crkdg_set_tableau(h, 3, dp(c), dp(A_nan), dp(b)) == K.CRKDG_EINVAL
-    assert L.crkdg_set_tableau(h, 5, dp(c), dp(A_ok), dp(b)) == K.CRKDG_EINVAL
+    A7, b7, c7 = np.zeros((7, 7)), np.full(7, 1 / 7), np.zeros(7)
+    assert L.crkdg_set_tableau(h, 7, dp(c7), dp(A7), dp(b7)) == K.CRKDG_EINVAL  # > 6 stages
     L.crkdg_destroy(h)
+
+
+def test_six_stage_tableaus_size_the_workspace():
+    """the workspace holds max(4, s) stages: a six-stage tableau set before
+    binding enlarges it (4 more state slots), one set after binding a
+    four-stage workspace is refused; rk_stages = 5 (Fehlberg) sizes it at
+    creation"""
+    L = K.lib()
+    dp = lambda a: np.ascontiguousarray(a, float).ctypes.data_as(C.POINTER(C.c_double))
+    A6, b6, c6 = np.zeros((6, 6)), np.full(6, 1 / 6), np.zeros(6)
+    for i in range(1, 6):
+        A6[i, i - 1] = 0.5
+    rc, h = _create()
+    w4 = L.crkdg_workspace_bytes(h)
+    S = L.crkdg_state_bytes(h)
+    assert L.crkdg_set_tableau(h, 6, dp(c6), dp(A6), dp(b6)) == 0
+    assert L.crkdg_workspace_bytes(h) == w4 + 4 * S
+    L.crkdg_destroy(h)
+    rc, h = _create(stages=5)
+    assert rc == 0 and L.crkdg_workspace_bytes(h) == w4 + 4 * S
+    L.crkdg_destroy(h)
+    rc, h = _create()
+    assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+    assert L.crkdg_set_tableau(h, 6, dp(c6), dp(A6), dp(b6)) == K.CRKDG_EINVAL
+    assert L.crkdg_set_tableau(h, 4, dp(c6[:4]), dp(A6[:4, :4]), dp(b6[:4])) == 0
+    L.crkdg_destroy(h)
+
+
+def test_burgers_and_degree_four_are_accepted():
+    for kw in (dict(equation=K.EQ_BURGERS, dim=1, ny=1, flux=K.FLUX_GODUNOV, k=4, stages=5),
+               dict(equation=K.EQ_ADVECTION, dim=2, flux=K.FLUX_UPWIND, k=4, stages=5),
+               dict(equation=K.EQ_ADVECTION, dim=1, ny=1, flux=K.FLUX_UPWIND, k=4, stages=4)):
+        rc, h = _create(**kw)
+        assert rc == 0, kw
+        K.lib().crkdg_destroy(h)
 
 
 def test_strerror():
@@ -154,3 +234,15 @@ def test_double_mach_reflection_mesh_checks():
     for bad in (dict(bc=(2, 2, 2, 2)), dict(bc=(0, 1, 2, 2)), dict(equation=K.EQ_ADVECTION)):
         rc, _ = _create(**{**dmr, **bad})
         assert rc == K.CRKDG_EUNSUPPORTED, bad
+
+
+def test_burgers_initial_data_needs_burgers():
+    """checked before any device work (the bound pointers are never used)"""
+    L = K.lib()
+    rc, h = _create(equation=K.EQ_ADVECTION, dim=1, ny=1, flux=K.FLUX_UPWIND)
+    assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+    assert L.crkdg_project(h, K.IC_BURGERS_SIN, None, 0, None) == K.CRKDG_EINVAL
+    out = (C.c_double * 3)()
+    assert L.crkdg_error(h, K.IC_BURGERS_SIN, None, 0, 0.0, 0, out) == K.CRKDG_EINVAL
+    assert L.crkdg_project(h, 8, None, 0, None) == K.CRKDG_EINVAL
+    L.crkdg_destroy(h)
