@@ -251,6 +251,64 @@ def dmr_study(K):
     return out
 
 
+def fehlberg_study(K, steps=10, warmup=2):
+    """degree 4 with the six-stage fifth-order Runge--Kutta--Fehlberg method
+    (Section 4 pairs them), FP64: 2D advection Q4 on 4096 x 1024 cells
+    (upwind flux, periodic, velocity (1, 0.5)) and 1D Burgers P4 on 2^24
+    cells (Godunov flux, periodic, u0 = sin x), fixed dt.  The full tableau
+    takes the materialised inner stages: per step five loc passes (read a
+    stage, write loc of it: 2 states each), five combinations (stage i reads
+    u^n and i - 1 loc outputs, writes u^(i): 25 states in all) and one final
+    pass (u^n and the four other stages with b_i != 0 read, u^{n+1} written:
+    6 states)."""
+    import torch
+    per_launch = {"loc": 2.0, "combine": 25.0 / 5.0, "final": 6.0}  # states per launch
+    cases = [
+        ("2D advection Q4 4096x1024", K.make_mesh(2, 4096, 1024, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
+                                                   equation=K.EQ_ADVECTION, adv=(1.0, 0.5)),
+         K.FLUX_UPWIND, K.IC_ADV_SIN, 0.02 / (1.0 * 1024 + 0.5 * 1024)),  # CFL 0.02
+        ("1D Burgers P4 2^24 cells", K.make_mesh(1, 1 << 24, 1, x0=-np.pi, x1=np.pi,
+                                                  equation=K.EQ_BURGERS),
+         K.FLUX_GODUNOV, K.IC_BURGERS_SIN, 0.05 * 2 * np.pi / (1 << 24)),
+    ]
+    out = {}
+    for name, lm, flux, ic, dt in cases:
+        s = K.Solver(lm, 4, flux, K.RK_FEHLBERG5)
+        s.crkdg_project(ic)
+        for _ in range(warmup):
+            s.crkdg_step(dt)
+        torch.cuda.synchronize()
+        s.crkdg_profile_begin(16 * steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s.stream):
+            e0.record(s.stream)
+            for _ in range(steps):
+                s.crkdg_step(dt)
+            e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = s.crkdg_profile_end()
+        dofs = s.ncells * s.nmodes * s.ncomp
+        kern = {}
+        for cls, (tms, cnt) in prof.items():
+            if cnt == 0:
+                continue
+            by = per_launch.get(cls, 0.0) * s.state_bytes
+            kern[cls] = {"ms_per_launch": tms / cnt, "launches": cnt, "share": tms / ms,
+                         "achieved_GBs": by / (tms / cnt * 1e-3) / 1e9 if by else None}
+        out[name] = {"value": dofs * steps / (ms / 1e3), "unit": "DOF-updates/s",
+                     "ms_per_step": ms / steps, "dofs": dofs, "state_bytes": s.state_bytes,
+                     "kernels": kern}
+        log(f"fehlberg k=4 {name}: {ms / steps:.3f} ms/step, "
+            f"{out[name]['value']:.3e} DOF-updates/s, "
+            + ", ".join(f"{c} {v['achieved_GBs']:.0f} GB/s" for c, v in kern.items()
+                        if v["achieved_GBs"]))
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def save_indicator(path, P, lo, hi, info):
     """a trained indicator as .npz: parameters, band, training report (JSON)"""
     np.savez(path, P=np.asarray(P, dtype=np.float32), lo=lo, hi=hi,
@@ -280,6 +338,10 @@ def main():
                     help="end with a plain 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--no-rkdg", action="store_true",
                     help="profiling runs only: skip the original-RKDG form")
+    ap.add_argument("--no-fehlberg", action="store_true",
+                    help="skip the degree-4 / fifth-order Runge-Kutta-Fehlberg runs")
+    ap.add_argument("--fehlberg-only", action="store_true",
+                    help="profiling runs: only the degree-4 Fehlberg runs (prints their JSON)")
     ap.add_argument("--dmr", action="store_true",
                     help="also run the double Mach reflection at 1920x480 (Q1, Q2) to t = 0.2")
     ap.add_argument("--dmr-only", action="store_true",
@@ -302,6 +364,9 @@ def main():
 
     if args.dmr_only:
         print(json.dumps({"double_mach_reflection": dmr_study(K)}), flush=True)
+        return
+    if args.fehlberg_only:
+        print(json.dumps({"fehlberg_k4": fehlberg_study(K)}), flush=True)
         return
 
     mlp = None
@@ -372,6 +437,8 @@ def main():
         out["equal_error"] = equal_error(K, W, args.equal_error_scale, mlp)
         log(f"equal error: {out['equal_error']['verdict']} "
             f"{json.dumps(out['equal_error']['mean_error_ratio_vs_fp64_tvb'])}")
+    if not args.no_fehlberg:
+        out["fehlberg_k4"] = fehlberg_study(K)
     if args.dmr:
         out["double_mach_reflection"] = dmr_study(K)
     if not args.no_cpu_baseline:
