@@ -256,13 +256,13 @@ def fehlberg_study(K, steps=10, warmup=2):
     (Section 4 pairs them), FP64: 2D advection Q4 on 4096 x 1024 cells
     (upwind flux, periodic, velocity (1, 0.5)) and 1D Burgers P4 on 2^24
     cells (Godunov flux, periodic, u0 = sin x), fixed dt.  The full tableau
-    takes the materialised inner stages: per step five loc passes (read a
-    stage, write loc of it: 2 states each), five combinations (stage i reads
-    u^n and i - 1 loc outputs, writes u^(i): 25 states in all) and one final
-    pass (u^n and the four other stages with b_i != 0 read, u^{n+1} written:
-    6 states)."""
+    takes one pass per inner stage i = 1..5: it reads u^(i-1), u^n (once for
+    i = 1) and the i - 1 earlier loc outputs, and writes loc(u^(i-1)) (not
+    for i = 5: no later stage uses it) and u^(i): 3 + 5 + 6 + 7 + 7 = 28
+    states; the final pass reads u^n and the four other stages with
+    b_i != 0 and writes u^{n+1}: 6 states."""
     import torch
-    per_launch = {"loc": 2.0, "combine": 25.0 / 5.0, "final": 6.0}  # states per launch
+    per_launch = {"inner": 28.0 / 5.0, "final": 6.0}  # states per launch
     cases = [
         ("2D advection Q4 4096x1024", K.make_mesh(2, 4096, 1024, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
                                                    equation=K.EQ_ADVECTION, adv=(1.0, 0.5)),

@@ -505,27 +505,29 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev,
     e = launch_inner(st->eq, st->k, st->prec, st->ph, st->geo, ia, st->stream);
   } else if (s > 1) {
     if (st->prec != P64) return CRKDG_EUNSUPPORTED;  // materialised path: FP64 only
-    // general tableau: materialise L_j = loc(u^(j)) and combine
-    const long long n = (long long)(st->S / sizeof(double));
+    // general tableau: one pass per inner stage computes L_{i-1} =
+    // loc(u^(i-1)), keeps it in the workspace if a later stage uses it, and
+    // forms u^(i) = u^n - dt sum_j a_ij L_j
     for (int i = 1; i < s && e == hipSuccess; ++i) {
-      double* Lj = (double*)lbuf_ptr(st, i - 1);
-      {
-        ProfScope ps(st, KC_LOC);
-        e = launch_loc(st->eq, st->k, st->ph, st->geo, (const double*)stages[i - 1], Lj, st->stream);
-      }
-      if (e != hipSuccess) break;
-      double coef[MAXS];
-      const double* X[MAXS];
-      int nx = 0;
-      for (int j = 0; j < i; ++j) {
+      LocCombineArgs la{};
+      la.in = (const double*)stages[i - 1];
+      la.un = (const double*)un;
+      bool later = false;
+      for (int m = i + 1; m < s; ++m) later = later || st->A[m][i - 1] != 0.0;
+      la.L_out = later ? (double*)lbuf_ptr(st, i - 1) : nullptr;
+      for (int j = 0; j < i - 1; ++j) {
         if (st->A[i][j] == 0.0) continue;
-        coef[nx] = dt_dev ? -st->A[i][j] : -dt * st->A[i][j];
-        X[nx] = (const double*)lbuf_ptr(st, j);
-        ++nx;
+        la.coef[la.nx] = dt_dev ? -st->A[i][j] : -dt * st->A[i][j];
+        la.X[la.nx] = (const double*)lbuf_ptr(st, j);
+        ++la.nx;
       }
+      la.use_last = st->A[i][i - 1] != 0.0;
+      la.coef_last = dt_dev ? -st->A[i][i - 1] : -dt * st->A[i][i - 1];
+      la.dt_ptr = dt_dev;
       double* ui = (double*)stage_ptr(st, i);
-      ProfScope ps(st, KC_COMBINE);
-      e = launch_combine(n, ui, (const double*)un, nx, coef, X, dt_dev, st->stream);
+      la.out = ui;
+      ProfScope ps(st, KC_INNER);
+      e = launch_loc_combine(st->eq, st->k, st->ph, st->geo, la, st->stream);
       stages[i] = ui;
       lays[i] = L64;
     }

@@ -90,6 +90,22 @@ struct FinalArgs {
   double cst[MAXS];
 };
 
+// one inner stage of a full tableau (FP64 layout): L_{i-1} = loc(in), stored
+// to L_out if set; out = un + sum_j coef_j X_j (+ coef_last L_{i-1} if
+// use_last), every coefficient times *dt_ptr if set
+struct LocCombineArgs {
+  const double* in;       // u^(i-1)
+  const double* un;       // u^n
+  double* L_out;          // NULL: L_{i-1} is not needed by a later stage
+  double* out;            // u^(i)
+  const double* X[MAXS];  // L_j (j < i - 1) with a_ij != 0, ascending j
+  double coef[MAXS];
+  int nx;
+  int use_last;           // a_{i,i-1} != 0
+  double coef_last;
+  const double* dt_ptr;
+};
+
 // launchers (crkdg_kernels.hip); each returns hipSuccess or the launch error.
 // prec: one of Prec (layouts and compute types follow from it).
 // device time of time-dependent boundary data: *t = v, or *t += *dt
@@ -101,6 +117,8 @@ hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g
                         const BCDev& bc, const FinalArgs& a, hipStream_t s);
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s);
+hipError_t launch_loc_combine(int eq, int k, const PhysDev& ph, const Geo& g,
+                              const LocCombineArgs& a, hipStream_t s);
 hipError_t launch_combine(long long n, double* out, const double* base, int nx,
                           const double* coef, const double* const* X, const double* dt_ptr,
                           hipStream_t s);

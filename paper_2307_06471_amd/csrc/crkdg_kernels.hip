@@ -995,6 +995,49 @@ __global__ __launch_bounds__(256) void k_loc(PhysDev ph, Geo g, const double* __
   store_state<R, NC, NB, L64>(out, g.N, cell, acc);
 }
 
+// One inner stage of a tableau with a full lower triangle in one pass:
+// L_{i-1} = loc(u^(i-1)) (equation (dxl)), stored only when a later stage
+// needs it, and u^(i) = u^n + sum_{j<i} coef_j L_j (equation (crkdg), first
+// line), the earlier L_j read back, L_{i-1} taken from registers and added
+// last (the order of the two-pass k_loc + k_combine, so the bits agree).
+template <class EQ, int K>
+__global__ __launch_bounds__(256) void k_loc_combine(PhysDev ph, Geo g, LocCombineArgs a) {
+  constexpr int NC = EQ::NC, NB = Sizes<K, EQ::DIM>::NB;
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= g.N) return;
+  const EQ eq = make_eq<EQ>(ph);
+  double u[NC][NB], L[NC][NB];
+  load_state<double, NC, NB, L64>(a.in, g.N, cell, u);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) L[c][b] = 0.0;
+  loc_acc<EQ, K, double>(eq, u, 1.0, g.inv_dx, g.inv_dy, L);
+  if (a.L_out) store_state<double, NC, NB, L64>(a.L_out, g.N, cell, L);
+  // the accumulator starts from u^n (already in u when u^(i-1) is u^n)
+  if (a.in != a.un) load_state<double, NC, NB, L64>(a.un, g.N, cell, u);
+  const double scale = a.dt_ptr ? *a.dt_ptr : 1.0;
+  const unsigned o8 = (unsigned)cell * 8u;
+#pragma unroll 1
+  for (int j = 0; j < a.nx; ++j) {
+    const double cf = a.coef[j] * scale;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const auto r = rsrc(byte_add(a.X[j], (long long)c * NB * g.N * 8));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = u[c][b] + cf * bload<double>(r, o8, (unsigned)(b * g.N * 8));
+    }
+  }
+  if (a.use_last) {
+    const double cf = a.coef_last * scale;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = u[c][b] + cf * L[c][b];
+  }
+  store_state<double, NC, NB, L64>(a.out, g.N, cell, u);
+}
+
 // ---------------------------------------------------------------------------
 // RK stage combination: out = base + sum_j (coef_j * dtscale) X_j
 // ---------------------------------------------------------------------------
@@ -1965,6 +2008,13 @@ struct RunLoc {
   }
 };
 template <class EQ, int K>
+struct RunLocCombine {
+  static hipError_t run(const PhysDev& ph, const Geo& g, const LocCombineArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_loc_combine<EQ, K>), dim3(nblk(g.N, 256)), dim3(256), 0, s, ph, g, a);
+    return hipGetLastError();
+  }
+};
+template <class EQ, int K>
 struct RunWave {
   static hipError_t run(const PhysDev& ph, const Geo& g, const void* u, int lay, double* partial,
                         int nb, double cfl, double* smax, double* dt, hipStream_t s) {
@@ -2076,6 +2126,11 @@ hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s) {
   return dispatch<RunLoc>(eq, k, ph, g, in, out, s);
+}
+hipError_t launch_loc_combine(int eq, int k, const PhysDev& ph, const Geo& g,
+                              const LocCombineArgs& a, hipStream_t s) {
+  if (a.nx < 0 || a.nx > MAXS) return hipErrorInvalidValue;
+  return dispatch<RunLocCombine>(eq, k, ph, g, a, s);
 }
 hipError_t launch_combine(long long n, double* out, const double* base, int nx,
                           const double* coef, const double* const* X, const double* dt_ptr,

@@ -199,3 +199,19 @@ def test_euler_q3_fehlberg(K):
         u = O.step_crkdg(om, k, RKF5, n * dt, dt, u)
     assert np.isfinite(u).all()
     assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+def test_fehlberg_device_dt_equals_host_dt(K):
+    """the six-stage path with dt in device memory gives the host-dt bits"""
+    import torch
+    k, N = 4, 257
+    _, s1 = burgers(K, N, k, 5)
+    _, s2 = burgers(K, N, k, 5)
+    s1.crkdg_project(K.IC_BURGERS_SIN)
+    s2.crkdg_project(K.IC_BURGERS_SIN)
+    dt = 0.05 * 2 * PI / N
+    d = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s1.crkdg_step(dt)
+        s2.crkdg_step_dev(d)
+    assert np.array_equal(s1.crkdg_get_state(), s2.crkdg_get_state())
