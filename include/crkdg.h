@@ -181,6 +181,11 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
  * (Section 3.2.1 gives the order-2 form): every stage applies the DG
  * operator with face fluxes and boundary data at its stage time and, when
  * M >= 0, the TVB limiter of crkdg_limit (no flags); M < 0 skips the limiter.
+ * order 0: the Butcher form of equation (rkdg) with the state's own tableau
+ * (crkdg_create's rk_stages or crkdg_set_tableau; Section 4 runs RKDG with
+ * classical RK4 at k = 3 and the fifth-order Runge--Kutta--Fehlberg method at
+ * k = 4), without limiter (M must be < 0, else CRKDG_EINVAL); it uses the
+ * workspace's operator slots and first two stage slots.
  * FP64 state only (CRKDG_EUNSUPPORTED otherwise).  dt_dev (device double,
  * nullable) overrides dt, as in crkdg_step_dev (with time-dependent boundary
  * data the time is kept and advanced in device memory, the stages' data and

@@ -244,7 +244,8 @@ class Solver:
 
     def crkdg_step_rkdg(self, order, dt, M=-1.0, dt_tensor=None):
         """one original-RKDG step (SSP order 2 or 3, limiter every stage if
-        M >= 0); dt_tensor: device double that overrides dt"""
+        M >= 0; order 0: Butcher form with the handle's tableau, M < 0);
+        dt_tensor: device double that overrides dt"""
         p = None if dt_tensor is None else C.c_void_p(dt_tensor.data_ptr())
         _check(lib().crkdg_step_rkdg(self.h, int(order), float(M), float(dt), p),
                "crkdg_step_rkdg")

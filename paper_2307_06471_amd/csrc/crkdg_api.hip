@@ -598,7 +598,8 @@ static int limit_impl(crkdg_state* st, double M, const float* params, float tau_
 int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const double* dt_dev) {
   if (!st) return CRKDG_EINVAL;
   if (!st->bound) return CRKDG_EUNBOUND;
-  if ((order != 2 && order != 3) || isnan(M)) return CRKDG_EINVAL;
+  if ((order != 0 && order != 2 && order != 3) || isnan(M)) return CRKDG_EINVAL;
+  if (order == 0 && M >= 0.0) return CRKDG_EINVAL;  // the Butcher form runs unlimited
   if (!dt_dev && (!isfinite(dt) || !(dt > 0.0))) return CRKDG_EINVAL;
   if (st->prec != P64) return CRKDG_EUNSUPPORTED;
   // time-dependent boundary data with dt on the device: the time lives in
@@ -648,6 +649,72 @@ int crkdg_step_rkdg(crkdg_state* st, int order, double M, double dt, const doubl
                              st->t + f * h, nullptr, 0.0);
   };
   const double t = st->t;
+  if (order == 0) {
+    // Butcher form with the state's tableau: E_i = -dt DG(u^(i)) at the
+    // stage time t + c_i dt (a final-stage pass from a zero base), u^(i) =
+    // u^n + sum_{j<i} a_ij E_j and u^{n+1} = u^n + sum_i b_i E_i (combination
+    // passes); E_j lives in the j-th operator slot, the last one in the
+    // second stage slot, u^(i) (i >= 1) in the first stage slot
+    const int s = st->s;
+    const long long n = (long long)(st->S / sizeof(double));
+    auto E = [&](int j) { return (double*)(j < st->ws - 1 ? lbuf_ptr(st, j) : stage_ptr(st, 2)); };
+    int rc = CRKDG_OK;
+    for (int i = 0; i < s && !rc; ++i) {
+      const void* ui = u0;
+      if (i > 0) {
+        double coef[MAXS];
+        const double* X[MAXS];
+        int nx = 0;
+        for (int j = 0; j < i; ++j) {
+          if (st->A[i][j] == 0.0) continue;
+          coef[nx] = st->A[i][j];
+          X[nx++] = E(j);
+        }
+        ProfScope ps(st, KC_COMBINE);
+        if (launch_combine(n, (double*)s1, (const double*)u0, nx, coef, X, nullptr, st->stream) !=
+            hipSuccess)
+          rc = CRKDG_EHIP;
+        ui = s1;
+      }
+      if (!rc) {
+        FinalArgs fa{};
+        fa.t_ptr = tdev ? td : nullptr;
+        fa.cst[0] = st->c[i];
+        fa.base = nullptr;
+        fa.lay_base = st->lay;
+        fa.out = E(i);
+        fa.dt = dt;
+        fa.dt_ptr = dt_dev;
+        fa.ns = 1;
+        fa.st[0] = ui;
+        fa.lay[0] = st->lay;
+        fa.w[0] = 1.0;
+        fa.tst[0] = t + st->c[i] * h;
+        ProfScope ps(st, KC_FINAL);
+        if (launch_final(st->eq, st->k, st->prec, st->ph, st->geo, st->bc, fa, st->stream) !=
+            hipSuccess)
+          rc = CRKDG_EHIP;
+      }
+    }
+    if (!rc) {
+      double coef[MAXS];
+      const double* X[MAXS];
+      int nx = 0;
+      for (int i = 0; i < s; ++i) {
+        if (st->b[i] == 0.0) continue;
+        coef[nx] = st->b[i];
+        X[nx++] = E(i);
+      }
+      ProfScope ps(st, KC_COMBINE);
+      if (launch_combine(n, (double*)un, (const double*)u0, nx, coef, X, nullptr, st->stream) !=
+          hipSuccess)
+        rc = CRKDG_EHIP;
+    }
+    if (!rc) st->cur ^= 1;
+    if (!rc && tdev) rc = launch_time_add(td, dt_dev, st->stream) == hipSuccess ? CRKDG_OK : CRKDG_EHIP;
+    if (!rc && !dt_dev) st->t += dt;
+    return rc;
+  }
   int rc = pass(nullptr, 1.0, 0.0, u0, 1.0, t, 0.0, s1);  // u^(1) = u^n - dt DG(u^n)
   if (!rc) rc = limit(s1, 1.0);
   if (order == 2) {  // u^{n+1} = u^n / 2 + (u^(1) - dt DG(u^(1))) / 2

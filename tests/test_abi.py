@@ -207,7 +207,8 @@ def test_rkdg_step_argument_checks():
     assert L.crkdg_step_rkdg(h, 3, 50.0, 0.1, None) == K.CRKDG_EUNBOUND
     assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
     for order, M, dt in ((1, 50.0, 0.1), (4, 50.0, 0.1), (3, float("nan"), 0.1),
-                         (3, 50.0, 0.0), (2, -1.0, float("inf")), (3, 50.0, -1.0)):
+                         (3, 50.0, 0.0), (2, -1.0, float("inf")), (3, 50.0, -1.0),
+                         (0, 50.0, 0.1), (0, 0.0, 0.1), (0, -1.0, 0.0), (-1, -1.0, 0.1)):
         assert L.crkdg_step_rkdg(h, order, M, dt, None) == K.CRKDG_EINVAL, (order, M, dt)
     L.crkdg_destroy(h)
     for prec in (K.FP32_MIXED, K.FP32_INNER):

@@ -117,3 +117,65 @@ def test_device_dt_and_conservation(K):
     assert np.array_equal(a, b)
     for c in range(4):
         assert abs(s.crkdg_total(c) - before[c]) <= 1e-13 * max(1.0, abs(before[c]))
+
+
+# --- the Butcher form with the state's tableau (order 0) ----------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_butcher_form_euler_rk4(K, k):
+    from tests.tableaus import RK4
+    om, s = pair(K, 2, 70, 9, k, "euler", box=(0.0, 2.0, 0.0, 1.0))
+    s4 = K.Solver(s.mesh, k, K.FLUX_LLF, 4)
+    u = W.random_euler_modes(np.random.default_rng(60 + k), (k + 1) ** 2, 70 * 9)
+    s4.crkdg_set_state(u)
+    dt = 5e-4
+    for n in range(3):
+        s4.crkdg_step_rkdg(0, dt)
+        u = O.step_rkdg(om, k, RK4, n * dt, dt, u)
+    assert np.isfinite(u).all()
+    assert rel_err(s4.crkdg_get_state(), u) < TOL
+
+
+def test_butcher_form_inflow_stage_times_fehlberg(K):
+    """1D advection with inflow data sin(-t): the six stages of Fehlberg's
+    method take their boundary data at t + c_i dt"""
+    from tests.tableaus import RKF5
+    N, k = 60, 4
+    L = 4 * np.pi
+    om = O.Mesh(1, N, x0=0.0, x1=L, bc=(2, 1, 0, 0), adv=(1.0, 0.0), bc_exact=O.IC_ADV_SIN,
+                equation=O.EQ_ADVECTION, flux=O.FLUX_UPWIND)
+    lm = K.make_mesh(1, N, 1, x0=0.0, x1=L, bc=(2, 1, 0, 0), adv=(1.0, 0.0),
+                     bc_exact=K.IC_ADV_SIN, equation=K.EQ_ADVECTION)
+    s = K.Solver(lm, k, K.FLUX_UPWIND, 5)
+    s.crkdg_project(K.IC_ADV_SIN)
+    u = O.project(om, k, O.IC_ADV_SIN)
+    dt = 0.02 * L / N
+    for n in range(20):
+        s.crkdg_step_rkdg(0, dt)
+        u = O.step_rkdg(om, k, RKF5, n * dt, dt, u)
+    assert rel_err(s.crkdg_get_state(), u) < TOL
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_butcher_form_burgers_table_rows(K, k):
+    """the RKDG rows of Table 'table_burgers1d' at N = 40, 80: RK4 (k = 3)
+    and Fehlberg (k = 4) in Butcher form, errors within 9% of the printed
+    ones and equal to the oracle's"""
+    import math
+    from tests.tableaus import RK4, RKF5
+    printed = {3: [6.3822e-07, 4.1961e-08], 4: [1.0505e-08, 3.5188e-10]}[k]
+    for i, N in enumerate((40, 80)):
+        om = O.Mesh(1, N, x0=-np.pi, x1=np.pi, equation=O.EQ_BURGERS, flux=O.FLUX_GODUNOV)
+        lm = K.make_mesh(1, N, 1, x0=-np.pi, x1=np.pi, equation=K.EQ_BURGERS)
+        s = K.Solver(lm, k, K.FLUX_GODUNOV, 4 if k == 3 else 5)
+        s.crkdg_project(K.IC_BURGERS_SIN)
+        u = O.project(om, k, O.IC_BURGERS_SIN)
+        dt = 0.05 * 2 * np.pi / N
+        n = math.floor(0.2 / dt + 1e-12)
+        for j in range(n):
+            s.crkdg_step_rkdg(0, dt)
+            u = O.step_rkdg(om, k, RK4 if k == 3 else RKF5, j * dt, dt, u)
+        assert rel_err(s.crkdg_get_state(), u) < TOL
+        e = s.crkdg_error(K.IC_BURGERS_SIN, t=n * dt)
+        print(f"[rkdg butcher] k={k} N={N} L2 {e[1]:.5e} printed {printed[i]:.5e}", flush=True)
+        assert e[1] == pytest.approx(printed[i], rel=0.09)
