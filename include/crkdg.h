@@ -39,6 +39,13 @@
  *    perturbed-RK theorem it cites): perturbing only the inner-stage
  *    operator evaluations by O(eps) perturbs a step by O(eps dt^2), so this
  *    form keeps the FP64 accuracy.
+ *    CRKDG_FP32_INCREMENTS: the inner and the final stage compute in FP32
+ *    on FP64 states: both accumulate the increment over u^n in FP32 and add
+ *    it to u^n in FP64 (u^(i) as in CRKDG_FP32_INNER, u^{n+1} likewise; the
+ *    cell averages and face-flux sums stay FP64).  FP32 rounding then enters
+ *    a step only through increments of size O(dt), where the FP32-bulk form
+ *    also rounds the stored higher modes themselves every step.  FP64 DOF
+ *    layout; the limiter is the FP64 one.
  *  - Errors: every int-returning call returns CRKDG_OK (0) or a negative code;
  *    crkdg_strerror maps it to text.  Kernel launch failures return
  *    CRKDG_EHIP.  Invalid arguments never reach a kernel.
@@ -67,7 +74,7 @@ extern "C" {
 enum { CRKDG_EQ_ADVECTION = 0, CRKDG_EQ_EULER = 1, CRKDG_EQ_BURGERS = 2 };
 enum { CRKDG_FLUX_UPWIND = 0, CRKDG_FLUX_LLF = 1, CRKDG_FLUX_GODUNOV = 2 };
 enum { CRKDG_BC_PERIODIC = 0, CRKDG_BC_TRANSMISSIVE = 1, CRKDG_BC_DIRICHLET = 2 };
-enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1, CRKDG_FP32_INNER = 2 };
+enum { CRKDG_FP64 = 0, CRKDG_FP32_MIXED = 1, CRKDG_FP32_INNER = 2, CRKDG_FP32_INCREMENTS = 3 };
 enum { CRKDG_OP_LOC = 0, CRKDG_OP_DG = 1 };
 
 /* initial conditions / exact solutions known to the library */

@@ -21,7 +21,7 @@ CRKDG_OK, CRKDG_EINVAL, CRKDG_EUNSUPPORTED, CRKDG_ENONPHYSICAL, CRKDG_EHIP, CRKD
 EQ_ADVECTION, EQ_EULER, EQ_BURGERS = 0, 1, 2
 FLUX_UPWIND, FLUX_LLF, FLUX_GODUNOV = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
-FP64, FP32_MIXED, FP32_INNER = 0, 1, 2
+FP64, FP32_MIXED, FP32_INNER, FP32_INCREMENTS = 0, 1, 2, 3
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
 IC_DMR = 6  # double Mach reflection

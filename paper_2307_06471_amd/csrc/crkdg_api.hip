@@ -37,7 +37,7 @@ struct crkdg_state {
   size_t S;       // bytes of one state (device layout lay)
   size_t S_stage; // bytes of one stored stage state (layout lay_stage)
   int lay, lay_stage;
-  int prec;  // Prec: P64, PBULK or PINNER
+  int prec;  // Prec: P64, PBULK, PINNER or PINC
   // per-launch timing (measurement only)
   bool prof;
   int prof_max;
@@ -187,7 +187,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   if (flux != CRKDG_FLUX_UPWIND && flux != CRKDG_FLUX_LLF && flux != CRKDG_FLUX_GODUNOV)
     return CRKDG_EINVAL;
   if (mesh->precision != CRKDG_FP64 && mesh->precision != CRKDG_FP32_MIXED &&
-      mesh->precision != CRKDG_FP32_INNER)
+      mesh->precision != CRKDG_FP32_INNER && mesh->precision != CRKDG_FP32_INCREMENTS)
     return CRKDG_EINVAL;
   for (int sd = 0; sd < 4; ++sd)
     if (mesh->bc[sd] < CRKDG_BC_PERIODIC || mesh->bc[sd] > CRKDG_BC_DIRICHLET) return CRKDG_EINVAL;
@@ -277,8 +277,10 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
     case 4: set_tableau_internal(st, 4, R4_c, R4_A, R4_b); break;
     default: set_tableau_internal(st, 6, F5_c, F5_A, F5_b); break;
   }
-  st->prec = mesh->precision == CRKDG_FP32_MIXED ? PBULK
-             : mesh->precision == CRKDG_FP32_INNER ? PINNER : P64;
+  st->prec = mesh->precision == CRKDG_FP32_MIXED        ? PBULK
+             : mesh->precision == CRKDG_FP32_INNER      ? PINNER
+             : mesh->precision == CRKDG_FP32_INCREMENTS ? PINC
+                                                        : P64;
   // stored stages use the state's layout
   if (st->prec == PBULK) {
     st->lay = LMIX;

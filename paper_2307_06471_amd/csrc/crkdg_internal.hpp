@@ -54,7 +54,11 @@ enum EqId { EQ_ADV1 = 0, EQ_ADV2 = 1, EQ_EULER2 = 2, EQ_BURGERS1 = 3 };
 //          stored stage formed as u^n + increment in FP64), FP64 final stage
 //          (Section 3.3: perturbing only the inner-stage operator evaluations
 //          by O(eps) perturbs a step by O(eps dt^2))
-enum Prec { P64 = 0, PBULK = 1, PINNER = 2 };
+//  PINC:   FP32 arithmetic in the inner and the final stage on FP64 states:
+//          both accumulate increments over u^n in FP32 and add them to u^n
+//          in FP64 (cell averages and face sums FP64), so FP32 rounding
+//          enters a step through dt-sized increments only
+enum Prec { P64 = 0, PBULK = 1, PINNER = 2, PINC = 3 };
 
 struct InnerArgs {
   const void* un;

@@ -699,6 +699,10 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
     hslot = tid - 2 * TX - TY;
   }
 
+  // FP32 arithmetic on the FP64 layout: acc holds the increment over u^n
+  // (FP32), added to u^n in FP64 at the store (the FP32-increments form)
+  constexpr bool INC = LAY == L64 && sizeof(R) == 4;
+  static_assert(!(INC && B2), "the original RKDG runs in FP64");
   R acc[NC][NB];
   double a0[NC];  // cell averages, FP64
 #pragma unroll
@@ -709,9 +713,9 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
   }
   // u^n is usually also the first final-stage state (u^(1) = u^n): then it is
   // read once, in the stage loop
-  const bool base_is_st0 = a.base != nullptr && a.ns > 0 && a.base == a.st[0];
+  const bool base_is_st0 = !INC && a.base != nullptr && a.ns > 0 && a.base == a.st[0];
   if (active && a.base) {
-    if (!base_is_st0) load_state<R, NC, NB, LAY>(a.base, g.N, cell, acc);
+    if (!INC && !base_is_st0) load_state<R, NC, NB, LAY>(a.base, g.N, cell, acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c) a0[c] = load_avg<NC, NB, LAY>(a.base, g.N, c, cell);
   }
@@ -879,7 +883,23 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
       }
     lift_y<EQ, K, R>(gr, gl, R(-0.5 * dt * g.inv_dy), acc);
   }
-  store_state<R, NC, NB, LAY>(a.out, g.N, cell, acc, a0);
+  if constexpr (INC) {
+    // u^{n+1} = u^n + increment, formed in FP64 (one rounding per mode)
+    const unsigned o8 = (unsigned)cell * 8u;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const auto rin = rsrc(byte_add(a.base, (long long)c * NB * g.N * 8));
+      const auto rout = rsrc(byte_add(a.out, (long long)c * NB * g.N * 8));
+      bstore<double>(a0[c], rout, o8, 0u);
+#pragma unroll
+      for (int b = 1; b < NB; ++b) {
+        const unsigned so = (unsigned)(b * g.N * 8);
+        bstore<double>(bload<double>(rin, o8, so) + (double)acc[c][b], rout, o8, so);
+      }
+    }
+  } else {
+    store_state<R, NC, NB, LAY>(a.out, g.N, cell, acc, a0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1970,7 +1990,7 @@ struct FinalL {
         if (a.base2 && (a.ns < 1 || a.base2 != a.st[0])) return hipErrorInvalidValue;
         const dim3 blk(T::TX * T::TY);
         const bool dmr = bc.exact == CRKDG_IC_DMR;
-        if constexpr (LAY == L64) {
+        if constexpr (LAY == L64 && sizeof(typename EQ::Real) == 8) {
           if (a.base2) {
             if constexpr (EQ::EULER) {
               if (dmr) {
@@ -2112,7 +2132,8 @@ hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g
                         const InnerArgs& a, hipStream_t s) {
   switch (prec) {
     case PBULK: return dispatch_mixed<InnerL<LMIX, LMIX, false>::template Run>(eq, k, ph, g, a, s);
-    case PINNER: return dispatch_mixed<InnerL<L64, L64, true>::template Run>(eq, k, ph, g, a, s);
+    case PINNER:
+    case PINC: return dispatch_mixed<InnerL<L64, L64, true>::template Run>(eq, k, ph, g, a, s);
     default: return dispatch<InnerL<L64, L64, false>::template Run>(eq, k, ph, g, a, s);
   }
 }
@@ -2120,6 +2141,9 @@ hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g
                         const BCDev& bc, const FinalArgs& a, hipStream_t s) {
   switch (prec) {
     case PBULK: return dispatch_mixed<FinalL<LMIX>::template Run>(eq, k, ph, g, bc, a, s);
+    case PINC:  // FP32 increments over the FP64 u^n
+      if (!a.base || a.base2) return hipErrorInvalidValue;
+      return dispatch_mixed<FinalL<L64>::template Run>(eq, k, ph, g, bc, a, s);
     default: return dispatch<FinalL<L64>::template Run>(eq, k, ph, g, bc, a, s);  // FP64 final stage
   }
 }

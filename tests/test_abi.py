@@ -106,7 +106,9 @@ def _create(**kw):
     (dict(gamma=1.0), K.CRKDG_EINVAL),
     (dict(x1=0.0), K.CRKDG_EINVAL),
     (dict(bc=(7, 0, 0, 0)), K.CRKDG_EINVAL),
-    (dict(precision=3), K.CRKDG_EINVAL),
+    (dict(precision=4), K.CRKDG_EINVAL),
+    (dict(precision=K.FP32_INCREMENTS, k=0), K.CRKDG_EUNSUPPORTED),
+    (dict(precision=K.FP32_INCREMENTS, k=4), K.CRKDG_EUNSUPPORTED),
     (dict(precision=K.FP32_INNER, equation=K.EQ_ADVECTION), K.CRKDG_EUNSUPPORTED),
     (dict(precision=K.FP32_INNER, k=0), K.CRKDG_EUNSUPPORTED),
     (dict(precision=K.FP32_MIXED, k=0), K.CRKDG_EUNSUPPORTED),
@@ -133,6 +135,7 @@ def test_create_sizes_and_unbound_errors():
 def test_state_sizes_of_the_precision_forms():
     L = K.lib()
     for prec, nbytes in ((K.FP64, 4 * 9 * 64 * 8), (K.FP32_INNER, 4 * 9 * 64 * 8),
+                         (K.FP32_INCREMENTS, 4 * 9 * 64 * 8),
                          (K.FP32_MIXED, 4 * 64 * 8 + 4 * 8 * 64 * 4)):
         rc, h = _create(precision=prec)
         assert rc == 0
@@ -211,7 +214,7 @@ def test_rkdg_step_argument_checks():
                          (0, 50.0, 0.1), (0, 0.0, 0.1), (0, -1.0, 0.0), (-1, -1.0, 0.1)):
         assert L.crkdg_step_rkdg(h, order, M, dt, None) == K.CRKDG_EINVAL, (order, M, dt)
     L.crkdg_destroy(h)
-    for prec in (K.FP32_MIXED, K.FP32_INNER):
+    for prec in (K.FP32_MIXED, K.FP32_INNER, K.FP32_INCREMENTS):
         rc, h = _create(precision=prec)
         assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
         assert L.crkdg_step_rkdg(h, 3, 50.0, 0.1, None) == K.CRKDG_EUNSUPPORTED

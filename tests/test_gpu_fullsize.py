@@ -15,7 +15,8 @@ Each case runs the library in the launch configuration the benchmark times
 steps before the checked step.
 
 Tolerances: FP64 path 1e-12 relative to the largest value in the cell;
-FP32-bulk path 1e-5 relative (FP32 arithmetic on FP32-stored modes, one step).
+FP32-bulk and FP32-increments paths 1e-5 relative (FP32 arithmetic, one
+step).
 Limiter decisions are compared where the oracle's decision margin is above
 1e-9 of the compared values' scale (both sides decide in FP64).
 """
@@ -107,6 +108,7 @@ CASES = [
     ("c4", "mixed", 1001, 4),
     ("c5", "fp64", 2000, 3),
     ("c5", "mixed", 2000, 3),
+    ("c5", "incr", 2000, 3),
 ]
 
 
@@ -114,7 +116,7 @@ CASES = [
 def test_full_size_sampled_parity(K, case):
     import torch
     name, prec, seed, pre = case
-    precision = K.FP64 if prec == "fp64" else K.FP32_MIXED
+    precision = {"fp64": K.FP64, "mixed": K.FP32_MIXED, "incr": K.FP32_INCREMENTS}[prec]
     tol = 1e-12 if prec == "fp64" else 1e-5
     s, cfg, bc, bc_state = build(K, name, precision, seed)
     print(f"[fullsize] {name} {prec} {cfg['nx']}x{cfg['ny']} k={cfg['k']}", flush=True)
