@@ -536,12 +536,13 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg"):
             "cells": s.ncells, "dofs": dofs, "nx": cfg["nx"], "ny": cfg["ny"]}
 
 
-def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002), checkpoints=(0.05, 0.1, 0.25),
+def equal_error(K, W, scale, mlp, seeds=(2000, 2001, 2002, 2003, 2004, 2005),
+                checkpoints=(0.05, 0.1, 0.25),
                 samples=10):
     """the shock workload with cell counts divided by `scale`, run to T = 0.25
     by FP64 + TVB, the original RKDG (SSP-RK3, limiter every stage, FP64),
-    FP32-inner + TVB, FP32-bulk + TVB and FP32-bulk + learned indicator, for
-    each seed; L1/L2 density errors of the cell averages against FP64 + TVB on the
+    FP32-inner + TVB, FP32-bulk + TVB, FP32-bulk + learned indicator and the
+    two FP32-increments forms, for each seed; L1/L2 density errors of the cell averages against FP64 + TVB on the
     2x finer mesh restricted to this one (same initial density function), at
     each checkpoint time (the runs land on them exactly).
 
