@@ -215,3 +215,61 @@ def test_fehlberg_device_dt_equals_host_dt(K):
         s1.crkdg_step(dt)
         s2.crkdg_step_dev(d)
     assert np.array_equal(s1.crkdg_get_state(), s2.crkdg_get_state())
+
+
+@pytest.mark.parametrize("case", ["adv2d-q4-4096x1024", "burgers-p4-2^24"])
+def test_fehlberg_full_size_sampled_parity(K, case):
+    """the benchmark's degree-4 Fehlberg workloads at full size: after two
+    steps, one more step is checked on sampled cells, each against the
+    oracle's step of the patch of its face neighbours (the compact stencil
+    of Section 3.1: u^{n+1} of a cell depends on u^n of the cell and its
+    face neighbours only; the periodic patch wraps onto itself, which
+    changes its edge cells but not the centre)"""
+    rng = np.random.default_rng(17)
+    if case.startswith("adv"):
+        nx, ny, k = 4096, 1024, 4
+        lm = K.make_mesh(2, nx, ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, equation=K.EQ_ADVECTION,
+                         adv=(1.0, 0.5))
+        s = K.Solver(lm, k, K.FLUX_UPWIND, 5)
+        s.crkdg_project(K.IC_ADV_SIN)
+        dt = 0.02 / (1.0 * 1024 + 0.5 * 1024)
+        dx, dy = 4.0 / nx, 1.0 / ny
+    else:
+        nx, ny, k = 1 << 24, 1, 4
+        lm = K.make_mesh(1, nx, 1, x0=-PI, x1=PI, equation=K.EQ_BURGERS)
+        s = K.Solver(lm, k, K.FLUX_GODUNOV, 5)
+        s.crkdg_project(K.IC_BURGERS_SIN)
+        dt = 0.05 * 2 * PI / nx
+        dx, dy = 2 * PI / nx, 1.0
+    print(f"[fullsize] fehlberg {case}", flush=True)
+    for _ in range(2):
+        s.crkdg_step(dt)
+    u0 = s.crkdg_get_state()
+    s.crkdg_step(dt)
+    u1 = s.crkdg_get_state()
+    assert np.isfinite(u1).all()
+    fixed = [(0, 0), (nx - 1, 0), (nx // 2, ny - 1), (63, 0), (64, ny - 1), (65, ny // 2)]
+    cells = fixed + [(int(a), int(b)) for a, b in
+                     zip(rng.integers(0, nx, 100), rng.integers(0, ny, 100))]
+    worst = 0.0
+    for (i, j) in cells:
+        ii = [(i + d) % nx for d in (-1, 0, 1)]
+        if ny > 1:
+            jj = [(j + d) % ny for d in (-1, 0, 1)]
+            idx = np.array([b * nx + a for b in jj for a in ii])
+            om = O.Mesh(2, 3, 3, x0=(i - 1) * dx, x1=(i + 2) * dx, y0=(j - 1) * dy,
+                        y1=(j + 2) * dy, equation=O.EQ_ADVECTION, adv=(1.0, 0.5),
+                        flux=O.FLUX_UPWIND)
+            centre = 4
+        else:
+            idx = np.array(ii)
+            om = O.Mesh(1, 3, x0=-PI + (i - 1) * dx, x1=-PI + (i + 2) * dx,
+                        equation=O.EQ_BURGERS, flux=O.FLUX_GODUNOV)
+            centre = 1
+        up = np.ascontiguousarray(u0[:, :, idx])
+        ref = O.step_crkdg(om, k, RKF5, 0.0, dt, up)[:, :, centre]
+        got = u1[:, :, j * nx + i]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err < TOL, (i, j, err)
+    print(f"[fullsize] fehlberg {case}: worst error {worst:.2e}", flush=True)
