@@ -309,6 +309,30 @@ def fehlberg_study(K, steps=10, warmup=2):
     return out
 
 
+def stream_copy_gbs(nbytes=1 << 30, reps=10):
+    """achievable HBM bandwidth on this device: a device-to-device copy of
+    `nbytes` (read once, written once), the best of `reps` event-timed
+    copies, in GB/s of bytes moved"""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def save_indicator(path, P, lo, hi, info):
     """a trained indicator as .npz: parameters, band, training report (JSON)"""
     np.savez(path, P=np.asarray(P, dtype=np.float32), lo=lo, hi=hi,
@@ -325,8 +349,8 @@ def load_indicator(path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--equal-error-scale", type=int, default=4,
@@ -396,6 +420,9 @@ def main():
         rk = run_form(K, W, args, K.FP64, None, scheme="rkdg3")
         log(f"fp64 RKDG SSP3 + TVB every stage: {rk['ms_per_step']:.3f} ms/step")
     head = forms["fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"]
+    copy_gbs = round(stream_copy_gbs(), 1)
+    log(f"stream copy: {copy_gbs} GB/s; the dominant kernel at "
+        f"{head['roofline']['achieved'] / copy_gbs:.3f} of it")
     plain = forms["fp64 + TVB"]
     tvb32 = forms["fp32-bulk + TVB"]
     out = {
@@ -414,6 +441,8 @@ def main():
                            "fp32-bulk + TVB (profiling run without the learned indicator)",
                    "cells": head["cells"], "dofs": head["dofs"], "parallelism": "1 GPU"},
         "roofline": head["roofline"],
+        "stream_copy_GBs": copy_gbs,
+        "frac_of_stream_copy": round(head["roofline"]["achieved"] / copy_gbs, 4),
         "kernels": head["kernels"],
         "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"],
                        "roofline": plain["roofline"], "kernels": plain["kernels"]},
