@@ -6,7 +6,7 @@
   python -m paper_2307_06471_amd.profsummary counters <counter_collection.csv>
       "<kernel>;<kernel>;..." <out.txt> <command>
       per-dispatch SQ/GRBM counter averages of the named kernels and the
-      VALU-instructions-per-wave, VALU-busy and memory-wait ratios
+      VALU-instructions-per-wave, VALU-busy, MFMA-busy and memory-wait ratios
 
   python -m paper_2307_06471_amd.profsummary traffic <fetch counter_collection.csv>
       <write counter_collection.csv> <kernel substring> <copy_bytes> <out.txt> <command>
@@ -97,7 +97,10 @@ def counters(csv_path, kernels, out, command, simds=1024, xcds=8):
         (SQ_ACTIVE_INST_VALU counts in units of 4 cycles; GRBM_GUI_ACTIVE is
         summed over the XCDs)
       wait_fraction = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of the waves'
-        lifetime spent waiting for memory results)"""
+        lifetime spent waiting for memory results)
+    and, when counted, mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (simds *
+    GRBM_GUI_ACTIVE / xcds) and mfma_bf16_flop = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16
+    per dispatch"""
     rows = list(csv.DictReader(open(csv_path)))
     lines = [f"# SQ counters per dispatch", "",
              "command (repo root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):",
@@ -122,6 +125,11 @@ def counters(csv_path, kernels, out, command, simds=1024, xcds=8):
         if "SQ_ACTIVE_INST_VALU" in avg and "GRBM_GUI_ACTIVE" in avg:
             busy = 4.0 * avg["SQ_ACTIVE_INST_VALU"] / (simds * avg["GRBM_GUI_ACTIVE"] / xcds)
             lines.append(f"  valu_busy: {busy:.3f}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and "GRBM_GUI_ACTIVE" in avg:
+            mb = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * avg["GRBM_GUI_ACTIVE"] / xcds)
+            lines.append(f"  mfma_busy: {mb:.4f}")
+        if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in avg:
+            lines.append(f"  mfma_bf16_flop: {avg['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512:.4g}")
         if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
             lines.append(f"  wait_fraction: {avg['SQ_WAIT_INST_ANY'] / avg['SQ_WAVE_CYCLES']:.3f}")
         lines.append("")
