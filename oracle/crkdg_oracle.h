@@ -20,7 +20,10 @@
  *   - Shu--Osher substitution, Section 3.2.1, equations (ssprk2) and
  *     (ssprk2-wrong_scheme);
  *   - limiter applied once after the final stage, Section 2.2 remark on
- *     limiters and Section 4.2.
+ *     limiters and Section 4.2;
+ *   - Burgers' equation with the Godunov flux and its exact solution by
+ *     characteristics, Section 4.1.1 example 'ex:1dburgers' (pinned to the
+ *     printed errors of Table 'table_burgers1d').
  * Readings of points the paper leaves open are listed in the design notes
  * (quadrature, Lax--Friedrichs alpha, TVB limiter details, error norms).
  *
