@@ -179,3 +179,57 @@ def test_butcher_form_burgers_table_rows(K, k):
         e = s.crkdg_error(K.IC_BURGERS_SIN, t=n * dt)
         print(f"[rkdg butcher] k={k} N={N} L2 {e[1]:.5e} printed {printed[i]:.5e}", flush=True)
         assert e[1] == pytest.approx(printed[i], rel=0.09)
+
+
+# --- Example 'ex:2dadv' (Table 'table:2dlinear-dirichlet') on rectangles ----
+
+def _adv2d(K, N, scheme, inflow):
+    bc = (2, 1, 2, 1) if inflow else (0, 0, 0, 0)
+    kw = dict(x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, bc=bc, adv=(1.0, 1.0),
+              bc_exact=K.IC_ADV_SIN if inflow else 0)
+    lm = K.make_mesh(2, N, N, equation=K.EQ_ADVECTION, **kw)
+    om = O.Mesh(2, N, N, x0=-1, x1=1, y0=-1, y1=1, bc=bc, adv=(1.0, 1.0),
+                bc_exact=O.IC_ADV_SIN if inflow else 0, equation=O.EQ_ADVECTION,
+                flux=O.FLUX_UPWIND)
+    s = K.Solver(lm, 3, K.FLUX_UPWIND, 4)
+    s.crkdg_project(K.IC_ADV_SIN)
+    n = round(0.4 / ((2.0 / N) / (30 if scheme == "crkdg" else 20)))
+    dt = 0.4 / n
+    for _ in range(n):
+        if scheme == "crkdg":
+            s.crkdg_step(dt)
+        else:
+            s.crkdg_step_rkdg(0, dt)
+    return s, om, n, dt
+
+
+def test_2d_inflow_cartesian_analogue(K):
+    """Q^3 / RK4 on N x N rectangles of [-1, 1]^2 with inflow data on the
+    left and bottom (the paper's example on triangles): the GPU runs equal
+    the oracle's at N = 16, and from N = 64 to 128 cRKDG stays fourth order
+    in L2 and Linf while the Butcher-form RKDG drops to about second order
+    in Linf, as in the paper's table"""
+    from tests.tableaus import RK4
+    for scheme in ("crkdg", "rkdg"):
+        s, om, n, dt = _adv2d(K, 16, scheme, True)
+        u = O.project(om, 3, O.IC_ADV_SIN)
+        step = O.step_crkdg if scheme == "crkdg" else O.step_rkdg
+        for i in range(n):
+            u = step(om, 3, RK4, i * dt, dt, u)
+        assert rel_err(s.crkdg_get_state(), u) < TOL, scheme
+    errs = {}
+    for scheme in ("crkdg", "rkdg"):
+        e = []
+        for N in (32, 64, 128):
+            s, om, n, dt = _adv2d(K, N, scheme, True)
+            e.append(s.crkdg_error(K.IC_ADV_SIN, t=0.4))
+        errs[scheme] = e
+        o2 = [np.log2(e[i][1] / e[i + 1][1]) for i in range(2)]
+        oi = [np.log2(e[i][2] / e[i + 1][2]) for i in range(2)]
+        print(f"[2d inflow] {scheme}: L2 {[f'{x[1]:.3e}' for x in e]} orders {o2}; "
+              f"Linf {[f'{x[2]:.3e}' for x in e]} orders {oi}", flush=True)
+    c, r = errs["crkdg"], errs["rkdg"]
+    assert abs(np.log2(c[1][1] / c[2][1]) - 4.0) < 0.15
+    assert abs(np.log2(c[1][2] / c[2][2]) - 4.0) < 0.2
+    assert np.log2(r[1][2] / r[2][2]) < 2.6
+    assert c[2][2] < 0.2 * r[2][2]
