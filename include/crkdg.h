@@ -288,7 +288,7 @@ int crkdg_total(crkdg_state* st, int comp, double* out_host);
  * out = loc(in) or DG(in) at boundary-data time t_bc (device arrays in the
  * state's layout, FP64 layout only). */
 int crkdg_apply_op(crkdg_state* st, int op, const void* in_dev, void* out_dev, double t_bc);
-/* RK stage combination out = base + sum_j coef_j X_j, j < n <= 4 (device
+/* RK stage combination out = base + sum_j coef_j X_j, j < n <= 6 (device
  * arrays of crkdg_state_bytes each, FP64 layout only). */
 int crkdg_combine(crkdg_state* st, void* out_dev, const void* base_dev, int n,
                   const double* coef, const void* const* X_dev);

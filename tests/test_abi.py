@@ -250,3 +250,16 @@ def test_burgers_initial_data_needs_burgers():
     assert L.crkdg_error(h, K.IC_BURGERS_SIN, None, 0, 0.0, 0, out) == K.CRKDG_EINVAL
     assert L.crkdg_project(h, 8, None, 0, None) == K.CRKDG_EINVAL
     L.crkdg_destroy(h)
+
+
+def test_combine_argument_checks():
+    """at most six arrays (the largest tableau); checked before device work"""
+    L = K.lib()
+    rc, h = _create()
+    assert L.crkdg_bind(h, C.c_void_p(0x100000), C.c_void_p(0x200000), None) == 0
+    coef = (C.c_double * 7)(*([0.5] * 7))
+    X = (C.c_void_p * 7)(*([0x300000] * 7))
+    assert L.crkdg_combine(h, C.c_void_p(0x400000), None, 7, coef, X) == K.CRKDG_EINVAL
+    assert L.crkdg_combine(h, C.c_void_p(0x400000), None, -1, coef, X) == K.CRKDG_EINVAL
+    assert L.crkdg_combine(h, None, None, 1, coef, X) == K.CRKDG_EINVAL
+    L.crkdg_destroy(h)
