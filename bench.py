@@ -412,8 +412,9 @@ def main():
              ("fp32-inner + TVB", K.FP32_INNER, None)]
     plan += [("fp32-increments + MLP", K.FP32_INCREMENTS, mlp)] if mlp is not None else []
     plan += [("fp32-increments + TVB", K.FP32_INCREMENTS, None)]
+    head_name = "fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"
     for name, prec, ind in plan:
-        forms[name] = run_form(K, W, args, prec, ind)
+        forms[name] = run_form(K, W, args, prec, ind, repeats=4 if name == head_name else 0)
         log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
     rk = None
     if not args.no_rkdg:
@@ -441,6 +442,9 @@ def main():
                            "fp32-bulk + TVB (profiling run without the learned indicator)",
                    "cells": head["cells"], "dofs": head["dofs"], "parallelism": "1 GPU"},
         "roofline": head["roofline"],
+        "repeats_ms_per_step": {"first": head["ms_per_step"], "more": head["repeat_ms_per_step"],
+                                "median_of_5": float(np.median([head["ms_per_step"]] +
+                                                               head["repeat_ms_per_step"]))},
         "stream_copy_GBs": copy_gbs,
         "frac_of_stream_copy": round(head["roofline"]["achieved"] / copy_gbs, 4),
         "kernels": head["kernels"],
@@ -502,7 +506,10 @@ def measured_traffic(kernel, precision_tag):
     return float(d["traffic_bytes_per_launch"])
 
 
-def run_form(K, W, args, precision, mlp=None, scheme="crkdg"):
+def run_form(K, W, args, precision, mlp=None, scheme="crkdg", repeats=0):
+    """warm-up, then exactly args.steps timed steps (the reported rate);
+    `repeats` further timed regions of args.steps steps each, continuing the
+    same run, give the run-to-run spread (reported beside, not in, the rate)"""
     import torch
     s, cfg, params, xi = make_solver(K, W, args.scale, precision)
     stream = s.stream
@@ -539,6 +546,17 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     prof = s.crkdg_profile_end()
+    rep_ms = []
+    for _ in range(repeats):
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            r0.record(stream)
+            for _ in range(args.steps):
+                step()
+            r1.record(stream)
+        torch.cuda.synchronize()
+        rep_ms.append(r0.elapsed_time(r1) / args.steps)
     n_flag = s.crkdg_limit(M, None, count=True)  # raises if a cell average went non-physical
 
     dofs = s.ncells * s.nmodes * s.ncomp
@@ -561,6 +579,7 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg"):
     if traffic is not None:
         roof["traffic_over_algorithmic"] = round(traffic / by, 3)
     return {"value": dofs * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
+            "repeat_ms_per_step": rep_ms,
             "roofline": roof, "kernels": kern, "flagged_cells_end": n_flag,
             "cells": s.ncells, "dofs": dofs, "nx": cfg["nx"], "ny": cfg["ny"]}
 
