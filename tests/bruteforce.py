@@ -62,6 +62,8 @@ class Problem:
     def flux(self, q, d):
         if self.equation == "advection":
             return self.adv[d] * q
+        if self.equation == "burgers":
+            return 0.5 * q * q
         return euler_flux(q, d, self.dim)
 
     def speed(self, q, d):
@@ -70,7 +72,14 @@ class Problem:
         return euler_speed(q, d, self.dim)
 
     def lf(self, qL, qR, d):
-        """flux across a face in the +e_d direction, left/right traces"""
+        """flux across a face in the +e_d direction, left/right traces:
+        Lax--Friedrichs, or for Burgers the flux of the exact Riemann
+        solution sampled at the face (a shock moving at (qL + qR)/2 when
+        qL > qR, else a rarefaction fan u = x/t clipped to [qL, qR])"""
+        if self.equation == "burgers":
+            shock = qL > qR
+            u0 = np.where(shock, np.where(qL + qR > 0, qL, qR), np.clip(0.0, qL, qR))
+            return 0.5 * u0 * u0
         a = np.maximum(self.speed(qL, d), self.speed(qR, d))
         return 0.5 * (self.flux(qL, d) + self.flux(qR, d) - a * (qR - qL))
 

@@ -179,3 +179,21 @@ def test_burgers_table_rkdg(k):
     assert np.all(np.abs(orders - (k + 1)) < 0.15), orders
     c = [_run(N, k, "crkdg") for N in g["N"][:3]]
     assert all(ci < ei for ci, ei in zip(c, e))
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_burgers_operators_match_dense_brute_force(k, bc):
+    """both operators against the dense brute force of tests/bruteforce.py
+    (full mass matrix, numpy Legendre and Gauss tables, the Godunov flux as
+    the sampled Riemann solution) on random states of both signs"""
+    from tests import bruteforce as BF
+    N, L = 7, 1.3
+    m = O.Mesh(1, N, x0=0.0, x1=L, bc=(0 if bc == "periodic" else 1,) * 2 + (0, 0),
+               equation=O.EQ_BURGERS, flux=O.FLUX_GODUNOV)
+    prob = BF.Problem(1, N, 1, k, L, 1.0, "burgers", bc=bc)
+    u = np.random.default_rng(50 + k).standard_normal(m.shape(k))
+    for op, name in ((O.OP_LOC, "loc"), (O.OP_DG, "dg")):
+        a = O.apply(m, k, op, u)
+        b = BF.apply(prob, u, name)
+        assert np.abs(a - b).max() <= 1e-12 * (1 + np.abs(b).max()), name

@@ -142,7 +142,7 @@ def _random_euler_state(rng, shape, dim):
     return u
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("dim", [1, 2])
 @pytest.mark.parametrize("equation", ["advection", "euler"])
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
