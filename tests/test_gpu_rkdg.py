@@ -233,3 +233,24 @@ def test_2d_inflow_cartesian_analogue(K):
     assert abs(np.log2(c[1][2] / c[2][2]) - 4.0) < 0.2
     assert np.log2(r[1][2] / r[2][2]) < 2.6
     assert c[2][2] < 0.2 * r[2][2]
+
+
+def test_butcher_form_device_dt_with_inflow_equals_host_dt(K):
+    """order 0 with dt in device memory and time-dependent inflow data (the
+    step's time then lives on the device): the same bits as host dt"""
+    import torch
+    N, k = 60, 3
+    L = 4 * np.pi
+    lm = K.make_mesh(1, N, 1, x0=0.0, x1=L, bc=(2, 1, 0, 0), adv=(1.0, 0.0),
+                     bc_exact=K.IC_ADV_SIN, equation=K.EQ_ADVECTION)
+    s1 = K.Solver(lm, k, K.FLUX_UPWIND, 4)
+    s2 = K.Solver(lm, k, K.FLUX_UPWIND, 4)
+    s1.crkdg_project(K.IC_ADV_SIN)
+    s2.crkdg_project(K.IC_ADV_SIN)
+    dt = 0.05 * L / N
+    d = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    for _ in range(12):
+        s1.crkdg_step_rkdg(0, dt)
+        s2.crkdg_step_rkdg(0, 0.0, dt_tensor=d)
+    assert np.array_equal(s1.crkdg_get_state(), s2.crkdg_get_state())
+    assert s2.crkdg_get_time() == pytest.approx(s1.crkdg_get_time(), rel=1e-14)
