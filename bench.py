@@ -421,9 +421,11 @@ def main():
         rk = run_form(K, W, args, K.FP64, None, scheme="rkdg3")
         log(f"fp64 RKDG SSP3 + TVB every stage: {rk['ms_per_step']:.3f} ms/step")
     head = forms["fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"]
-    copy_gbs = round(stream_copy_gbs(), 1)
-    log(f"stream copy: {copy_gbs} GB/s; the dominant kernel at "
-        f"{head['roofline']['achieved'] / copy_gbs:.3f} of it")
+    # (not in counter runs: their one large copy is the traffic calibration)
+    copy_gbs = None if args.calibrate_copy else round(stream_copy_gbs(), 1)
+    if copy_gbs:
+        log(f"stream copy: {copy_gbs} GB/s; the dominant kernel at "
+            f"{head['roofline']['achieved'] / copy_gbs:.3f} of it")
     plain = forms["fp64 + TVB"]
     tvb32 = forms["fp32-bulk + TVB"]
     out = {
@@ -446,7 +448,7 @@ def main():
                                 "median_of_5": float(np.median([head["ms_per_step"]] +
                                                                head["repeat_ms_per_step"]))},
         "stream_copy_GBs": copy_gbs,
-        "frac_of_stream_copy": round(head["roofline"]["achieved"] / copy_gbs, 4),
+        "frac_of_stream_copy": round(head["roofline"]["achieved"] / copy_gbs, 4) if copy_gbs else None,
         "kernels": head["kernels"],
         "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"],
                        "roofline": plain["roofline"], "kernels": plain["kernels"]},

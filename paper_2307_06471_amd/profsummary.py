@@ -72,6 +72,10 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, out, command):
         kib = sum(kern) / len(kern)
         res[name] = {"kib_per_dispatch": kib, "dispatches": len(kern), "copy_kib": kib_copy,
                      "factor": factor, "bytes_per_launch": kib * 1024.0 * factor}
+    # WRITE_SIZE counts a copy's written bytes exactly on this hardware: a
+    # factor far from 1 means the largest copy is not the calibration copy
+    if abs(res["write"]["factor"] - 1.0) > 0.1:
+        raise SystemExit(f"calibration copy mismatch: write factor {res['write']['factor']:.3f}")
     lines = [f"# HBM traffic per launch of {kernel}", "",
              "commands (repo root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):",
              f"  {command}", "",

@@ -93,6 +93,25 @@ def test_combine(K):
     assert rel_err(out, ref) < 1e-15
 
 
+def test_combine_odd_length_and_many_arrays(K):
+    """an odd number of doubles (the last one takes the scalar tail path),
+    up to six arrays, with and without a base, on a mesh whose vector count
+    is not a multiple of the two vectors each thread handles per pass"""
+    import torch
+    om, lm = meshes(K, 1, 257, 1, "advection", flux="upwind")
+    s = solver(K, lm, 0, "upwind")
+    rng = np.random.default_rng(1)
+    arrs = [rng.standard_normal(om.shape(0)) for _ in range(7)]
+    assert arrs[0].size % 2 == 1
+    t = [torch.from_numpy(a).cuda() for a in arrs]
+    coefs = [0.3, -1.25, 2.0, 1e-3, -0.7, 0.25]
+    out = s.crkdg_combine(t[0], coefs, t[1:]).cpu().numpy()
+    ref = arrs[0] + sum(c * a for c, a in zip(coefs, arrs[1:]))
+    assert rel_err(out, ref) < 1e-15
+    out = s.crkdg_combine(None, coefs[:1], t[1:2]).cpu().numpy()
+    assert rel_err(out, coefs[0] * arrs[1]) < 1e-15
+
+
 TABS = ["fe", "eq2", "eq3", "rk4", "ssp3"]
 
 
