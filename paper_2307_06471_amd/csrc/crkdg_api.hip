@@ -969,7 +969,9 @@ int crkdg_profile_begin(crkdg_state* st, int max_launches) {
     const size_t old = st->ev.size();
     st->ev.resize(2 * (size_t)max_launches);
     for (size_t e = old; e < st->ev.size(); ++e)
-      if (hipEventCreate(&st->ev[e]) != hipSuccess) {
+      // timing-only events: no system-scope fence (and cache writeback) at
+      // each record; profile_end synchronises the stream before reading them
+      if (hipEventCreateWithFlags(&st->ev[e], hipEventDisableSystemFence) != hipSuccess) {
         st->ev.resize(e);
         return CRKDG_EHIP;
       }
