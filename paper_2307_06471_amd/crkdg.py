@@ -196,6 +196,10 @@ class Solver:
 
     # -- the C entry points ---------------------------------------------
     def crkdg_set_tableau(self, A, b, c):
+        """explicit Butcher tableau (A strictly lower triangular).  The
+        Solver binds its workspace at construction for max(4, stages)
+        stages, so a five- or six-stage tableau needs a Solver created with
+        rk_stages = RK_FEHLBERG5 (CRKDG_EINVAL otherwise)"""
         A = np.ascontiguousarray(A, dtype=np.float64)
         b = np.ascontiguousarray(b, dtype=np.float64)
         c = np.ascontiguousarray(c, dtype=np.float64)
