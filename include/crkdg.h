@@ -116,7 +116,8 @@ typedef struct {
   int equation;             /* CRKDG_EQ_* */
   double adv[2];            /* advection velocity */
   double gamma;             /* ratio of specific heats (Euler) */
-  int precision;            /* CRKDG_FP64 | CRKDG_FP32_MIXED | CRKDG_FP32_INNER */
+  int precision;            /* CRKDG_FP64 | CRKDG_FP32_MIXED | CRKDG_FP32_INNER |
+                               CRKDG_FP32_INCREMENTS */
 } crkdg_mesh;
 
 typedef struct crkdg_state crkdg_state;
@@ -268,7 +269,14 @@ int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int s
 
 /* L1, L2 (unnormalised integrals over the domain) and Linf errors of
  * component comp against exact solution ic at time t, (k+3)^dim Gauss points
- * per cell; out on host (syncs).  Deterministic two-pass reduction. */
+ * per cell; out on host (syncs).  Deterministic two-pass reduction.  The
+ * error tables of Section 4 (Tables 'table:boundary_treatment',
+ * 'table:euler accuracy', 'table:2deuler-periodic-rectangle') report these
+ * norms; the paper does not define them, and the unnormalised integral is
+ * the reading under which its printed L2 exceeds its Linf on (0, 4 pi).
+ * params: the initial-condition parameters of ic (nparams of them, as for
+ * crkdg_project).  CRKDG_EINVAL for an unknown ic or a component out of
+ * range, CRKDG_EUNBOUND before crkdg_bind. */
 int crkdg_error(crkdg_state* st, int ic, const double* params, int nparams, double t,
                 int comp, double out_l1_l2_linf[3]);
 /* L1, L2 (unnormalised, |K|-weighted sums) and Linf errors of the cell
