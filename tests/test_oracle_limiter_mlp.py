@@ -243,3 +243,146 @@ def test_mlp_infer_matches_forward_within_bf16():
     # the logit scale at most
     assert np.abs(zin - z64).max() < 0.05 * max(1.0, np.abs(z64).max())
     assert np.abs(zin - z64).max() > 0.0  # the rounding is really applied
+
+
+def test_forced_reconstruction_returns_the_p1_slopes():
+    """positivity forces the limited P1 reconstruction on a cell whose slopes
+    no field limits (huge M): mapping the characteristic slopes back must
+    give the conserved slopes unchanged (R L s = s for any s), and every
+    other mode, including (1,1), is zeroed; the mean is kept"""
+    mesh = quad_mesh(4, bc=1)
+    k = 2
+    u = O.project(mesh, k, O.IC_CONST, [1.0, 0.3, -0.2, 2.5])
+    cell = 5
+    sx = np.array([0.1, 0.05, -0.03, 0.2])    # mode (1,0) of the four components
+    sy = np.array([-0.08, 0.02, 0.04, -0.1])  # mode (0,1)
+    u[:, 1, cell] = sx
+    u[:, 3, cell] = sy
+    u[0, 4, cell] = 1.5                       # density mode (1,1): rho < 0 at corners
+    u[3, 8, cell] = 0.05                      # energy mode (2,2)
+    v, flags, _ = O.limit_tvb(mesh, k, 1e12, u)
+    assert flags[cell] == 2                   # forced by the point test, not by TVB
+    assert np.abs(v[:, 1, cell] - sx).max() <= 1e-14
+    assert np.abs(v[:, 3, cell] - sy).max() <= 1e-14
+    assert np.all(v[:, [2, 4, 5, 6, 7, 8], cell] == 0.0)
+    assert np.array_equal(v[:, 0], u[:, 0])
+
+
+def _fd_jacobian(q, d):
+    J = np.zeros((4, 4))
+    eps = 1e-6
+    for j in range(4):
+        e = np.zeros(4)
+        e[j] = eps
+        J[:, j] = (BF.euler_flux(q + e, d, 2) - BF.euler_flux(q - e, d, 2)) / (2 * eps)
+    return J
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_one_limited_characteristic_field_matches_numpy_eigenvectors(d):
+    """the middle cell of a 3-cell row (column for d = 1), P1 slope s and
+    neighbour differences D+ and D- built in the eigenvector basis of the
+    flux Jacobian (numpy's eig of central differences of an independently
+    written flux, not the oracle's eigenvectors): the u - c field has
+    coefficients (1, 0.2, 0.5), so minmod limits it to 0.2; the u + c field
+    (0.3, 1, 0.8) keeps 0.3; in the double eigenvalue u's eigenspace D+ and
+    D- are 2 s, so that part of s is kept in every basis of the eigenspace.
+    With M = 0 the limited slope is independent of how the eigenvectors
+    are scaled: it must be s - 0.8 (0.02 r_{u-c})."""
+    qb = np.array([1.3, 0.4, -0.5, 3.7])
+    J = _fd_jacobian(qb, d)
+    lam, V = np.linalg.eig(J)
+    assert np.abs(lam.imag).max() < 1e-9
+    lam, V = lam.real, V.real
+    order = np.argsort(lam)
+    lam, V = lam[order], V[:, order]
+    un = qb[1 + d] / qb[0]
+    p = 0.4 * (qb[3] - 0.5 * (qb[1] ** 2 + qb[2] ** 2) / qb[0])
+    c = np.sqrt(1.4 * p / qb[0])
+    assert np.allclose(lam, [un - c, un, un, un + c], atol=1e-8)
+    r1, r2, r3, r4 = (V[:, i] for i in range(4))
+    a = 0.02
+    su = a * (0.1 * r2 - 0.05 * r3)          # the part of s in u's eigenspace
+    s = a * 1.0 * r1 + su + a * 0.3 * r4
+    dp = a * 0.2 * r1 + 2 * su + a * 1.0 * r4
+    dm = a * 0.5 * r1 + 2 * su + a * 0.8 * r4
+    expect = s - a * 0.8 * r1
+    k = 2
+    n = 3
+    mesh = O.Mesh(2, n if d == 0 else 1, 1 if d == 0 else n, x0=0, x1=n if d == 0 else 1,
+                  y0=0, y1=1 if d == 0 else n, bc=(1, 1, 1, 1), equation=O.EQ_EULER,
+                  flux=O.FLUX_LLF)
+    u = np.zeros((4, 9, 3))
+    u[:, 0, 0] = qb - dm
+    u[:, 0, 1] = qb
+    u[:, 0, 2] = qb + dp
+    slope = 1 if d == 0 else 3               # mode (1,0) or (0,1)
+    u[:, slope, 1] = s
+    u[:, 4, 1] = 0.01                         # mode (1,1): zeroed in a limited cell
+    v, flags, _ = O.limit_tvb(mesh, k, 0.0, u)
+    assert flags[1] == 1
+    assert np.abs(v[:, slope, 1] - expect).max() <= 1e-7 * np.abs(expect).max()
+    other = [b for b in range(1, 9) if b != slope]
+    assert np.all(v[:, other, 1] == 0.0)
+    assert np.array_equal(v[:, 0, 1], qb)
+    # the limited field really moved: the unlimited slope is far from it
+    assert np.abs(s - expect).max() > 1e-3
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_features_of_polynomial_data_in_closed_form(k):
+    """a density varying as x^2 (k = 2) or x^3 (k = 3) along x and an energy
+    varying as y^2 / y^3 along y, each represented exactly on every cell:
+    the trace jumps, neighbour differences and the 12 features follow from
+    point values and cell averages of the polynomials (written out here),
+    not from the modal coefficients"""
+    n, M = 6, 50.0
+    h = 1.0 / n
+    mesh = O.Mesh(2, n, n, x0=0, x1=1, y0=0, y1=1, bc=(1, 1, 1, 1), equation=O.EQ_EULER,
+                  flux=O.FLUX_LLF)
+    Q = k + 1
+    # Legendre coefficients on a cell of centre xc, width h of q(x) = x^k:
+    # substitute x = xc + (h/2) xi and expand xi^2 = (P0 + 2 P2)/3,
+    # xi^3 = (3 P1 + 2 P3)/5
+    def coeffs(xc):
+        g = h / 2
+        if k == 2:
+            return [xc * xc + g * g / 3, 2 * xc * g, 2 * g * g / 3]
+        return [xc ** 3 + xc * g * g, 3 * xc * xc * g + 3 * g ** 3 / 5, 2 * xc * g * g, 2 * g ** 3 / 5]
+
+    def avg(xc):  # exact cell average of x^k
+        a, b = xc - h / 2, xc + h / 2
+        return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * h)
+
+    u = np.zeros((4, Q * Q, n * n))
+    for j in range(n):
+        for i in range(n):
+            cell = j * n + i
+            xc, yc = (i + 0.5) * h, (j + 0.5) * h
+            cx, cy = coeffs(xc), coeffs(yc)
+            u[0, 0, cell] = 2.0 + cx[0]
+            u[3, 0, cell] = 3.0 + cy[0]
+            for m in range(1, Q):
+                u[0, m, cell] = cx[m]          # density modes (m, 0)
+                u[3, m * Q, cell] = cy[m]      # energy modes (0, m)
+    assert np.allclose(u[0, 0], 2.0 + np.tile([avg((i + 0.5) * h) for i in range(n)], n),
+                       rtol=0, atol=1e-15)
+    X = O.mlp_features(mesh, k, M, u)
+    f = lambda x: x ** k
+    for j in range(1, n - 1):
+        for i in range(1, n - 1):
+            cell = j * n + i
+            want = np.zeros(12)
+            for qi, (coord, along) in enumerate((((i + 0.5) * h, 0), ((j + 0.5) * h, 1))):
+                c = coord
+                fwd = f(c + h / 2) - avg(c)     # forward face value minus the average
+                bwd = avg(c) - f(c - h / 2)     # the average minus the backward face value
+                dp = avg(c + h) - avg(c)
+                dm = avg(c) - avg(c - h)
+                s = abs(dp) + abs(dm) + M * h * h + 1e-300
+                # direction `along` varies; the other direction sees constants
+                want[(qi * 2 + along) * 3:(qi * 2 + along) * 3 + 3] = [fwd / s, bwd / s,
+                                                                       (dp - dm) / s]
+            assert np.allclose(X[cell], want, rtol=1e-12, atol=1e-14), (i, j, X[cell], want)
+    # the backward and forward jumps really differ here (an even-degree term)
+    assert np.abs(X[:, 0] - X[:, 1]).max() > 1e-4
