@@ -266,6 +266,21 @@ int crkdg_mlp_grad(const float* params, const float* X, const uint8_t* y, int B,
                    void* stream);
 int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int step, float lr,
                    float beta1, float beta2, float eps, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): crkdg_mlp_grad
+ * without the work argument.  The same kernels and reduction order, so the
+ * result is bit-identical to crkdg_mlp_grad's.  The workgroup partials live
+ * in a library-owned device array of CRKDG_MLP_NOALLOC_MAX_B / 64 x 1506
+ * floats (1.5 MB), one per GPU, held until the process ends; this call
+ * allocates nothing (no hipMalloc, no allocating library routine).  The
+ * first call on a device looks up that device's copy of the array.  Every
+ * call on one GPU shares its array: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.
+ * CRKDG_EINVAL for B < 1, B > CRKDG_MLP_NOALLOC_MAX_B, a null pointer or a
+ * non-positive pos_weight; CRKDG_EHIP if the device lookup fails. */
+#define CRKDG_MLP_NOALLOC_MAX_B 16384
+int crkdg_mlp_grad_noalloc(const float* params, const float* X, const uint8_t* y, int B,
+                           float pos_weight, float* grad, float* loss, void* stream);
 
 /* L1, L2 (unnormalised integrals over the domain) and Linf errors of
  * component comp against exact solution ic at time t, (k+3)^dim Gauss points

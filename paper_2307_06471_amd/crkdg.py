@@ -83,6 +83,7 @@ def _sig():
         "crkdg_mlp_work_bytes": (sz, [C.c_int]),
         "crkdg_mlp_forward": (C.c_int, [vp, vp, C.c_int, vp, vp]),
         "crkdg_mlp_grad": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, vp, vp, vp, sz, vp]),
+        "crkdg_mlp_grad_noalloc": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, vp, vp, vp]),
         "crkdg_mlp_adam": (C.c_int, [vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float,
                                      C.c_float, vp]),
         "crkdg_profile_begin": (C.c_int, [vp, C.c_int]),
@@ -381,6 +382,18 @@ def crkdg_mlp_grad(params, X, y, pos_weight, grad=None, loss=None, work=None, st
         work = torch.empty(nb, dtype=torch.uint8, device=X.device)
     _check(lib().crkdg_mlp_grad(_ptr(params), _ptr(X), _ptr(y), B, float(pos_weight), _ptr(grad),
                                 _ptr(loss), _ptr(work), nb, _stream(stream)), "crkdg_mlp_grad")
+    return grad, loss
+
+
+MLP_NOALLOC_MAX_B = 16384  # CRKDG_MLP_NOALLOC_MAX_B
+
+
+def crkdg_mlp_grad_noalloc(params, X, y, pos_weight, grad, loss, stream=None):
+    """crkdg_mlp_grad with the library's own per-GPU partials buffer (no work
+    memory); grad (1505 floats) and loss (1 float) are caller-owned"""
+    _check(lib().crkdg_mlp_grad_noalloc(_ptr(params), _ptr(X), _ptr(y), X.shape[0],
+                                        float(pos_weight), _ptr(grad), _ptr(loss),
+                                        _stream(stream)), "crkdg_mlp_grad_noalloc")
     return grad, loss
 
 

@@ -845,6 +845,15 @@ int crkdg_mlp_grad(const float* params, const float* X, const uint8_t* y, int B,
                                 (hipStream_t)stream));
 }
 
+int crkdg_mlp_grad_noalloc(const float* params, const float* X, const uint8_t* y, int B,
+                           float pos_weight, float* grad, float* loss, void* stream) {
+  if (!params || !X || !y || !grad || B < 1 || !isfinite(pos_weight) || pos_weight <= 0)
+    return CRKDG_EINVAL;
+  if (B > mlp_noalloc_max_batch()) return CRKDG_EINVAL;
+  return hip_rc(launch_mlp_grad_noalloc(params, X, y, B, pos_weight, grad, loss,
+                                        (hipStream_t)stream));
+}
+
 int crkdg_mlp_adam(float* params, float* m1, float* m2, const float* grad, int step, float lr,
                    float beta1, float beta2, float eps, void* stream) {
   if (!params || !m1 || !m2 || !grad || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||

@@ -161,6 +161,9 @@ hipError_t launch_mlp_grad(const float* P, const float* X, const uint8_t* y, int
 hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, int step, float lr,
                            float b1, float b2, float eps, hipStream_t s);
 size_t mlp_work_floats(int B);
+hipError_t launch_mlp_grad_noalloc(const float* P, const float* X, const uint8_t* y, int B,
+                                   float pw, float* grad, float* loss, hipStream_t s);
+int mlp_noalloc_max_batch();
 
 constexpr int RED_BLOCKS = 1024;  // blocks of the first reduction pass
 

@@ -15,6 +15,8 @@
 // logits, pw * y * softplus(-z) + (1 - y) * softplus(z).
 #include <math.h>
 
+#include <mutex>
+
 #include "crkdg_internal.hpp"
 #include "mlp_core.hpp"
 
@@ -163,6 +165,54 @@ hipError_t launch_mlp_grad(const float* P, const float* X, const uint8_t* y, int
   hipLaunchKernelGGL(k_mlp_grad_final, dim3((NPART + 255) / 256), dim3(256), 0, s, work, nblk, B,
                      grad, loss);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The gradient without caller work memory: the workgroup partials live in a
+// file-scope device array (one copy per GPU, held until the process ends)
+// sized for batches of up to MLP_NOALLOC_MAX_B samples.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); each device's address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and the kernels get that.
+// ---------------------------------------------------------------------------
+constexpr int MLP_NOALLOC_MAX_B = 16384;
+constexpr size_t MLP_NOALLOC_FLOATS = (size_t)((MLP_NOALLOC_MAX_B + MB - 1) / MB) * NPART;
+static __device__ __align__(256) float scratch[MLP_NOALLOC_FLOATS];
+
+constexpr int MLP_NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[MLP_NOALLOC_MAX_DEVICES];
+
+// this device's address of `scratch` (resolved on the first call per device)
+static hipError_t noalloc_scratch(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MLP_NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+int mlp_noalloc_max_batch() { return MLP_NOALLOC_MAX_B; }
+
+// the same two kernels as launch_mlp_grad, partials in `scratch` (every
+// partial a later read uses is written first in stream order, so nothing
+// needs clearing)
+hipError_t launch_mlp_grad_noalloc(const float* P, const float* X, const uint8_t* y, int B,
+                                   float pw, float* grad, float* loss, hipStream_t s) {
+  if (B < 1 || B > MLP_NOALLOC_MAX_B) return hipErrorInvalidValue;
+  float* work = nullptr;
+  hipError_t e = noalloc_scratch(&work);
+  if (e != hipSuccess) return e;
+  return launch_mlp_grad(P, X, y, B, pw, grad, loss, work, s);
 }
 
 hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, int step, float lr,

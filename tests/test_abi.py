@@ -263,3 +263,17 @@ def test_combine_argument_checks():
     assert L.crkdg_combine(h, C.c_void_p(0x400000), None, -1, coef, X) == K.CRKDG_EINVAL
     assert L.crkdg_combine(h, None, None, 1, coef, X) == K.CRKDG_EINVAL
     L.crkdg_destroy(h)
+
+
+def test_noalloc_gradient_argument_checks():
+    """crkdg_mlp_grad_noalloc refuses batches beyond its fixed buffer and bad
+    arguments before any device work (no GPU needed)"""
+    L = K.lib()
+    fake = C.c_void_p(0x1000)
+    assert K.MLP_NOALLOC_MAX_B == 16384
+    big = K.MLP_NOALLOC_MAX_B + 1
+    assert L.crkdg_mlp_grad_noalloc(fake, fake, fake, big, 1.0, fake, None, None) == K.CRKDG_EINVAL
+    assert L.crkdg_mlp_grad_noalloc(fake, fake, fake, 0, 1.0, fake, None, None) == K.CRKDG_EINVAL
+    assert L.crkdg_mlp_grad_noalloc(fake, fake, fake, 64, 0.0, fake, None, None) == K.CRKDG_EINVAL
+    assert L.crkdg_mlp_grad_noalloc(None, fake, fake, 64, 1.0, fake, None, None) == K.CRKDG_EINVAL
+
