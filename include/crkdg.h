@@ -184,6 +184,32 @@ int crkdg_step(crkdg_state* st, double dt);
  * advanced time, and crkdg_get_time reads it back (syncs). */
 int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
 
+/* Schedule of crkdg_step / crkdg_step_dev.  The compact stencil of Section
+ * 3.1 (a step reaches only the face neighbours of a cell, for any number of
+ * stages, because the inner stages are element local) lets one kernel do
+ * the whole step on a tile plus a one-cell ring: read u^n once, recompute
+ * the ring's inner stages, evaluate the tile's faces, write u^{n+1}; no
+ * stage state goes through memory.
+ *   CRKDG_SCHED_SPLIT  inner-stage pass, then final-stage pass (any case);
+ *   CRKDG_SCHED_FUSED  the one-pass step, for 2D Euler in the FP32-bulk
+ *                      form with k = 1 or 2, constant boundary data
+ *                      (periodic, transmissive, time-independent Dirichlet)
+ *                      and a subdiagonal tableau whose weights are nonzero
+ *                      only on the first and last stages (schemes (eq:2),
+ *                      (eq:3), forward Euler).
+ * The results of the two schedules agree to the rounding of FP32 arithmetic
+ * (the fused step applies each stage's face fluxes separately).
+ * crkdg_set_schedule returns CRKDG_EUNSUPPORTED for CRKDG_SCHED_FUSED on a
+ * handle that does not meet these conditions, CRKDG_EINVAL for an unknown
+ * value.  crkdg_get_schedule returns the schedule the next step takes (a
+ * later crkdg_set_tableau can make a fused handle fall back to the split
+ * schedule).  New handles start with CRKDG_SCHED_FUSED_DEFAULT. */
+#define CRKDG_SCHED_SPLIT 0
+#define CRKDG_SCHED_FUSED 1
+#define CRKDG_SCHED_FUSED_DEFAULT CRKDG_SCHED_SPLIT
+int crkdg_set_schedule(crkdg_state* st, int sched);
+int crkdg_get_schedule(const crkdg_state* st);
+
 /* One step of the original RKDG method that the paper compares against
  * (Section 2.1, equation (rkdg)), in the Shu--Osher SSP form of order 2 or 3
  * (Section 3.2.1 gives the order-2 form): every stage applies the DG
@@ -227,9 +253,9 @@ int crkdg_limit(crkdg_state* st, double M, uint8_t* flags_dev, int64_t* n_flagge
  * same final-stage limiter, with the TVB troubled-cell test replaced by a
  * 12 -> 32 -> 32 -> 1 perceptron (ReLU, ReLU, logistic output; parameters
  * packed W1[32][12], b1[32], W2[32][32], b2[32], w3[32], b3 as 1505 device
- * floats) on 12 stencil features, evaluated at inference precision: the
- * features, W1, W2 and the first hidden layer rounded to bfloat16 (nearest
- * even) on the matrix cores with FP32 accumulation, the rest FP32.
+ * floats) on 12 stencil features (computed in FP64, rounded to FP32),
+ * evaluated in FP32: both hidden layers on the FP32 matrix cores, the output
+ * layer on the vector units.
  * p = sigmoid(logit): p >= tau_hi troubled, p <= tau_lo smooth, otherwise
  * the FP64 TVB test decides (flag bit 8); tau_lo <= tau_hi.
  * Reconstruction and positivity check as in crkdg_limit.  counts_host
@@ -253,7 +279,7 @@ int crkdg_limit_dt(crkdg_state* st, double M, const float* params_dev, float tau
  * a/s, at/s, (dp - dm)/s.  2D Euler only. */
 int crkdg_mlp_features(crkdg_state* st, double M, float* X_dev);
 /* MLP kernels on device arrays (stream = hipStream_t or NULL):
- * forward logits of B samples X[B][12] at the limiter's inference precision;
+ * forward logits of B samples X[B][12] by the limiter's FP32 inference;
  * the batch-mean weighted BCE loss (FP32 forward and backward)
  * pos_weight*y*softplus(-z) + (1-y)*softplus(z) and its gradient (1505
  * floats; loss: 1 device float or NULL) with a deterministic two-level
@@ -320,8 +346,8 @@ int crkdg_combine(crkdg_state* st, void* out_dev, const void* base_dev, int n,
  * kernel launch (at most max_launches) until crkdg_profile_end, which syncs
  * and returns the summed milliseconds and launch counts per kernel class:
  * 0 inner stages, 1 final stage, 2 local operator, 3 stage combination,
- * 4 dt reduction, 5 limiter, 6 other.  Host-side events only; no device
- * memory is allocated. */
+ * 4 dt reduction, 5 limiter, 6 other, 7 fused step.  Host-side events only;
+ * no device memory is allocated. */
 int crkdg_profile_begin(crkdg_state* st, int max_launches);
 int crkdg_profile_end(crkdg_state* st, double ms[8], int64_t counts[8]);
 

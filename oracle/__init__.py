@@ -71,8 +71,6 @@ def lib():
             "or_total_mass": (C.c_double, [mp, C.c_int, dp, C.c_int]),
             "or_mlp_features": (C.c_int, [mp, C.c_int, C.c_double, dp, dp]),
             "or_mlp_forward": (C.c_int, [dp, dp, C.c_int, dp]),
-            "or_mlp_infer": (C.c_int, [dp, dp, C.c_int, dp]),
-            "or_bf16": (C.c_float, [C.c_float]),
             "or_mlp_loss_grad": (C.c_double, [dp, dp, u8, C.c_int, C.c_double, dp]),
             "or_adam": (C.c_int, [dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_double]),
@@ -313,20 +311,6 @@ def mlp_forward(params, X):
     out = np.zeros(X.shape[0])
     lib().or_mlp_forward(_d(params), _d(X), X.shape[0], _d(out))
     return out
-
-
-def mlp_infer(params, X):
-    """logits at inference precision (bfloat16 features, weights and first
-    hidden layer; see or_mlp_infer)"""
-    params = np.ascontiguousarray(params, dtype=np.float64)
-    X = np.ascontiguousarray(X, dtype=np.float64)
-    out = np.zeros(X.shape[0])
-    lib().or_mlp_infer(_d(params), _d(X), X.shape[0], _d(out))
-    return out
-
-
-def bf16(f):
-    return lib().or_bf16(float(f))
 
 
 def mlp_loss_grad(params, X, y, pos_weight=1.0):

@@ -1171,47 +1171,6 @@ int or_mlp_forward(const double* params, const double* X, int B, double* logits)
   return 0;
 }
 
-/* round a binary32 value to bfloat16 (8 significand bits), round to nearest,
- * ties to even, on the bit pattern; NaN stays NaN */
-float or_bf16(float f) {
-  uint32_t b;
-  memcpy(&b, &f, 4);
-  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return f;
-  const uint32_t lsb = (b >> 16) & 1u;
-  b += 0x7fffu + lsb;
-  b &= 0xffff0000u;
-  float r;
-  memcpy(&r, &b, 4);
-  return r;
-}
-
-/* the forward pass at inference precision: features, W1, W2 and the first
- * hidden layer rounded to bfloat16 (each sum of exact products then rounded
- * to binary32 before the bias is added, as a binary32 accumulator holds it);
- * second hidden layer, w3 and the output in binary64 */
-int or_mlp_infer(const double* P, const double* X, int B, double* logits) {
-  for (int n = 0; n < B; ++n) {
-    const double* x = X + (size_t)n * NF;
-    double xb[NF], h1[H1], h2[H2];
-    for (int i = 0; i < NF; ++i) xb[i] = or_bf16((float)x[i]);
-    for (int o = 0; o < H1; ++o) {
-      double s = 0.0;
-      for (int i = 0; i < NF; ++i) s += (double)or_bf16((float)P[OW1 + o * NF + i]) * xb[i];
-      const float v = (float)s + (float)P[OB1 + o];
-      h1[o] = or_bf16(v > 0.0f ? v : 0.0f);
-    }
-    for (int o = 0; o < H2; ++o) {
-      double s = 0.0;
-      for (int i = 0; i < H1; ++i) s += (double)or_bf16((float)P[OW2 + o * H1 + i]) * h1[i];
-      h2[o] = relu((double)((float)s + (float)P[OB2 + o]));
-    }
-    double z = P[OB3];
-    for (int i = 0; i < H2; ++i) z += P[OW3 + i] * h2[i];
-    logits[n] = z;
-  }
-  return 0;
-}
-
 static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 

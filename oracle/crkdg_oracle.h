@@ -147,13 +147,9 @@ double or_total_mass(const or_mesh* m, int k, const double* u, int comp);
  * [forward trace jump, backward trace jump, second difference] / scale) */
 int    or_mlp_features(const or_mesh* m, int k, double M, const double* u, double* X);
 /* 12 -> 32 -> 32 -> 1 MLP, ReLU/ReLU/logit; parameters packed W1,b1,W2,b2,w3,b3.
- * or_mlp_forward: binary64 throughout (training semantics); or_mlp_infer:
- * inference precision (features, W1, W2 and the first hidden layer rounded
- * to bfloat16, round to nearest even; sums of exact products rounded to
- * binary32 before each bias); or_bf16: the bfloat16 rounding itself */
+ * or_mlp_forward: the network's definition, binary64 throughout; it is the
+ * reference for training and for inference alike */
 int    or_mlp_forward(const double* params, const double* X, int B, double* logits);
-int    or_mlp_infer(const double* params, const double* X, int B, double* logits);
-float  or_bf16(float f);
 double or_mlp_loss_grad(const double* params, const double* X, const uint8_t* y, int B,
                         double pos_weight, double* grad);
 int    or_adam(double* params, double* m1, double* m2, const double* grad, int n, int step,

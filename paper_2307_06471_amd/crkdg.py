@@ -22,6 +22,7 @@ EQ_ADVECTION, EQ_EULER, EQ_BURGERS = 0, 1, 2
 FLUX_UPWIND, FLUX_LLF, FLUX_GODUNOV = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MIXED, FP32_INNER, FP32_INCREMENTS = 0, 1, 2, 3
+SCHED_SPLIT, SCHED_FUSED = 0, 1
 OP_LOC, OP_DG = 0, 1
 IC_CONST, IC_ADV_SIN, IC_EULER_WAVE, IC_VORTEX, IC_QUADRANT, IC_SHOCK = 0, 1, 2, 3, 4, 5
 IC_DMR = 6  # double Mach reflection
@@ -65,6 +66,8 @@ def _sig():
         "crkdg_project": (C.c_int, [vp, C.c_int, dp, C.c_int, vp]),
         "crkdg_step": (C.c_int, [vp, C.c_double]),
         "crkdg_step_dev": (C.c_int, [vp, vp]),
+        "crkdg_set_schedule": (C.c_int, [vp, C.c_int]),
+        "crkdg_get_schedule": (C.c_int, [vp]),
         "crkdg_step_rkdg": (C.c_int, [vp, C.c_int, C.c_double, C.c_double, vp]),
         "crkdg_compute_dt": (C.c_int, [vp, C.c_double, vp]),
         "crkdg_max_wavespeed": (C.c_int, [vp, dp]),
@@ -235,6 +238,12 @@ class Solver:
     def crkdg_step(self, dt):
         _check(lib().crkdg_step(self.h, float(dt)), "crkdg_step")
 
+    def crkdg_set_schedule(self, sched):
+        _check(lib().crkdg_set_schedule(self.h, int(sched)), "crkdg_set_schedule")
+
+    def crkdg_get_schedule(self):
+        return lib().crkdg_get_schedule(self.h)
+
     def crkdg_step_dev(self, dt_tensor):
         _check(lib().crkdg_step_dev(self.h, C.c_void_p(dt_tensor.data_ptr())), "crkdg_step_dev")
 
@@ -322,7 +331,7 @@ class Solver:
                                    _dp(cf), ptrs), "crkdg_combine")
         return out
 
-    KERNEL_CLASSES = ("inner", "final", "loc", "combine", "dt", "limit", "other", "spare")
+    KERNEL_CLASSES = ("inner", "final", "loc", "combine", "dt", "limit", "other", "fused")
 
     def crkdg_profile_begin(self, max_launches):
         _check(lib().crkdg_profile_begin(self.h, int(max_launches)), "crkdg_profile_begin")

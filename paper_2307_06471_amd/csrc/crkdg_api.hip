@@ -38,6 +38,7 @@ struct crkdg_state {
   size_t S_stage; // bytes of one stored stage state (layout lay_stage)
   int lay, lay_stage;
   int prec;  // Prec: P64, PBULK, PINNER or PINC
+  int sched; // CRKDG_SCHED_SPLIT or CRKDG_SCHED_FUSED (when the step allows it)
   // per-launch timing (measurement only)
   bool prof;
   int prof_max;
@@ -95,7 +96,8 @@ void set_tableau_internal(crkdg_state* st, int s, const double* c, const double*
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? CRKDG_OK : CRKDG_EHIP; }
 
-enum { KC_INNER = 0, KC_FINAL = 1, KC_LOC = 2, KC_COMBINE = 3, KC_DT = 4, KC_LIMIT = 5, KC_OTHER = 6 };
+enum { KC_INNER = 0, KC_FINAL = 1, KC_LOC = 2, KC_COMBINE = 3, KC_DT = 4, KC_LIMIT = 5, KC_OTHER = 6,
+       KC_FUSED = 7 };
 
 // event pair around one launch when profiling is on
 struct ProfScope {
@@ -291,6 +293,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   }
   st->lay_stage = st->lay;
   st->S_stage = st->S;
+  st->sched = CRKDG_SCHED_FUSED_DEFAULT;
   st->bound = false;
   st->cur = 0;
   st->t = 0.0;
@@ -467,6 +470,17 @@ int crkdg_project(crkdg_state* st, int ic, const double* params, int nparams,
   return hip_rc(e);
 }
 
+// whether this step can run as one fused pass: 2D, a kernel for the
+// equation/degree/precision/boundary data, and a subdiagonal tableau whose
+// weights are nonzero only on the first and the last stage
+static bool fusable(const crkdg_state* st) {
+  if (st->mesh.dim != 2 || !fused_supported(st->eq, st->k, st->prec, st->bc)) return false;
+  if (st->s > 1 && !st->subdiag) return false;
+  for (int i = 1; i + 1 < st->s; ++i)
+    if (st->b[i] != 0.0) return false;
+  return true;
+}
+
 // one step with dt from the host (dt_dev == NULL) or from device memory
 static int step_impl(crkdg_state* st, double dt, const double* dt_dev,
                      const double* t_dev = nullptr) {
@@ -474,6 +488,24 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev,
   void* unew = nxt_ptr(st);
   hipError_t e = hipSuccess;
   const int s = st->s;
+  if (st->sched == CRKDG_SCHED_FUSED && fusable(st)) {
+    FusedArgs fa{};
+    fa.un = un;
+    fa.out = unew;
+    fa.s = s;
+    for (int i = 1; i < s; ++i) fa.a_sub[i] = st->A[i][i - 1];
+    fa.w_first = st->b[0];
+    fa.w_last = s > 1 ? st->b[s - 1] : 0.0;
+    fa.dt = dt;
+    fa.dt_ptr = dt_dev;
+    {
+      ProfScope ps(st, KC_FUSED);
+      e = launch_fused(st->eq, st->k, st->prec, st->ph, st->geo, st->bc, fa, st->stream);
+    }
+    if (e != hipSuccess) return CRKDG_EHIP;
+    st->cur ^= 1;
+    return CRKDG_OK;
+  }
   FinalArgs fa{};
   fa.base = un;
   fa.lay_base = st->lay;
@@ -554,6 +586,18 @@ static int step_impl(crkdg_state* st, double dt, const double* dt_dev,
   if (e != hipSuccess) return CRKDG_EHIP;
   st->cur ^= 1;
   return CRKDG_OK;
+}
+
+int crkdg_set_schedule(crkdg_state* st, int sched) {
+  if (!st || (sched != CRKDG_SCHED_SPLIT && sched != CRKDG_SCHED_FUSED)) return CRKDG_EINVAL;
+  if (sched == CRKDG_SCHED_FUSED && !fusable(st)) return CRKDG_EUNSUPPORTED;
+  st->sched = sched;
+  return CRKDG_OK;
+}
+
+int crkdg_get_schedule(const crkdg_state* st) {
+  if (!st) return CRKDG_EINVAL;
+  return st->sched == CRKDG_SCHED_FUSED && fusable(st) ? CRKDG_SCHED_FUSED : CRKDG_SCHED_SPLIT;
 }
 
 int crkdg_step(crkdg_state* st, double dt) {

@@ -94,6 +94,19 @@ struct FinalArgs {
   double cst[MAXS];
 };
 
+// the whole step in one pass (2D, FP32-bulk, subdiagonal tableaus whose
+// weights are nonzero only on the first and last stages, constant boundary
+// data): u^n in, u^{n+1} out
+struct FusedArgs {
+  const void* un;
+  void* out;
+  int s;
+  double a_sub[MAXS];    // a_{i, i-1}
+  double w_first, w_last;  // b_1 and b_s (s = 1: w_first only)
+  double dt;
+  const double* dt_ptr;
+};
+
 // one inner stage of a full tableau (FP64 layout): L_{i-1} = loc(in), stored
 // to L_out if set; out = un + sum_j coef_j X_j (+ coef_last L_{i-1} if
 // use_last), every coefficient times *dt_ptr if set
@@ -119,6 +132,11 @@ hipError_t launch_inner(int eq, int k, int prec, const PhysDev& ph, const Geo& g
                         const InnerArgs& a, hipStream_t s);
 hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, const FinalArgs& a, hipStream_t s);
+// whether launch_fused supports this step (equation, degree, precision,
+// boundary data); the tableau condition is the caller's
+bool fused_supported(int eq, int k, int prec, const BCDev& bc);
+hipError_t launch_fused(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, const FusedArgs& a, hipStream_t s);
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s);
 hipError_t launch_loc_combine(int eq, int k, const PhysDev& ph, const Geo& g,

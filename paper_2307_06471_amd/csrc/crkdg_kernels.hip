@@ -54,6 +54,9 @@
 #ifndef FINAL_OCC_F64
 #define FINAL_OCC_F64 1
 #endif
+#ifndef FUSED_OCC
+#define FUSED_OCC 2
+#endif
 #ifndef FINAL_TX_F32
 #define FINAL_TX_F32 64
 #endif
@@ -900,6 +903,276 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
   } else {
     store_state<R, NC, NB, LAY>(a.out, g.N, cell, acc, a0);
   }
+}
+
+// ---------------------------------------------------------------------------
+// K14: the whole step in one pass (the compact stencil of Section 3.1)
+// ---------------------------------------------------------------------------
+// A cRKDG step reaches only the face neighbours of a cell, whatever the
+// number of stages: the inner stages are element local and only the final
+// stage couples neighbours (Section 3.1).  So a workgroup can read u^n of its
+// tile plus a one-cell ring, compute every inner stage of the ring cells
+// itself, evaluate the shared faces, and write u^{n+1} of the tile: one read
+// of u^n and one write of u^{n+1} per step, no stage state in memory.
+//
+// Workgroup: FX x FY lanes, one cell each: the owned OX x OY tile
+// (OX = FX - 2, OY = FY - 2) and its ring, corners unused.  A ring cell
+// outside the mesh has no lane work: with a non-periodic side its trace on
+// the boundary face is written by the owned cell next to it (transmissive:
+// its own trace; Dirichlet: the boundary state), as in the final-stage
+// kernel.  Every face of the tile is evaluated by one lane per quadrature
+// point in canonical (+x / +y) orientation; a face shared with a
+// neighbouring tile is evaluated by both with the same code on the same
+// traces (the ring cell's inner stages are computed by the same instructions
+// as by its owner), so both see the same bits and the cell averages stay
+// conservative.
+//
+// Schedule: the inner stages first (register chain as in k_inner), then the
+// final stage's terms one stage state at a time (u^(1) = u^n, u^(s)):
+// volume term into the update, traces to LDS, face fluxes, and their lift
+// into both neighbours, the cell averages in FP64 (equation (avg)).  The
+// tableau must have nonzero weights b_i only on the first and last stages
+// (scheme (eq:2), scheme (eq:3), forward Euler), so that at most u^n and
+// u^(s) are live; the split kernels take the others.
+#ifndef FUSED_ROWS
+#define FUSED_ROWS 8
+#endif
+constexpr int FUSED_FX = 64, FUSED_FY = FUSED_ROWS;
+constexpr int FUSED_OX = FUSED_FX - 2, FUSED_OY = FUSED_FY - 2;
+
+template <class R, int NV>
+struct FusedSmem {
+  // x faces: OY rows of OX + 1 faces; y faces: OY + 1 rows of OX faces
+  static constexpr int NXF = NV * FUSED_OY * (FUSED_OX + 1);
+  static constexpr int NYF = NV * (FUSED_OY + 1) * FUSED_OX;
+  static constexpr size_t BYTES = sizeof(R) * 2 * (NXF + NYF);
+};
+
+template <class EQ, int K>
+__global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysDev ph, Geo g, BCDev bc,
+                                                                   FusedArgs a) {
+  using R = typename EQ::Real;
+  constexpr int LAY = StepLayout<EQ>::value;
+  constexpr int FX = FUSED_FX, OX = FUSED_OX, OY = FUSED_OY, NT = FUSED_FX * FUSED_FY;
+  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q;
+  using SM = FusedSmem<R, NV>;
+  constexpr int NXP = Q * (OX + 1) * OY, NFP = NXP + Q * OX * (OY + 1);
+  constexpr int NPASS = (NFP + NT - 1) / NT;
+  constexpr int CSX = Q * OY * (OX + 1), CSY = Q * (OY + 1) * OX;
+  constexpr GTab<Q> T = Tab<Q>::t;
+  __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
+  // tR[v][y][x]: right trace of cell x - 1 (x = 0: the left ring cell);
+  // tL: left trace of cell x; tT[v][y][x]: top trace of row y - 1;
+  // tB: bottom trace of row y (tile coordinates of the owned cells)
+  R(*tR)[OY][OX + 1] = reinterpret_cast<R(*)[OY][OX + 1]>(smem);
+  R(*tL)[OY][OX + 1] = reinterpret_cast<R(*)[OY][OX + 1]>(smem + sizeof(R) * SM::NXF);
+  R(*tT)[OY + 1][OX] = reinterpret_cast<R(*)[OY + 1][OX]>(smem + sizeof(R) * 2 * SM::NXF);
+  R(*tB)[OY + 1][OX] =
+      reinterpret_cast<R(*)[OY + 1][OX]>(smem + sizeof(R) * (2 * SM::NXF + SM::NYF));
+  R* tRf = &tR[0][0][0];
+  R* tLf = &tL[0][0][0];
+  R* tTf = &tT[0][0][0];
+  R* tBf = &tB[0][0][0];
+
+  const int tid = threadIdx.x, lx = tid % FX, ly = tid / FX;
+  const int i0 = blockIdx.x * OX, j0 = blockIdx.y * OY;
+  const int nax = min(OX, g.nx - i0), nay = min(OY, g.ny - j0);
+  const bool owned = lx >= 1 && lx <= nax && ly >= 1 && ly <= nay;
+  const bool ringx = (lx == 0 || lx == nax + 1) && ly >= 1 && ly <= nay;
+  const bool ringy = (ly == 0 || ly == nay + 1) && lx >= 1 && lx <= nax;
+  int i = i0 - 1 + lx, j = j0 - 1 + ly;
+  bool has = owned;
+  if (ringx || ringy) {
+    // a ring cell outside the mesh exists only across a periodic side
+    const bool outx = i < 0 || i >= g.nx, outy = j < 0 || j >= g.ny;
+    has = true;
+    if (outx) {
+      if (bc.type[i < 0 ? 0 : 1] == CRKDG_BC_PERIODIC) i = i < 0 ? i + g.nx : i - g.nx;
+      else has = false;
+    }
+    if (outy) {
+      if (bc.type[j < 0 ? 2 : 3] == CRKDG_BC_PERIODIC) j = j < 0 ? j + g.ny : j - g.ny;
+      else has = false;
+    }
+  }
+  const long long cell = (long long)j * g.nx + i;
+  const EQ eq = make_eq<EQ>(ph);
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
+  // boundary sides of an owned cell whose exterior traces it provides
+  const int bl = owned && i == 0 && bc.type[0] != CRKDG_BC_PERIODIC ? bc.type[0] : -1;
+  const int br = owned && i == g.nx - 1 && bc.type[1] != CRKDG_BC_PERIODIC ? bc.type[1] : -1;
+  const int bb = owned && j == 0 && bc.type[2] != CRKDG_BC_PERIODIC ? bc.type[2] : -1;
+  const int bt = owned && j == g.ny - 1 && bc.type[3] != CRKDG_BC_PERIODIC ? bc.type[3] : -1;
+
+  // u^n in the compute precision (kept: every inner stage starts from it),
+  // and the last stage state
+  R un[NC][NB], u[NC][NB];
+  if (has) load_state<R, NC, NB, LAY>(a.un, g.N, cell, un);
+  else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) un[c][b] = R(0);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) u[c][b] = un[c][b];
+  // inner stages: u^(i+1) = u^n - dt a_{i+1,i} loc(u^(i))
+  if (has) {
+#pragma unroll 1
+    for (int st = 1; st < a.s; ++st) {
+      R acc[NC][NB];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
+      loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[st]), R(g.inv_dx), R(g.inv_dy), acc);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
+    }
+  }
+  // the update, started from u^n (higher modes in the compute precision,
+  // the averages in FP64 from memory)
+  R fin[NC][NB];
+  double a0[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) fin[c][b] = un[c][b];
+    a0[c] = owned ? load_avg<NC, NB, LAY>(a.un, g.N, c, cell) : 0.0;
+  }
+
+  // one final-stage term: stage state U with weight w
+  auto final_term = [&](const R(&U)[NC][NB], const double w) {
+    if (owned) {
+      const R vs = R(0.5 * dt * w);
+      volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), fin);
+    }
+    if (has) {
+      R t[NC][Q];
+      // right trace: face lx of row ly - 1 (left side); also the exterior
+      // trace of a transmissive right boundary
+      if (ly >= 1 && ly <= nay && lx <= nax) {
+        trace_x<+1, EQ, K, R>(U, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) {
+            tR[c * Q + p][ly - 1][lx] = t[c][p];
+            if (br == CRKDG_BC_TRANSMISSIVE) tL[c * Q + p][ly - 1][lx] = t[c][p];
+          }
+      }
+      if (ly >= 1 && ly <= nay && lx >= 1) {
+        trace_x<-1, EQ, K, R>(U, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) {
+            tL[c * Q + p][ly - 1][lx - 1] = t[c][p];
+            if (bl == CRKDG_BC_TRANSMISSIVE) tR[c * Q + p][ly - 1][lx - 1] = t[c][p];
+          }
+      }
+      if (lx >= 1 && lx <= nax && ly <= nay) {
+        trace_y<+1, EQ, K, R>(U, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) {
+            tT[c * Q + p][ly][lx - 1] = t[c][p];
+            if (bt == CRKDG_BC_TRANSMISSIVE) tB[c * Q + p][ly][lx - 1] = t[c][p];
+          }
+      }
+      if (lx >= 1 && lx <= nax && ly >= 1) {
+        trace_y<-1, EQ, K, R>(U, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) {
+            tB[c * Q + p][ly - 1][lx - 1] = t[c][p];
+            if (bb == CRKDG_BC_TRANSMISSIVE) tT[c * Q + p][ly - 1][lx - 1] = t[c][p];
+          }
+      }
+    }
+    // constant Dirichlet data on the boundary faces of this tile
+    if (bl == CRKDG_BC_DIRICHLET || br == CRKDG_BC_DIRICHLET || bb == CRKDG_BC_DIRICHLET ||
+        bt == CRKDG_BC_DIRICHLET) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          if (bl == CRKDG_BC_DIRICHLET) tR[c * Q + p][ly - 1][lx - 1] = (R)bc.state[0][c];
+          if (br == CRKDG_BC_DIRICHLET) tL[c * Q + p][ly - 1][lx] = (R)bc.state[1][c];
+          if (bb == CRKDG_BC_DIRICHLET) tT[c * Q + p][ly - 1][lx - 1] = (R)bc.state[2][c];
+          if (bt == CRKDG_BC_DIRICHLET) tB[c * Q + p][ly][lx - 1] = (R)bc.state[3][c];
+        }
+    }
+    __syncthreads();
+    // every face point of the tile once; the flux replaces the lower/left
+    // trace in LDS (each point belongs to one lane)
+    const bool full = nax == OX && nay == OY;
+#pragma unroll
+    for (int k = 0; k < NPASS; ++k) {
+      const int f = tid + k * NT;
+      if (f >= NFP) break;
+      const bool dy = f >= NXP;
+      const int e = dy ? f - NXP : f;
+      bool valid = full;
+      if (!full) {
+        int fx, fy, p;
+        face_point<OX, OY>(f, NXP, fx, fy, p);
+        valid = dy ? (fx < nax && fy <= nay) : (fx <= nax && fy < nay);
+      }
+      if (valid) {
+        R* A = dy ? tTf : tRf;
+        const R* B = dy ? tBf : tLf;
+        const int cs = dy ? CSY : CSX;
+        R qa[NC], qb[NC], F[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qa[c] = A[c * cs + e];
+          qb[c] = B[c * cs + e];
+        }
+        eq.num_flux_d(qa, qb, dy, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) A[c * cs + e] = F[c];
+      }
+    }
+    __syncthreads();
+    if (owned) {
+      R FL[NC][Q], FR[NC][Q], GB[NC][Q], GT[NC][Q];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          FL[c][p] = tR[c * Q + p][ly - 1][lx - 1];
+          FR[c][p] = tR[c * Q + p][ly - 1][lx];
+          GB[c][p] = tT[c * Q + p][ly - 1][lx - 1];
+          GT[c][p] = tT[c * Q + p][ly][lx - 1];
+        }
+      // cell averages in FP64 (equation (avg)) from this stage's fluxes
+      const double lxs = -0.5 * dt * w * g.inv_dx, lys = -0.5 * dt * w * g.inv_dy;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          sx += T.W[p] * ((double)FR[c][p] - (double)FL[c][p]);
+          sy += T.W[p] * ((double)GT[c][p] - (double)GB[c][p]);
+        }
+        a0[c] += lxs * sx + lys * sy;
+      }
+      lift_x<EQ, K, R>(FR, FL, R(lxs), fin);
+      lift_y<EQ, K, R>(GT, GB, R(lys), fin);
+    }
+    __syncthreads();  // the next term overwrites the traces
+  };
+  // (the weights are kernel arguments: the branches are uniform)
+  if (a.w_first != 0.0) final_term(un, a.w_first);
+  if (a.w_last != 0.0) final_term(u, a.w_last);
+  if (owned) store_state<R, NC, NB, LAY>(a.out, g.N, cell, fin, a0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1791,7 +2064,6 @@ __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_li
       for (int d = 0; d < DIM; ++d) limit_neighbours<NC, NB, LAY, DMRB>(g, bc, u, i, j, d, avg, dp[d], dm[d]);
     }
     if constexpr (USE_MLP) {
-      __shared__ MlpWaveSmem sm[4];
       __shared__ MlpWeightsSmem ws;
       mlp_stage_weights(la.P, ws);
       float x[MLP_IN];
@@ -1799,7 +2071,7 @@ __global__ __launch_bounds__(256, MLP ? LIMIT_OCC_MLP : LIMIT_OCC_TVB) void k_li
       for (int e = 0; e < MLP_IN; ++e) x[e] = 0.0f;
       if (in && !bad) cell_features_jumps(a, at, dp, dm, Mh2[0], Mh2[1], x);
       __syncthreads();  // the staged weights
-      const float z = mlp_infer_wave(la.P, ws, x, sm[threadIdx.x >> 6]);
+      const float z = mlp_infer_wave(la.P, ws, x);
       if (in && !bad) {
         if (z >= la.z_hi)
           troubled = true;
@@ -2188,6 +2460,19 @@ hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g
       return dispatch_mixed<FinalL<L64>::template Run>(eq, k, ph, g, bc, a, s);
     default: return dispatch<FinalL<L64>::template Run>(eq, k, ph, g, bc, a, s);  // FP64 final stage
   }
+}
+bool fused_supported(int eq, int k, int prec, const BCDev& bc) {
+  return eq == EQ_EULER2 && prec == PBULK && (k == 1 || k == 2) && bc.exact <= 0;
+}
+hipError_t launch_fused(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
+                        const BCDev& bc, const FusedArgs& a, hipStream_t s) {
+  if (!fused_supported(eq, k, prec, bc) || a.s < 1 || a.s > MAXS) return hipErrorInvalidValue;
+  const dim3 grid(nblk(g.nx, FUSED_OX), nblk(g.ny, FUSED_OY)), blk(FUSED_FX * FUSED_FY);
+  if (k == 1)
+    hipLaunchKernelGGL((k_fused2<Euler2<float>, 1>), grid, blk, 0, s, ph, g, bc, a);
+  else
+    hipLaunchKernelGGL((k_fused2<Euler2<float>, 2>), grid, blk, 0, s, ph, g, bc, a);
+  return hipGetLastError();
 }
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
                       double* out, hipStream_t s) {

@@ -1,8 +1,8 @@
 // crkdg_mlp.hip -- training kernels of the learned troubled-cell indicator
 // (not part of the paper's method; FP32).
 //
-//   k_mlp_forward       logits of a batch of feature vectors, at inference
-//                       precision (bf16 matrix cores, as in the limiter)
+//   k_mlp_forward       logits of a batch of feature vectors, by the limiter's
+//                       inference routine (FP32 matrix cores)
 //   k_mlp_grad_partial  forward + backward of 64 samples per workgroup: each
 //                       lane runs one sample, the activations go to LDS, then
 //                       each lane sums a fixed subset of the 1505 parameter
@@ -25,11 +25,10 @@ namespace crk {
 constexpr int MB = 64;  // samples per workgroup of the gradient kernel
 constexpr int NPART = MLP_NPAR + 1;  // partial gradients + partial loss
 
-// logits at inference precision (the same routine the limiter uses)
+// logits by the limiter's inference routine
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P,
                                                      const float* __restrict__ X, int B,
                                                      float* __restrict__ out) {
-  __shared__ MlpWaveSmem sm[4];
   __shared__ MlpWeightsSmem ws;
   mlp_stage_weights(P, ws);
   __syncthreads();
@@ -37,7 +36,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
   float x[MLP_IN];
 #pragma unroll
   for (int i = 0; i < MLP_IN; ++i) x[i] = n < B ? X[(long long)n * MLP_IN + i] : 0.0f;
-  const float z = mlp_infer_wave(P, ws, x, sm[threadIdx.x >> 6]);
+  const float z = mlp_infer_wave(P, ws, x);
   if (n < B) out[n] = z;
 }
 

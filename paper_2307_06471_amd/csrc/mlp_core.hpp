@@ -1,7 +1,7 @@
 // mlp_core.hpp -- the learned troubled-cell indicator (not part of the paper's
 // method): a 12 -> 32 -> 32 -> 1 perceptron with ReLU hidden layers and a
 // logistic output on per-cell stencil features.  Training runs in FP32 per
-// lane; inference runs per wavefront on the bf16 matrix cores.
+// lane; inference runs per wavefront on the FP32 matrix cores.
 //
 // Parameters are packed W1[32][12], b1[32], W2[32][32], b2[32], w3[32], b3.
 // All lanes of a wave read the same weight at the same time, so the weights
@@ -52,125 +52,108 @@ __device__ __forceinline__ float mlp_forward1(const float* __restrict__ P, const
 }
 
 // ---------------------------------------------------------------------------
-// Inference at bfloat16 on the matrix cores: one wavefront evaluates its 64
-// lanes' feature vectors together.  Layers 1 and 2 are 32x32x16 bf16 MFMAs
-// (features, W1, W2 and the first hidden layer rounded to bf16, round to
-// nearest even; FP32 accumulation; biases added in FP32 afterwards); the
-// second hidden layer and the output stay FP32.  Operand layouts of
-// v_mfma_f32_32x32x16_bf16: lane l supplies row (A) / column (B) l % 32 and
-// the 8 k-values (l / 32) * 8 ... + 7; accumulator element j of lane l is
-// row (j / 4) * 8 + (l / 32) * 4 + j % 4, column l % 32.  The transposes
-// between layers go through a per-wave LDS scratch.
+// Inference in FP32 on the matrix cores: one wavefront evaluates its 64
+// cells as two groups of 32 (group h: the cells of lanes 32h .. 32h + 31).
+// v_mfma_f32_32x32x2_f32 computes D[32x32] += A[32x2] B[2x32] in FP32; lane l
+// supplies A[l % 32][l / 32] and B[l / 32][l % 32], and accumulator element j
+// of lane l is D[r(j, l)][l % 32] with r(j, l) = 8 (j / 4) + 4 (l / 32) + j % 4.
+//   layer 1  D1 = [W1 | b1] [x; 1]: neurons are rows, cells columns, seven
+//            steps over the 12 features and the bias row (padded to 14); a
+//            lane holds features of its own cell, and one v_permlane32_swap
+//            per feature pair gives both groups' B operands;
+//   layer 2  D2 = [W2 | b2] [h1; 1]: step j (j < 16) contracts the two input
+//            neurons r(j, 0) and r(j, 32), exactly the layer-1 accumulator
+//            element j the lane already holds, so relu(D1) feeds layer 2 in
+//            place; step 16 adds the bias;
+//   output   each lane sums w3 relu(D2) over its 16 neurons, and the two
+//            lanes of a cell (l and l ^ 32) add their halves after one more
+//            permlane swap.
+// No value is rounded below FP32 and no activation passes through LDS.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-struct MlpWaveSmem {
-  union {
-    struct {
-      __bf16 x[64][16];   // features, padded 12 -> 16
-      __bf16 h1[64][32];  // first hidden layer
-    };
-    float h2[32][36];     // second hidden layer, one half of the rows at a time,
-                          // written once x and h1 are read (rows of 144 B:
-                          // 16-byte aligned, consecutive rows 4 banks apart)
-  };
-};
-// W1 and W2 in bf16, already in the matrix cores' B-operand order: lane l
-// reads its 8 values of W1 and twice 8 of W2 with three 16-byte loads
+constexpr int MLP_S1 = (MLP_IN + 2) / 2;  // layer-1 steps: 12 features + bias row
+constexpr int MLP_S2 = MLP_H1 / 2 + 1;    // layer-2 steps: 32 inputs + bias row
+
+__device__ __forceinline__ int mlp_acc_row(int j, int l) {
+  return 8 * (j >> 2) + 4 * ((l >> 5) & 1) + (j & 3);
+}
+
+// the weights in the matrix cores' A-operand order per step and lane (and
+// the output weights in accumulator order): each lane reads one float per
+// step, consecutive lanes consecutive words
 struct MlpWeightsSmem {
-  bf16x8 w1[64], w2a[64], w2b[64];
+  float w1[MLP_S1][64];
+  float w2[MLP_S2][64];
+  float w3[16][64];
 };
 
 // the block stages the weights once (every thread calls this, then the
 // block synchronises)
 __device__ __forceinline__ void mlp_stage_weights(const float* __restrict__ P,
                                                   MlpWeightsSmem& ws) {
-  for (int t = threadIdx.x; t < 3 * 64 * 8; t += blockDim.x) {
-    const int which = t / 512, l = (t / 8) & 63, e = t & 7;
-    const int n = l & 31, k = (l >> 5) * 8 + e;
-    float v;
-    if (which == 0) v = k < MLP_IN ? P[MLP_OW1 + n * MLP_IN + k] : 0.0f;
-    else if (which == 1) v = P[MLP_OW2 + n * MLP_H1 + k];
-    else v = P[MLP_OW2 + n * MLP_H1 + 16 + k];
-    bf16x8* dst = which == 0 ? ws.w1 : which == 1 ? ws.w2a : ws.w2b;
-    dst[l][e] = (__bf16)v;
+  constexpr int NS = MLP_S1 + MLP_S2 + 16;
+  for (int t = threadIdx.x; t < NS * 64; t += blockDim.x) {
+    const int step = t >> 6, l = t & 63, n = l & 31, hi = l >> 5;
+    if (step < MLP_S1) {
+      const int kk = 2 * step + hi;  // feature index; MLP_IN is the bias row
+      ws.w1[step][l] = kk < MLP_IN ? P[MLP_OW1 + n * MLP_IN + kk]
+                                   : (kk == MLP_IN ? P[MLP_OB1 + n] : 0.0f);
+    } else if (step < MLP_S1 + MLP_S2) {
+      const int j = step - MLP_S1;
+      ws.w2[j][l] = j < MLP_S2 - 1 ? P[MLP_OW2 + n * MLP_H1 + mlp_acc_row(j, l)]
+                                   : (hi ? 0.0f : P[MLP_OB2 + n]);
+    } else {
+      const int j = step - MLP_S1 - MLP_S2;
+      ws.w3[j][l] = P[MLP_OW3 + mlp_acc_row(j, l)];
+    }
   }
 }
 
-// order this wave's LDS accesses (they complete in issue order on the
-// hardware; this keeps the compiler from moving them across)
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// swap lanes 32..63 of a with lanes 0..31 of b
+__device__ __forceinline__ void lane_half_swap(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
 }
 
-// every lane of the wave must call this (uniform control flow), after the
-// block has staged the weights
+// logit of this lane's cell; every lane of the wave must call this (uniform
+// control flow), after the block has staged the weights
 __device__ __forceinline__ float mlp_infer_wave(const float* __restrict__ P,
                                                 const MlpWeightsSmem& ws,
-                                                const float (&x)[MLP_IN], MlpWaveSmem& sm) {
+                                                const float (&x)[MLP_IN]) {
   const int l = threadIdx.x & 63;
-  const int n = l & 31, kb = (l >> 5) * 8;
-  {
-    bf16x8 lo, hi;
+  const float one = l < 32 ? 1.0f : 0.0f;  // B operand of a bias step
+  f32x16 d0 = {}, d1 = {};
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      lo[e] = (__bf16)x[e];
-      hi[e] = (__bf16)(e + 8 < MLP_IN ? x[e + 8] : 0.0f);
+  for (int s = 0; s < MLP_S1; ++s) {
+    float b0 = one, b1 = one;
+    if (2 * s + 1 < MLP_IN) {
+      b0 = x[2 * s];
+      b1 = x[2 * s + 1];
+      lane_half_swap(b0, b1);  // b0: group 0's operand, b1: group 1's
     }
-    *reinterpret_cast<bf16x8*>(&sm.x[l][0]) = lo;
-    *reinterpret_cast<bf16x8*>(&sm.x[l][8]) = hi;
+    const float a = ws.w1[s][l];
+    d0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, d1, 0, 0, 0);
   }
-  const bf16x8 w1 = ws.w1[l], w2a = ws.w2a[l], w2b = ws.w2b[l];
-  const float b1 = P[MLP_OB1 + n], b2 = P[MLP_OB2 + n];
-  wave_lds_fence();
+  float part[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sm.x[h * 32 + n][kb]);
-    f32x16 c = {};
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, w1, c, 0, 0, 0);
+    const f32x16& d = h ? d1 : d0;
+    f32x16 e = {};
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int r = (j >> 2) * 8 + (l >> 5) * 4 + (j & 3);
-      sm.h1[h * 32 + r][n] = (__bf16)relu_f(c[j] + b1);
-    }
+    for (int j = 0; j < MLP_S2 - 1; ++j)
+      e = __builtin_amdgcn_mfma_f32_32x32x2f32(ws.w2[j][l], relu_f(d[j]), e, 0, 0, 0);
+    e = __builtin_amdgcn_mfma_f32_32x32x2f32(ws.w2[MLP_S2 - 1][l], one, e, 0, 0, 0);
+    float z = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) z = z + ws.w3[j][l] * relu_f(e[j]);
+    part[h] = z;
   }
-  wave_lds_fence();
-  bf16x8 a0[2], a1[2];  // all of layer 2's inputs, before h2 overwrites them
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    a0[h] = *reinterpret_cast<const bf16x8*>(&sm.h1[h * 32 + n][kb]);
-    a1[h] = *reinterpret_cast<const bf16x8*>(&sm.h1[h * 32 + n][16 + kb]);
-  }
-  wave_lds_fence();
-  typedef float f32x4 __attribute__((ext_vector_type(4)));
-  float z = 0.0f;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    f32x16 c = {};
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[h], w2a, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[h], w2b, c, 0, 0, 0);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int r = (j >> 2) * 8 + (l >> 5) * 4 + (j & 3);
-      sm.h2[r][n] = relu_f(c[j] + b2);
-    }
-    wave_lds_fence();
-    // lane l's row is row l % 32 of half l / 32
-    if ((l >> 5) == h) {
-      z = P[MLP_OB3];
-#pragma unroll
-      for (int q = 0; q < MLP_H2 / 4; ++q) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(&sm.h2[n][4 * q]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) z = z + P[MLP_OW3 + 4 * q + e] * v[e];
-      }
-    }
-    wave_lds_fence();  // the half is read before the next one overwrites it
-  }
-  return z;
+  lane_half_swap(part[0], part[1]);
+  return P[MLP_OB3] + (part[0] + part[1]);
 }
 
 // 12 stencil features of one cell (computed in FP64, returned in FP32): for

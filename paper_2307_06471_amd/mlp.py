@@ -233,3 +233,115 @@ def rates(P, X, y, tau_lo, tau_hi):
             "fp_rate": float((trouble & ~pos).sum() / max(1, (~pos).sum())),
             "fallback_fraction": float(band.mean()),
             "n": int(len(y)), "positives": int(pos.sum())}
+
+
+def compare_with_tvb(family, seed, n, P, tau_lo, tau_hi, M=50.0, samples=10, t_frac=0.25,
+                     reference=True, precision=K.FP64):
+    """what the learned indicator changes against the TVB test alone on one
+    problem (the gain test): the same problem run to the same final time
+    with the limiter deciding by the TVB test (M) and by the network with
+    the FP64 TVB fallback band, in `precision`.  Reported: the limiter's
+    device time per step, the flagged and fallback fractions, the false
+    negative / positive rates of the network's decisions against the FP64
+    TVB test taken on the same pre-limiter states (an FP64 copy, at about
+    `samples` steps), and with `reference` the L1 / L2 errors of the density
+    cell averages against an FP64 TVB run on the 2x finer mesh restricted to
+    this one.  family: "quadrant" (n x n cells) or "shock" (cell counts
+    divided by n).  If a run drives a cell average out of the physical set
+    the result holds only "stopped" (the run that stopped)."""
+    import torch
+
+    def build(nn, prec):
+        if family == "quadrant":
+            s, cfg = quadrant_solver(seed, nn, precision=prec)
+        else:
+            s, cfg = shock_solver(seed, nn, precision=prec)
+        s.crkdg_limit(M)  # the projected jumps overshoot
+        return s, cfg
+
+    s0, cfg = build(n, precision)
+    if family == "quadrant":
+        smax = s0.crkdg_max_wavespeed()
+        h = (cfg["box"][1] - cfg["box"][0]) / n
+        T = t_frac / (smax * h / 2.0)
+    else:
+        T = cfg["T"]
+    del s0
+
+    def run(nn, prec, learned, compare):
+        s, cfg = build(nn, prec)
+        flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+        clone = tflags = None
+        if compare:
+            clone = K.Solver(s.mesh if prec == K.FP64 else
+                             K.make_mesh(2, s.mesh.nx, s.mesh.ny, x0=s.mesh.x0, x1=s.mesh.x1,
+                                         y0=s.mesh.y0, y1=s.mesh.y1, bc=tuple(s.mesh.bc),
+                                         bc_state=[list(r) for r in s.mesh.bc_state],
+                                         equation=K.EQ_EULER, gamma=s.mesh.gamma,
+                                         precision=K.FP64), cfg["k"], K.FLUX_LLF, 3)
+            tflags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+        t, step = 0.0, 0
+        est = None
+        tot = {"flagged": 0, "fallback": 0, "cells": 0, "tvb_pos": 0, "fn": 0, "fp": 0,
+               "neg": 0, "limit_ms": 0.0}
+        while t < T:
+            dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), T - t)
+            if est is None:
+                est = max(1, int(T / dt) // samples)
+            s.crkdg_step(dt)
+            t = t + dt if T - t - dt > 1e-14 else T
+            step += 1
+            sample = compare and step % est == 0
+            if sample:
+                clone.crkdg_set_state(s.crkdg_get_state())
+                clone.crkdg_limit(M, tflags)
+            s.crkdg_profile_begin(4)
+            if learned:
+                nf, nb = s.crkdg_limit_mlp(M, P, tau_lo, tau_hi, flags if sample else None)
+                tot["fallback"] += nb
+            else:
+                nf = s.crkdg_limit(M, flags if sample else None)
+            prof = s.crkdg_profile_end()
+            tot["limit_ms"] += prof.get("limit", (0.0, 0))[0]
+            tot["flagged"] += nf
+            tot["cells"] += s.ncells
+            if sample:
+                tv = (tflags & 1).bool()
+                ml = (flags & 1).bool()
+                tot["tvb_pos"] += int(tv.sum())
+                tot["neg"] += int((~tv).sum())
+                tot["fn"] += int((tv & ~ml).sum())
+                tot["fp"] += int((ml & ~tv).sum())
+        torch.cuda.synchronize()
+        return s, step, tot
+
+    out = {"family": family, "seed": seed, "mesh": None, "T": T}
+    runs = {}
+    for name, learned in (("tvb", False), ("learned", True)):
+        try:
+            s, nsteps, tot = run(n, precision, learned, compare=learned)
+        except K.CrkdgError as e:
+            # a cell average left the physical set (as some random quadrant
+            # states do under any limiter): no comparison for this problem
+            if e.code != K.CRKDG_ENONPHYSICAL:
+                raise
+            out["stopped"] = name
+            return out
+        out["mesh"] = f"{s.mesh.nx}x{s.mesh.ny}"
+        r = {"steps": nsteps, "limit_ms_per_step": tot["limit_ms"] / nsteps,
+             "flagged_fraction": tot["flagged"] / tot["cells"]}
+        if learned:
+            r["fallback_fraction"] = tot["fallback"] / tot["cells"]
+            r["fn_rate_vs_tvb"] = tot["fn"] / max(1, tot["tvb_pos"])
+            r["fp_rate_vs_tvb"] = tot["fp"] / max(1, tot["neg"])
+            r["tvb_positives_sampled"] = tot["tvb_pos"]
+        runs[name] = (s, r)
+    if reference:
+        fine = 2 * n if family == "quadrant" else max(1, n // 2)
+        ref, _, _ = run(fine, K.FP64, False, compare=False)
+        for name, (s, r) in runs.items():
+            e = s.crkdg_error_ref(ref, 0)
+            r["L1"], r["L2"] = float(e[0]), float(e[1])
+    for name, (s, r) in runs.items():
+        out[name] = r
+    return out

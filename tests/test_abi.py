@@ -277,3 +277,32 @@ def test_noalloc_gradient_argument_checks():
     assert L.crkdg_mlp_grad_noalloc(fake, fake, fake, 64, 0.0, fake, None, None) == K.CRKDG_EINVAL
     assert L.crkdg_mlp_grad_noalloc(None, fake, fake, 64, 1.0, fake, None, None) == K.CRKDG_EINVAL
 
+
+def test_schedule_selection_is_host_logic():
+    """the fused schedule is accepted only where the fused kernel applies
+    (2D Euler, FP32-bulk, k = 1 or 2, constant boundary data, weights on the
+    first and last stage only); no GPU needed"""
+    L = K.lib()
+
+    def handle(k=2, stages=3, precision=K.FP32_MIXED, bc=(1, 1, 1, 1), bc_exact=0, dim=2):
+        m = K.make_mesh(dim, 70, 9 if dim == 2 else 1, bc=bc, bc_exact=bc_exact,
+                        equation=K.EQ_EULER, precision=precision)
+        return K.crkdg_create(m, k, K.FLUX_LLF, stages)
+
+    h = handle()
+    assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT            # the default
+    assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_OK
+    assert L.crkdg_get_schedule(h) == K.SCHED_FUSED
+    assert L.crkdg_set_schedule(h, 7) == K.CRKDG_EINVAL
+    assert L.crkdg_set_schedule(h, K.SCHED_SPLIT) == K.CRKDG_OK
+    L.crkdg_destroy(h)
+    for kw in (dict(precision=K.FP64), dict(k=3), dict(stages=4),
+               dict(precision=K.FP32_INNER), dict(bc=(2, 1, 2, 2), bc_exact=K.IC_DMR)):
+        h = handle(**kw)
+        assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_EUNSUPPORTED, kw
+        assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT
+        L.crkdg_destroy(h)
+    for kw in (dict(k=1, stages=2), dict(stages=1), dict(bc=(0, 0, 0, 0)), dict(bc=(2, 2, 2, 2))):
+        h = handle(**kw)
+        assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_OK, kw
+        L.crkdg_destroy(h)

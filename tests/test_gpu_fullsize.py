@@ -25,7 +25,7 @@ import pytest
 
 import oracle as O
 from paper_2307_06471_amd import workloads as W
-from tests.helpers import BC, tableau
+from tests.helpers import BC, mlp_fp32_bound, tableau
 
 pytestmark = pytest.mark.gpu
 
@@ -109,6 +109,9 @@ CASES = [
     ("c5", "fp64", 2000, 3),
     ("c5", "mixed", 2000, 3),
     ("c5", "incr", 2000, 3),
+    # the fused one-pass step (same form, one kernel for the whole step)
+    ("c4", "mixed-fused", 1001, 4),
+    ("c5", "mixed-fused", 2000, 3),
 ]
 
 
@@ -116,9 +119,11 @@ CASES = [
 def test_full_size_sampled_parity(K, case):
     import torch
     name, prec, seed, pre = case
-    precision = {"fp64": K.FP64, "mixed": K.FP32_MIXED, "incr": K.FP32_INCREMENTS}[prec]
+    precision = {"fp64": K.FP64, "mixed": K.FP32_MIXED, "incr": K.FP32_INCREMENTS,
+                 "mixed-fused": K.FP32_MIXED}[prec]
     tol = 1e-12 if prec == "fp64" else 1e-5
     s, cfg, bc, bc_state = build(K, name, precision, seed)
+    s.crkdg_set_schedule(K.SCHED_FUSED if prec == "mixed-fused" else K.SCHED_SPLIT)
     print(f"[fullsize] {name} {prec} {cfg['nx']}x{cfg['ny']} k={cfg['k']}", flush=True)
     k = cfg["k"]
     tab = tableau(cfg["tableau"])
@@ -183,11 +188,15 @@ def test_full_size_learned_indicator_parity(K):
     (4096 x 1024 Q2 shock, FP32-bulk state, dt from the device, crkdg_step_dev,
     then crkdg_limit_dt with the learned indicator; a fixed random network
     and band (0.35, 0.65) stand in for the trained one).  On sampled cells the
-    decision is the oracle's inference-precision network on the oracle's
-    features of the cell's 3 x 3 patch, and the FP64 TVB test inside the
-    band; compared where the probability is 2e-3 or more from a threshold
-    and, in the band, the TVB margin above 1e-9 of the averages' scale.
-    Limited states are compared where the decision equals the TVB test's."""
+    decision is the oracle's FP64 network on the oracle's features of the
+    cell's 3 x 3 patch, and the FP64 TVB test inside the band; compared where
+    the logit is further than the binary32 error bound from a threshold's
+    logit and, in the band, the TVB margin above 1e-9 of the averages' scale.
+    Limited states are compared where the decision equals the TVB test's;
+    the sample holds 150 cells both the network and the TVB test flag and
+    50 band cells the TVB test flags (besides cells the network alone flags,
+    other band cells and random cells), so that more than 100 limited states
+    are compared."""
     import torch
     s, cfg, bc, bc_state = build(K, "c5", K.FP32_MIXED, 2000)
     k, M, cfl = cfg["k"], cfg["limiter"][1], cfg["cfl"]
@@ -210,27 +219,40 @@ def test_full_size_learned_indicator_parity(K):
     u2 = s.crkdg_get_state()
     fl = flags.cpu().numpy()
     nx = cfg["nx"]
+    # the TVB test's flags on the same pre-limiter state (a second handle):
+    # limited states are compared where both tests flag a cell, so the sample
+    # takes cells flagged by both, band cells, and cells the network alone flags
+    tv = K.Solver(s.mesh, k, K.FLUX_LLF, 3)
+    tv.crkdg_set_state(u1)
+    tflags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+    tv.crkdg_limit(M, tflags)
+    tf = tflags.cpu().numpy()
+    del tv
     extra = []
-    for bit in (1, 8):
-        cells = np.nonzero(fl & bit)[0]
-        assert len(cells) > 0, bit
-        extra += [(int(c % nx), int(c // nx)) for c in rng.choice(cells, min(40, len(cells)),
+    for sel, want in (((fl & 1) & (tf & 1), 150), ((fl & 8) & ((tf & 1) << 3), 50),
+                      ((fl & 1) & ~tf & 1, 40), (fl & 8, 40)):
+        cells = np.nonzero(sel)[0]
+        assert len(cells) > 0, want
+        extra += [(int(c % nx), int(c // nx)) for c in rng.choice(cells, min(want, len(cells)),
                                                                    replace=False)]
+    P64 = Pf.astype(np.float64)
+    zlo, zhi = np.log(lo / (1 - lo)), np.log(hi / (1 - hi))
     checked = states = 0
     for (i, j) in sample_cells(cfg, rng, extra):
         cell = j * nx + i
         om, up, c = patch(cfg, bc, bc_state, u1, i, j)
         X = O.mlp_features(om, k, M, up)[c:c + 1]
-        p = 1.0 / (1.0 + np.exp(-O.mlp_infer(Pf.astype(np.float64), X)[0]))
+        z = O.mlp_forward(P64, X)[0]
+        zb = mlp_fp32_bound(P64, X)[0]
         fo, margin, _ = O.tvb_flags(om, k, M, up)
-        band = lo < p < hi
+        band = zlo < z < zhi
         scale = max(1.0, np.abs(up[:, 0]).max())
-        if min(abs(p - lo), abs(p - hi)) < 2e-3 or (band and margin[c] <= 1e-9 * scale):
+        if min(abs(z - zlo), abs(z - zhi)) <= zb or (band and margin[c] <= 1e-9 * scale):
             continue
-        dec = int(fo[c] & 1) if band else int(p >= hi)
+        dec = int(fo[c] & 1) if band else int(z >= zhi)
         checked += 1
-        assert (fl[cell] & 1) == dec, (i, j, p, fl[cell])
-        assert ((fl[cell] & 8) != 0) == band, (i, j, p, fl[cell])
+        assert (fl[cell] & 1) == dec, (i, j, z, fl[cell])
+        assert ((fl[cell] & 8) != 0) == band, (i, j, z, fl[cell])
         if dec == (fo[c] & 1):
             lim, flo, _ = O.limit_tvb(om, k, M, up)
             if (fl[cell] & 7) == (flo[c] & 7):
@@ -239,4 +261,4 @@ def test_full_size_learned_indicator_parity(K):
                 assert e < 1e-5, (i, j, e)
     print(f"[fullsize] learned indicator: decisions checked {checked}, limited states "
           f"checked {states}", flush=True)
-    assert checked > 150 and states > 50
+    assert checked > 300 and states > 100

@@ -1,0 +1,172 @@
+"""The fused one-pass cRKDG step (crkdg_set_schedule(CRKDG_SCHED_FUSED)).
+
+The compact stencil of Section 3.1 lets one kernel read u^n of a tile plus a
+one-cell ring, recompute the ring's inner stages, evaluate the tile's faces
+and write u^{n+1}.  Checked against the oracle's step (FP64) within the FP32
+tolerance of the build (1e-5 relative) on meshes of several 62 x 6 tiles
+with ragged tails, every boundary type the fused kernel takes, degrees 1
+and 2 and the tableaus it takes (forward Euler, (eq:2), (eq:3)); against
+the split schedule on the same state; conservation of the FP64 cell
+averages; and degenerate meshes (a mesh smaller than one tile, one cell
+wide) where a periodic ring wraps onto the tile itself.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2307_06471_amd import workloads as W
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2307_06471_amd import crkdg
+    return crkdg
+
+
+GHOST = [1.2, 0.3, -0.1, 2.9]
+
+
+def pair(K, nx, ny, bc, k, stages):
+    bc_state = [GHOST] * 4
+    lm = K.make_mesh(2, nx, ny, x0=0.0, x1=1.3, y0=-0.2, y1=0.5, bc=bc, bc_state=bc_state,
+                     equation=K.EQ_EULER, precision=K.FP32_MIXED)
+    om = O.Mesh(2, nx, ny, x0=0.0, x1=1.3, y0=-0.2, y1=0.5, bc=bc, bc_state=bc_state,
+                equation=O.EQ_EULER, flux=O.FLUX_LLF)
+    s = K.Solver(lm, k, K.FLUX_LLF, stages)
+    s.crkdg_set_schedule(K.SCHED_FUSED)
+    assert s.crkdg_get_schedule() == K.SCHED_FUSED
+    return s, om
+
+
+def fp32_modes(u):
+    """the FP32-bulk layout's values: FP64 averages, FP32 higher modes"""
+    v = u.copy()
+    v[:, 1:] = v[:, 1:].astype(np.float32).astype(np.float64)
+    return v
+
+
+CASES = [
+    # nx, ny, bc (left, right, bottom, top)
+    (130, 13, (0, 0, 0, 0)),
+    (131, 14, (1, 1, 1, 1)),
+    (125, 19, (2, 1, 1, 1)),     # the shock workload's boundary types
+    (64, 7, (1, 2, 0, 0)),
+    (62, 6, (2, 2, 2, 2)),       # exactly one tile
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}-bc{''.join(map(str, c[2]))}")
+@pytest.mark.parametrize("k,tab", [(2, "eq3"), (1, "eq2"), (2, "fe")])
+def test_fused_step_matches_oracle(K, case, k, tab):
+    nx, ny, bc = case
+    s, om = pair(K, nx, ny, bc, k, W.RK_STAGES[tab])
+    rng = np.random.default_rng(nx * 100 + ny + k)
+    u = fp32_modes(W.random_euler_modes(rng, (k + 1) ** 2, nx * ny))
+    s.crkdg_set_state(u)
+    assert rel_err(s.crkdg_get_state(), u) == 0.0
+    A, b, c = (np.array(v, float) for v in W.TABLEAU[tab])
+    dt = 0.05 / O.max_wavespeed(om, k, u)
+    s.crkdg_step(dt)
+    ref = O.step_crkdg(om, k, (A, b, c), 0.0, dt, u)
+    got = s.crkdg_get_state()
+    err = rel_err(got, ref)
+    err_avg = rel_err(got[:, 0], ref[:, 0])
+    print(f"[fused] {nx}x{ny} bc{bc} k={k} {tab}: max rel err {err:.2e} (averages {err_avg:.2e})",
+          flush=True)
+    assert err < TOL
+    # the update of the FP64 averages carries FP32 fluxes only: errors of
+    # FP32 size relative to the flux difference times dt/h, far below TOL
+    assert err_avg < TOL
+
+
+def test_fused_equals_split_on_the_same_state(K):
+    import torch
+    nx, ny = 200, 31
+    rng = np.random.default_rng(3)
+    u = fp32_modes(W.random_euler_modes(rng, 9, nx * ny))
+    out = {}
+    for sched in (K.SCHED_SPLIT, K.SCHED_FUSED):
+        s, om = pair(K, nx, ny, (2, 1, 1, 1), 2, 3)
+        s.crkdg_set_schedule(sched)
+        s.crkdg_set_state(u)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.crkdg_compute_dt(0.1, dt_dev)
+        for _ in range(3):
+            s.crkdg_step_dev(dt_dev)
+        out[sched] = s.crkdg_get_state()
+    err = rel_err(out[K.SCHED_FUSED], out[K.SCHED_SPLIT])
+    print(f"[fused] fused vs split, 3 steps: {err:.2e}", flush=True)
+    assert err < TOL
+
+
+def test_fused_density_wave_run_and_conservation(K):
+    """the density-wave workload (Section 4.1.2 example) on 130 x 20 cells,
+    60 steps: within 1e-5 relative L2 of the FP64 oracle, and the FP64 cell
+    averages conserved to FP64 round-off (periodic)"""
+    cfg = dict(W.config("c3"), nx=130, ny=20, k=2)
+    x0, x1, y0, y1 = cfg["box"]
+    lm = K.make_mesh(2, 130, 20, x0=x0, x1=x1, y0=y0, y1=y1, equation=K.EQ_EULER,
+                     precision=K.FP32_MIXED)
+    om = O.Mesh(2, 130, 20, x0=x0, x1=x1, y0=y0, y1=y1, equation=O.EQ_EULER, flux=O.FLUX_LLF)
+    s = K.Solver(lm, 2, K.FLUX_LLF, 3)
+    s.crkdg_set_schedule(K.SCHED_FUSED)
+    P = cfg["ic_params"]
+    s.crkdg_project(K.IC_EULER_WAVE, P)
+    u = O.project(om, 2, O.IC_EULER_WAVE, P)
+    m0 = [s.crkdg_total(c) for c in range(4)]
+    dt = cfg["cfl"] / O.max_wavespeed(om, 2, u)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    for n in range(60):
+        s.crkdg_step(dt)
+        u = O.step_crkdg(om, 2, (A, b, c), n * dt, dt, u)
+    got = s.crkdg_get_state()
+    l2 = float(np.sqrt(((got - u) ** 2).sum() / (u ** 2).sum()))
+    drift = max(abs(s.crkdg_total(cc) - m0[cc]) / max(1.0, abs(m0[cc])) for cc in range(4))
+    print(f"[fused] density wave 60 steps: rel L2 {l2:.2e}, conservation drift {drift:.2e}",
+          flush=True)
+    assert l2 < 1e-5
+    assert drift < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(3, 2, (0, 0, 0, 0)), (1, 7, (0, 0, 1, 1)),
+                                      (5, 1, (1, 1, 0, 0)), (1, 1, (2, 2, 2, 2))])
+def test_fused_degenerate_meshes(K, nx, ny, bc):
+    s, om = pair(K, nx, ny, bc, 2, 3)
+    rng = np.random.default_rng(nx + 10 * ny)
+    u = fp32_modes(W.random_euler_modes(rng, 9, nx * ny))
+    s.crkdg_set_state(u)
+    dt = 0.05 / O.max_wavespeed(om, 2, u)
+    s.crkdg_step(dt)
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["eq3"])
+    ref = O.step_crkdg(om, 2, (A, b, c), 0.0, dt, u)
+    assert rel_err(s.crkdg_get_state(), ref) < TOL
+
+
+def test_fused_schedule_falls_back_for_other_tableaus(K):
+    """RK4 has nonzero weights on every stage: the fused schedule is refused
+    up front, and a fused handle whose tableau is replaced takes the split
+    schedule (checked against the oracle)"""
+    s, om = pair(K, 70, 9, (0, 0, 0, 0), 2, 3)
+    s2 = K.Solver(s.mesh, 2, K.FLUX_LLF, 4)
+    with pytest.raises(K.CrkdgError):
+        s2.crkdg_set_schedule(K.SCHED_FUSED)
+    assert s2.crkdg_get_schedule() == K.SCHED_SPLIT
+    # classical RK4 (weights on every stage) set on the fused handle
+    A, b, c = (np.array(v, float) for v in W.TABLEAU["rk4"])
+    s.crkdg_set_tableau(A, b, c)
+    assert s.crkdg_get_schedule() == K.SCHED_SPLIT
+    rng = np.random.default_rng(9)
+    u = fp32_modes(W.random_euler_modes(rng, 9, 70 * 9))
+    s.crkdg_set_state(u)
+    dt = 0.05 / O.max_wavespeed(om, 2, u)
+    s.crkdg_step(dt)
+    ref = O.step_crkdg(om, 2, (A, b, c), 0.0, dt, u)
+    assert rel_err(s.crkdg_get_state(), ref) < TOL

@@ -1,0 +1,73 @@
+"""What the trained troubled-cell network gains over the TVB test alone (the
+learned indicator is not part of the paper's method; the TVB minmod test of
+Section 4.2, M = 50, stays its judge and fallback).
+
+Four-quadrant Riemann problems (seeded states, transmissive sides): the
+network is trained by the library's own kernels on runs of seeds 0-31 at
+128 x 128, its decision band is chosen on seeds 64-79 at 256 x 256 (false
+negatives against TVB at most 0.5% there, on runs limited by the network
+itself), and the held-out seeds 80-95 are
+run at 256 x 256 twice, limited by the TVB test and by the network with the
+FP64 TVB fallback band.  Asserted: the network misses at most 1% of the
+cells the FP64 TVB test flags on the same states (aggregated over the test
+seeds).  Printed: limiter time per step, flagged and fallback fractions,
+false-positive rate, and the L1 density error of both runs against an FP64
+TVB run on the 2x finer mesh (the gain, or the loss, in accuracy).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ML():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2307_06471_amd import mlp
+    return mlp
+
+
+def test_indicator_gain_on_held_out_quadrant_seeds(ML):
+    print("[gain] training on quadrant seeds 0-31 at 128x128", flush=True)
+    Xtr, ytr = ML.generate(range(0, 32), n=128)
+    P, info = ML.train(Xtr, ytr, epochs=10, batch=4096, seed=0)
+    # the band in two rounds: on validation runs limited by the TVB test,
+    # then on validation runs limited by the network with that band (the
+    # states it meets in use; labels always the FP64 TVB test)
+    Xva, yva = ML.generate(range(64, 80), n=256, sample_seed=1)
+    lo0, hi0 = ML.choose_band(P, Xva, yva, fn_target=0.005)
+    Xvp, yvp = ML.generate(range(64, 80), n=256, sample_seed=2, policy=(P, lo0, hi0))
+    lo, hi = ML.choose_band(P, Xvp, yvp, fn_target=0.005)
+    print(f"[gain] {len(ytr)} training samples ({int(ytr.sum())} positives); band "
+          f"({lo0:.4g}, {hi0:.4g}) on TVB-limited validation runs, ({lo:.4g}, {hi:.4g}) on "
+          f"network-limited ones", flush=True)
+    rows = []
+    stopped = []
+    for seed in range(80, 96):
+        r = ML.compare_with_tvb("quadrant", seed, 256, P, lo, hi)
+        if "stopped" in r:
+            print(f"[gain] seed {seed}: the {r['stopped']} run left the physical set; skipped",
+                  flush=True)
+            stopped.append(seed)
+            continue
+        t, m = r["tvb"], r["learned"]
+        print(f"[gain] seed {seed}: steps {t['steps']}/{m['steps']}, limiter ms/step "
+              f"{t['limit_ms_per_step']:.4f} -> {m['limit_ms_per_step']:.4f}, flagged "
+              f"{t['flagged_fraction']:.4f} -> {m['flagged_fraction']:.4f}, fallback "
+              f"{m['fallback_fraction']:.4f}, FN {m['fn_rate_vs_tvb']:.4f} FP "
+              f"{m['fp_rate_vs_tvb']:.4f}, L1 {t['L1']:.4e} -> {m['L1']:.4e}", flush=True)
+        rows.append(r)
+    pos = sum(r["learned"]["tvb_positives_sampled"] for r in rows)
+    fn = sum(r["learned"]["fn_rate_vs_tvb"] * r["learned"]["tvb_positives_sampled"]
+             for r in rows) / max(1, pos)
+    l1 = np.mean([r["learned"]["L1"] / r["tvb"]["L1"] for r in rows])
+    ms = [np.mean([r[k]["limit_ms_per_step"] for r in rows]) for k in ("tvb", "learned")]
+    fall = np.mean([r["learned"]["fallback_fraction"] for r in rows])
+    print(f"[gain] held-out seeds 80-95: FN {fn:.4f} of {pos} TVB-flagged cells, mean L1 "
+          f"ratio learned/TVB {l1:.4f}, limiter {ms[0]:.4f} -> {ms[1]:.4f} ms/step, fallback "
+          f"{fall:.4f}", flush=True)
+    assert len(stopped) <= 6, stopped
+    assert pos > 1000
+    assert fn <= 0.01

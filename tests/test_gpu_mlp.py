@@ -2,18 +2,18 @@
 method; parity against the oracle's FP64 MLP and features).
 
 Tolerances: features are FP64 ratios stored in FP32 (1e-6 absolute on O(1)
-values).  Logits come from the inference pass (bf16 matrix cores, FP32
-accumulation), compared with the oracle's inference-precision forward: the
-two round the same bf16 values except where an FP32 sum sits on a bf16
-rounding boundary, so the median difference is at FP32 level and the largest
-stays below 1e-2 of the logit scale.  Gradients (FP32 training pass) 1e-4
-relative L2 against FP64.
+values).  Logits come from the inference pass (FP32 matrix cores), compared
+per sample with the oracle's FP64 network within twice the forward error
+bound of binary32 evaluation (tests/helpers.mlp_fp32_bound).  Decisions are
+compared where the FP64 logit is further than that bound from a threshold.
+Gradients (FP32 training pass) 1e-4 relative L2 against FP64.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2307_06471_amd import workloads as W
+from tests.helpers import mlp_fp32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -66,10 +66,12 @@ def test_forward_grad_adam_match_oracle(K):
     # reference on the same FP32-rounded inputs
     P32, X32 = P.astype(np.float32).astype(float), X.astype(np.float32).astype(float)
     z = K.crkdg_mlp_forward(Pd, Xd).cpu().numpy()
-    zo = O.mlp_infer(P32, X32)
-    scale = max(1.0, np.abs(zo).max())
-    assert np.median(np.abs(z - zo)) < 1e-5 * scale
-    assert np.abs(z - zo).max() < 1e-2 * scale
+    zo = O.mlp_forward(P32, X32)
+    bound = mlp_fp32_bound(P32, X32)
+    print(f"[mlp] forward: max |dz| {np.abs(z - zo).max():.3g}, max |dz|/bound "
+          f"{(np.abs(z - zo) / bound).max():.3g}", flush=True)
+    assert np.all(np.abs(z - zo) <= bound)
+    assert np.abs(z - zo).max() > 0.0  # really evaluated in binary32
     g, loss = K.crkdg_mlp_grad(Pd, Xd, yd, 3.0)
     lo, go = O.mlp_loss_grad(P32, X32, y, 3.0)
     g = g.cpu().numpy()
@@ -114,8 +116,8 @@ def test_fallback_band_everywhere_equals_tvb(K):
 
 def test_mlp_decisions_match_oracle(K):
     """band collapsed at 0.5: the MLP alone decides; compare with the oracle's
-    inference-precision MLP on the oracle's features away from the decision
-    boundary"""
+    FP64 network on the oracle's features wherever the logit is further from
+    0 than the binary32 error bound"""
     import torch
     s, om = shock_state(K)
     u = s.crkdg_get_state()
@@ -126,11 +128,13 @@ def test_mlp_decisions_match_oracle(K):
     flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
     s.crkdg_limit_mlp(50.0, Pd, 0.5, 0.5, flags)
     Xo = O.mlp_features(om, 2, 50.0, u)
-    p = 1 / (1 + np.exp(-O.mlp_infer(P.astype(np.float32).astype(float), Xo)))
-    safe = np.abs(p - 0.5) > 2e-3
+    P32 = P.astype(np.float32).astype(float)
+    z = O.mlp_forward(P32, Xo)
+    safe = np.abs(z) > mlp_fp32_bound(P32, Xo)
     fg = (flags.cpu().numpy() & 1) != 0
-    assert safe.mean() > 0.95
-    assert np.array_equal(fg[safe], (p >= 0.5)[safe])
+    print(f"[mlp] decisions compared on {safe.mean():.4f} of the cells", flush=True)
+    assert safe.mean() > 0.99
+    assert np.array_equal(fg[safe], (z >= 0.0)[safe])
 
 
 @pytest.mark.slow

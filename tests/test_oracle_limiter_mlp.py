@@ -195,15 +195,6 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
 
 
-def test_bf16_rounding_ties_to_even():
-    """bfloat16 keeps 8 significand bits: spacing 2^-7 just above 1"""
-    assert O.bf16(1.0 + 2.0 ** -8) == 1.0                      # tie, even neighbour below
-    assert O.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6      # tie, even neighbour above
-    assert O.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
-    assert O.bf16(-(1.0 + 2.0 ** -8)) == -1.0
-    assert O.bf16(0.15625) == 0.15625                          # already representable
-
-
 def hand_network():
     """W1: h1_0 = x0, h1_1 = x1 - 0.5; W2: h2_0 = 3 h1_0 + 5 h1_1, h2_1 = -h1_0;
     output z = 2 h2_0 + 4 h2_1 - 1 (all other weights zero)"""
@@ -230,19 +221,6 @@ def test_mlp_relu_network_by_hand():
     X[1, :2] = [-1.0, 0.25]   # h1 = (0, 0): h2 = (0, 0): z = -1
     X[2, :2] = [-2.0, 1.0]    # h1 = (0, 0.5): h2 = (2.5, 0): z = 4
     assert np.array_equal(O.mlp_forward(P, X), [20.0, -1.0, 4.0])
-    assert np.array_equal(O.mlp_infer(P, X), [20.0, -1.0, 4.0])   # all values bf16-exact
-
-
-def test_mlp_infer_matches_forward_within_bf16():
-    rng = np.random.default_rng(3)
-    P = 0.3 * rng.standard_normal(O.N_MLP_PARAMS)
-    X = rng.standard_normal((200, 12))
-    z64 = O.mlp_forward(P, X)
-    zin = O.mlp_infer(P, X)
-    # bfloat16 carries 2^-9 relative error per rounded value; a few percent of
-    # the logit scale at most
-    assert np.abs(zin - z64).max() < 0.05 * max(1.0, np.abs(z64).max())
-    assert np.abs(zin - z64).max() > 0.0  # the rounding is really applied
 
 
 def test_forced_reconstruction_returns_the_p1_slopes():
