@@ -455,8 +455,8 @@ def main():
         plan += [("fp32-inner + TVB", K.FP32_INNER, None, S)]
         plan += [("fp32-increments + MLP", K.FP32_INCREMENTS, mlp, S)] if mlp is not None else []
         plan += [("fp32-increments + TVB", K.FP32_INCREMENTS, None, S)]
-    head_name = "fp32-bulk + MLP" if mlp is not None else "fp32-bulk + TVB"
-    other_name = head_name.replace("fp32-bulk", "fp32-bulk fused")
+    head_name = "fp32-bulk fused + MLP" if mlp is not None else "fp32-bulk fused + TVB"
+    other_name = head_name.replace("fp32-bulk fused", "fp32-bulk")
     for name, prec, ind, sched in plan:
         forms[name] = run_form(K, W, args, prec, ind, repeats=4 if name == head_name else 0,
                                schedule=sched)
@@ -526,7 +526,7 @@ def main():
                        "roofline": {k: plain["roofline"][k] for k in ("kernel", "achieved", "frac")},
                        "kernels": short_kernels(plain["kernels"])},
         "fp32_bulk_tvb": {"value": tvb32["value"], "ms_per_step": round(tvb32["ms_per_step"], 5)},
-        "fused_schedule": {"form": other_name, "value": other["value"],
+        "split_schedule": {"form": other_name, "value": other["value"],
                            "ms_per_step": round(other["ms_per_step"], 5),
                            "kernels": short_kernels(other["kernels"]),
                            "roofline": {k: other["roofline"][k]
@@ -721,7 +721,7 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
     forms = (("fp64 + TVB", K.FP64, None, False, "crkdg"),
              ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True, "crkdg"),
              ("fp32-bulk + TVB", K.FP32_MIXED, None, False, "crkdg"),
-             ("fp32-bulk + MLP", K.FP32_MIXED, mlp, False, "crkdg"))
+             ("fp32-bulk fused + MLP", K.FP32_MIXED, mlp, False, "crkdg-fused"))
     if full:
         forms += (("fp64 RKDG SSP3 + TVB every stage", K.FP64, None, False, "rkdg3"),
                   ("fp32-inner + TVB", K.FP32_INNER, None, False, "crkdg"),
@@ -777,7 +777,7 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
         return {"L2": "equal" if cand["L2"] <= 1.05 else "not equal",
                 "L1": "equal" if cand["L1"] <= 1.05 else "not equal", "at": f"t={T}"}
 
-    mlp_runs = [per_seed[k]["fp32-bulk + MLP"] for k in per_seed]
+    mlp_runs = [per_seed[k]["fp32-bulk fused + MLP"] for k in per_seed]
     rates = {key: float(np.mean([r[key] for r in mlp_runs]))
              for key in ("fn_rate_vs_tvb", "fp_rate_vs_tvb", "fallback_fraction",
                          "flagged_fraction")}
@@ -789,7 +789,7 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
             "checkpoints": list(checkpoints), "seeds": list(seeds),
             "criterion": "mean over seeds of the density-error ratio to FP64 + TVB at most 1.05",
             "mean_error_ratio_vs_fp64_tvb": ratios, "per_seed": per_seed,
-            "verdict": verdict("fp32-bulk + MLP"),
+            "verdict": verdict("fp32-bulk fused + MLP"),
             "verdict_fp32_increments_mlp": verdict("fp32-increments + MLP") if full else None}
 
 

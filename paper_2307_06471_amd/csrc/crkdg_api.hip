@@ -293,7 +293,7 @@ int crkdg_create(const crkdg_mesh* mesh, int k, int flux, int rk_stages, crkdg_s
   }
   st->lay_stage = st->lay;
   st->S_stage = st->S;
-  st->sched = CRKDG_SCHED_FUSED_DEFAULT;
+  st->sched = CRKDG_SCHED_FUSED;  // taken wherever the one-pass step applies
   st->bound = false;
   st->cur = 0;
   st->t = 0.0;

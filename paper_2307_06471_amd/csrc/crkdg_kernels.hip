@@ -929,13 +929,17 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 //
 // Schedule: the inner stages first (register chain as in k_inner), then the
 // final stage's terms one stage state at a time (u^(1) = u^n, u^(s)):
-// volume term into the update, traces to LDS, face fluxes, and their lift
-// into both neighbours, the cell averages in FP64 (equation (avg)).  The
+// volume term into the update, traces to LDS, face fluxes accumulated into
+// the stage-weighted sum G = sum_i b_i F^(i) (equation (g)) of each face
+// point; finally G is lifted into both neighbours, the cell averages in FP64
+// (equation (avg)).  Tile: 64 x 12 lanes, 62 x 10 owned cells (taller
+// tiles recompute fewer ring cells; twelve waves at 168 registers still fit
+// a compute unit).  The
 // tableau must have nonzero weights b_i only on the first and last stages
 // (scheme (eq:2), scheme (eq:3), forward Euler), so that at most u^n and
 // u^(s) are live; the split kernels take the others.
 #ifndef FUSED_ROWS
-#define FUSED_ROWS 8
+#define FUSED_ROWS 12
 #endif
 constexpr int FUSED_FX = 64, FUSED_FY = FUSED_ROWS;
 constexpr int FUSED_OX = FUSED_FX - 2, FUSED_OY = FUSED_FY - 2;
@@ -1017,12 +1021,48 @@ __global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysD
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) u[c][b] = un[c][b];
-  // inner stages: u^(i+1) = u^n - dt a_{i+1,i} loc(u^(i))
-  if (has) {
+    for (int b = 0; b < NB; ++b) u[c][b] = R(0);  // u^(s), set by the inner stages
+  // The first inner stage and the first final-stage term both need the
+  // volume integral of u^n: Z = (Vx / dx + Vy / dy)(u^n) is evaluated once;
+  // the inner stage takes 0.5 dt a_21 Z, the update 0.5 dt b_1 Z.  The
+  // update's share waits in LDS (free until the first term's traces) while
+  // the inner stages run.
+  const bool share_vol = a.s > 1 && a.w_first != 0.0;
+  R(*park)[NT] = reinterpret_cast<R(*)[NT]>(smem);  // park[NC * (NB - 1)][NT]
+  static_assert(sizeof(R) * NC * (NB - 1) * NT <= SM::BYTES, "the update fits the trace buffer");
+  // inner stages: u^(i+1) = u^n - dt a_{i+1,i} loc(u^(i)); the first one
+  // reads u^(1) = u^n itself
+  if (has && a.s > 1) {
+    R acc[NC][NB];
+    if (share_vol) {
+      R Z[NC][NB];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Z[c][b] = R(0);
+      volume_acc<EQ, K, R>(eq, un, R(g.inv_dx), R(g.inv_dy), Z);
+      const R ci = R(0.5 * dt * a.a_sub[1]), cf = R(0.5 * dt * a.w_first);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[c][b] = un[c][b] + ci * Z[c][b];
+          if (b > 0) park[c * (NB - 1) + b - 1][tid] = un[c][b] + cf * Z[c][b];
+        }
+      loc_face_acc2<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
+      loc_acc<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
 #pragma unroll 1
-    for (int st = 1; st < a.s; ++st) {
-      R acc[NC][NB];
+    for (int st = 2; st < a.s; ++st) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -1035,19 +1075,31 @@ __global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysD
     }
   }
   // the update, started from u^n (higher modes in the compute precision,
-  // the averages in FP64 from memory)
+  // the averages in FP64 from memory), or from u^n plus the first term's
+  // volume share parked above
   R fin[NC][NB];
   double a0[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) fin[c][b] = un[c][b];
+    for (int b = 0; b < NB; ++b)
+      fin[c][b] = share_vol && has && b > 0 ? park[c * (NB - 1) + b - 1][tid] : un[c][b];
     a0[c] = owned ? load_avg<NC, NB, LAY>(a.un, g.N, c, cell) : 0.0;
   }
+  if (share_vol) __syncthreads();  // every lane has its share before the traces overwrite it
 
-  // one final-stage term: stage state U with weight w
-  auto final_term = [&](const R(&U)[NC][NB], const double w) {
-    if (owned) {
+  // stage-weighted face fluxes G of this lane's face points (FP32: both
+  // cells of a face use the same value, so the FP64 averages stay
+  // conservative)
+  R Gp[NPASS][NC];
+#pragma unroll
+  for (int k = 0; k < NPASS; ++k)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Gp[k][c] = R(0);
+  // one final-stage term: stage state U with weight w (volume term into the
+  // update, traces to LDS, the weighted fluxes into G)
+  auto final_term = [&](const R(&U)[NC][NB], const double w, const bool volume) {
+    if (owned && volume) {
       const R vs = R(0.5 * dt * w);
       volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), fin);
     }
@@ -1110,9 +1162,10 @@ __global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysD
         }
     }
     __syncthreads();
-    // every face point of the tile once; the flux replaces the lower/left
-    // trace in LDS (each point belongs to one lane)
+    // every face point of the tile once: this lane's stage-weighted sum
+    // G = sum_i b_i F^(i) (equation (g)) gathers the point's flux
     const bool full = nax == OX && nay == OY;
+    const R wr = R(w);
 #pragma unroll
     for (int k = 0; k < NPASS; ++k) {
       const int f = tid + k * NT;
@@ -1126,7 +1179,7 @@ __global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysD
         valid = dy ? (fx < nax && fy <= nay) : (fx <= nax && fy < nay);
       }
       if (valid) {
-        R* A = dy ? tTf : tRf;
+        const R* A = dy ? tTf : tRf;
         const R* B = dy ? tBf : tLf;
         const int cs = dy ? CSY : CSX;
         R qa[NC], qb[NC], F[NC];
@@ -1137,41 +1190,54 @@ __global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysD
         }
         eq.num_flux_d(qa, qb, dy, F);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) A[c * cs + e] = F[c];
+        for (int c = 0; c < NC; ++c) Gp[k][c] = Gp[k][c] + wr * F[c];
       }
-    }
-    __syncthreads();
-    if (owned) {
-      R FL[NC][Q], FR[NC][Q], GB[NC][Q], GT[NC][Q];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          FL[c][p] = tR[c * Q + p][ly - 1][lx - 1];
-          FR[c][p] = tR[c * Q + p][ly - 1][lx];
-          GB[c][p] = tT[c * Q + p][ly - 1][lx - 1];
-          GT[c][p] = tT[c * Q + p][ly][lx - 1];
-        }
-      // cell averages in FP64 (equation (avg)) from this stage's fluxes
-      const double lxs = -0.5 * dt * w * g.inv_dx, lys = -0.5 * dt * w * g.inv_dy;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        double sx = 0.0, sy = 0.0;
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          sx += T.W[p] * ((double)FR[c][p] - (double)FL[c][p]);
-          sy += T.W[p] * ((double)GT[c][p] - (double)GB[c][p]);
-        }
-        a0[c] += lxs * sx + lys * sy;
-      }
-      lift_x<EQ, K, R>(FR, FL, R(lxs), fin);
-      lift_y<EQ, K, R>(GT, GB, R(lys), fin);
     }
     __syncthreads();  // the next term overwrites the traces
   };
   // (the weights are kernel arguments: the branches are uniform)
-  if (a.w_first != 0.0) final_term(un, a.w_first);
-  if (a.w_last != 0.0) final_term(u, a.w_last);
+  if (a.w_first != 0.0) final_term(un, a.w_first, !share_vol);
+  if (a.w_last != 0.0) final_term(u, a.w_last, true);
+  // G to LDS over the lower/left traces (each point belongs to one lane)
+#pragma unroll
+  for (int k = 0; k < NPASS; ++k) {
+    const int f = tid + k * NT;
+    if (f >= NFP) break;
+    const bool dy = f >= NXP;
+    const int e = dy ? f - NXP : f;
+    R* A = dy ? tTf : tRf;
+    const int cs = dy ? CSY : CSX;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) A[c * cs + e] = Gp[k][c];
+  }
+  __syncthreads();
+  if (owned) {
+    R FL[NC][Q], FR[NC][Q], GB[NC][Q], GT[NC][Q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        FL[c][p] = tR[c * Q + p][ly - 1][lx - 1];
+        FR[c][p] = tR[c * Q + p][ly - 1][lx];
+        GB[c][p] = tT[c * Q + p][ly - 1][lx - 1];
+        GT[c][p] = tT[c * Q + p][ly][lx - 1];
+      }
+    // cell averages in FP64 (equation (avg)): each face's G converted
+    // exactly, so both cells of a face subtract / add the same value
+    const double lxs = -0.5 * dt * g.inv_dx, lys = -0.5 * dt * g.inv_dy;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        sx += T.W[p] * ((double)FR[c][p] - (double)FL[c][p]);
+        sy += T.W[p] * ((double)GT[c][p] - (double)GB[c][p]);
+      }
+      a0[c] += lxs * sx + lys * sy;
+    }
+    lift_x<EQ, K, R>(FR, FL, R(lxs), fin);
+    lift_y<EQ, K, R>(GT, GB, R(lys), fin);
+  }
   if (owned) store_state<R, NC, NB, LAY>(a.out, g.N, cell, fin, a0);
 }
 

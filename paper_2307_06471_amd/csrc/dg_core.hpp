@@ -562,6 +562,29 @@ __device__ __forceinline__ void trace_flux(const EQ& eq, const R (&tr)[EQ::NC][N
   }
 }
 
+// acc += scale * (the face part of loc(U)) in 2D: the cell's own traces'
+// physical flux on its four faces, lifted (equation (dxl))
+template <class EQ, int K, class R>
+__device__ __forceinline__ void loc_face_acc2(const EQ& eq, const R (&U)[EQ::NC][Sizes<K, 2>::NB],
+                                              R scale, R inv_dx, R inv_dy,
+                                              R (&acc)[EQ::NC][Sizes<K, 2>::NB]) {
+  constexpr int NP = K + 1;
+  const R hx = R(0.5) * scale * inv_dx, hy = R(0.5) * scale * inv_dy;
+  R t0[EQ::NC][NP], t1[EQ::NC][NP], F0[EQ::NC][NP], F1[EQ::NC][NP];
+  trace_x<+1, EQ, K, R>(U, t0);
+  trace_x<-1, EQ, K, R>(U, t1);
+  trace_flux<0, EQ, NP, R>(eq, t0, F0);
+  trace_flux<0, EQ, NP, R>(eq, t1, F1);
+  lift_x<EQ, K, R>(F0, F1, hx, acc);
+  CRK_FENCE();
+  trace_y<+1, EQ, K, R>(U, t0);
+  trace_y<-1, EQ, K, R>(U, t1);
+  trace_flux<1, EQ, NP, R>(eq, t0, F0);
+  trace_flux<1, EQ, NP, R>(eq, t1, F1);
+  lift_y<EQ, K, R>(F0, F1, hy, acc);
+  CRK_FENCE();
+}
+
 // acc += scale * loc(U), the local operator of equation (dxl):
 // volume term plus the cell's own traces' physical flux on its faces.
 template <class EQ, int K, class R>
@@ -572,19 +595,7 @@ __device__ __forceinline__ void loc_acc(const EQ& eq, const R (&U)[EQ::NC][Sizes
   if constexpr (EQ::DIM == 2) {
     const R hx = R(0.5) * scale * inv_dx, hy = R(0.5) * scale * inv_dy;
     volume_acc<EQ, K, R>(eq, U, -hx, -hy, acc);
-    R t0[EQ::NC][NP], t1[EQ::NC][NP], F0[EQ::NC][NP], F1[EQ::NC][NP];
-    trace_x<+1, EQ, K, R>(U, t0);
-    trace_x<-1, EQ, K, R>(U, t1);
-    trace_flux<0, EQ, NP, R>(eq, t0, F0);
-    trace_flux<0, EQ, NP, R>(eq, t1, F1);
-    lift_x<EQ, K, R>(F0, F1, hx, acc);
-    CRK_FENCE();
-    trace_y<+1, EQ, K, R>(U, t0);
-    trace_y<-1, EQ, K, R>(U, t1);
-    trace_flux<1, EQ, NP, R>(eq, t0, F0);
-    trace_flux<1, EQ, NP, R>(eq, t1, F1);
-    lift_y<EQ, K, R>(F0, F1, hy, acc);
-    CRK_FENCE();
+    loc_face_acc2<EQ, K, R>(eq, U, scale, inv_dx, inv_dy, acc);
   } else {
     const R hx = scale * inv_dx;
     volume_acc<EQ, K, R>(eq, U, -hx, R(0), acc);

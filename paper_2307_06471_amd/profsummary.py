@@ -104,7 +104,9 @@ def counters(csv_path, kernels, out, command, simds=1024, xcds=8):
         lifetime spent waiting for memory results)
     and, when counted, mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (simds *
     GRBM_GUI_ACTIVE / xcds) and mfma_bf16_flop = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16
-    per dispatch"""
+    per dispatch; with the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64} counters,
+    the executed vector flops per dispatch (64 lanes per instruction, two
+    flops per FMA)"""
     rows = list(csv.DictReader(open(csv_path)))
     lines = [f"# SQ counters per dispatch", "",
              "command (repo root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):",
@@ -134,6 +136,12 @@ def counters(csv_path, kernels, out, command, simds=1024, xcds=8):
             lines.append(f"  mfma_busy: {mb:.4f}")
         if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in avg:
             lines.append(f"  mfma_bf16_flop: {avg['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512:.4g}")
+        for prec in ("F32", "F64"):
+            keys = [f"SQ_INSTS_VALU_{op}_{prec}" for op in ("ADD", "MUL", "FMA", "TRANS")]
+            if all(k in avg for k in keys):
+                # instructions count per wavefront: 64 lanes each; an FMA is 2 flops
+                fl = 64.0 * (avg[keys[0]] + avg[keys[1]] + 2.0 * avg[keys[2]] + avg[keys[3]])
+                lines.append(f"  valu_{prec.lower()}_flop: {fl:.6g}")
         if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
             lines.append(f"  wait_fraction: {avg['SQ_WAIT_INST_ANY'] / avg['SQ_WAVE_CYCLES']:.3f}")
         lines.append("")

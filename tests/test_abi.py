@@ -290,15 +290,17 @@ def test_schedule_selection_is_host_logic():
         return K.crkdg_create(m, k, K.FLUX_LLF, stages)
 
     h = handle()
-    assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT            # the default
+    assert L.crkdg_get_schedule(h) == K.SCHED_FUSED            # the default where it applies
+    assert L.crkdg_set_schedule(h, K.SCHED_SPLIT) == K.CRKDG_OK
+    assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT
+    assert L.crkdg_set_schedule(h, 7) == K.CRKDG_EINVAL
     assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_OK
     assert L.crkdg_get_schedule(h) == K.SCHED_FUSED
-    assert L.crkdg_set_schedule(h, 7) == K.CRKDG_EINVAL
-    assert L.crkdg_set_schedule(h, K.SCHED_SPLIT) == K.CRKDG_OK
     L.crkdg_destroy(h)
     for kw in (dict(precision=K.FP64), dict(k=3), dict(stages=4),
                dict(precision=K.FP32_INNER), dict(bc=(2, 1, 2, 2), bc_exact=K.IC_DMR)):
         h = handle(**kw)
+        assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT, kw      # falls back by itself
         assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_EUNSUPPORTED, kw
         assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT
         L.crkdg_destroy(h)

@@ -307,13 +307,22 @@ def l2_rel(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
 
 
+@pytest.mark.parametrize("sched", ["split", "fused"])
 @pytest.mark.parametrize("k,tab,stages", [(2, "eq3", 3), (3, "rk4", 4), (1, "eq2", 2)])
-def test_mixed_density_wave_run(K, k, tab, stages):
+def test_mixed_density_wave_run(K, k, tab, stages, sched):
     """density-wave workload (Section 4.1.2 example), 48 x 40 cells, 60 steps:
     the FP32-bulk form stays within 1e-5 relative L2 of the FP64 oracle, its
-    cell averages stay FP64 and the sums are conserved to FP64 round-off"""
+    cell averages stay FP64 and the sums are conserved to FP64 round-off; in
+    both step schedules (RK4 has weights on every stage, so it always takes
+    the split one)"""
     cfg = dict(W.config("c3"), nx=48, ny=40)
     s, om = mixed_solver(K, cfg, k, stages)
+    if sched == "split":
+        s.crkdg_set_schedule(K.SCHED_SPLIT)
+    elif tab != "rk4":
+        s.crkdg_set_schedule(K.SCHED_FUSED)
+    assert s.crkdg_get_schedule() == (K.SCHED_FUSED if sched == "fused" and tab != "rk4"
+                                      else K.SCHED_SPLIT)
     P = cfg["ic_params"]
     s.crkdg_project(K.IC_EULER_WAVE, P)
     u = O.project(om, k, O.IC_EULER_WAVE, P)
