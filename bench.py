@@ -34,6 +34,13 @@ METRIC = "2D Euler cRKDG DOF-updates/s: FP32+learned limiter vs FP64 plain, equa
 FN_TARGET = 0.005  # band: false negatives against TVB on validation (1% is the goal in use)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 4 SIMDs x 32 FMA lanes x 2 x 2.4 GHz)
+# FP32 vector flops one step needs per cell (Q2 Euler, scheme eq3): the
+# executed flops of the split schedule's inner and final kernels on the
+# 4096 x 1024 shock workload, which evaluate every cell's stages once
+# (profiles/shock_4096x1024_q2_flop_counters.txt: 1.546e10 + 1.612e10 per
+# launch over 4194304 cells)
+STEP_FLOP_PER_CELL = 7529.0
 
 
 def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final, scheme="crkdg"):
@@ -635,6 +642,18 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg", repeats=0, schedul
             "bytes_per_launch": by}
     if traffic is not None:
         roof["traffic_over_algorithmic"] = round(traffic / by, 3)
+    if dom == "fused" and cfg["k"] == 2:
+        # the one-pass step does all of a step's arithmetic for 2S bytes per
+        # cell (23.5 flop/B, above the FP32 ridge of 19.7 flop/B): ALU-bound
+        fl = STEP_FLOP_PER_CELL * s.ncells
+        tf = fl / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": dom, "flop_per_launch": fl, "bytes_per_launch": by,
+                "hbm_achieved_GBs": round(achieved, 1),
+                "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
+        if traffic is not None:
+            roof["traffic_over_algorithmic"] = round(traffic / by, 3)
     return {"value": dofs * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
             "repeat_ms_per_step": rep_ms,
             "roofline": roof, "kernels": kern, "flagged_cells_end": n_flag,

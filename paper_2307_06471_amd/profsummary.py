@@ -61,6 +61,9 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, out, command):
     res = {}
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _per_dispatch(path, counter)
+        names = {r["Kernel_Name"] for r in rows if kernel in r["Kernel_Name"]}
+        if len(names) > 1:  # one template instance per summary
+            raise SystemExit(f"{kernel!r} matches {len(names)} kernels in {path}")
         kern = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
         copies = [r for r in rows if "copy" in r["Kernel_Name"].lower()]
         if not kern or not copies:

@@ -21,6 +21,11 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.stdout == ""
 
 
+def test_algorithmic_bytes_of_the_fused_step():
+    S, N = 160, 1000
+    assert bench.algorithmic_bytes("fused", S * N, S * N, N, 2) == 2 * S * N
+
+
 def test_algorithmic_bytes_of_the_step_kernels():
     S, N = 160, 1000  # FP32-bulk Q2 state bytes per cell x cells
     state = S * N
@@ -46,11 +51,15 @@ def test_traffic_summary_round_trip_and_source_gate(tmp_path):
 
 
 def test_committed_traffic_summaries_parse():
-    for tag in ("fp32", "fp64"):
-        d = PS.read_traffic(os.path.join(ROOT, "profiles", f"k_final2_{tag}_traffic.txt"))
+    import glob
+    files = glob.glob(os.path.join(ROOT, "profiles", "k_*_traffic.txt"))
+    assert any(f.endswith("k_fused2_fp32_traffic.txt") for f in files)
+    for f in files:
+        d = PS.read_traffic(f)
         assert d is not None
         assert float(d["traffic_bytes_per_launch"]) > 0
         assert float(d["fetch_factor"]) > 0 and float(d["write_factor"]) > 0
+        assert d["fetch_dispatches"] == d["write_dispatches"]
 
 
 def test_indicator_file_round_trip(tmp_path):
@@ -97,6 +106,17 @@ def test_traffic_calibration_arithmetic(tmp_path):
     assert float(d["write_bytes_per_launch"]) == 500.0 * 1024
     assert float(d["traffic_bytes_per_launch"]) == 1100.0 * 2048 + 500.0 * 1024
     assert d["fetch_dispatches"] == "2"
+
+
+def test_traffic_refuses_a_name_matching_several_kernels(tmp_path):
+    import pytest
+    f = tmp_path / "f.csv"
+    with open(f, "w") as fh:
+        fh.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+        fh.write('"void k_final2<A, 2, 1, false, false>(x)",64,FETCH_SIZE,1\n')
+        fh.write('"void k_final2<A, 2, 0, false, false>(x)",64,FETCH_SIZE,1\n')
+    with pytest.raises(SystemExit):
+        PS.traffic(str(f), str(f), "k_final2<A", 1 << 20, str(tmp_path / "o.txt"), "cmd")
 
 
 def test_counter_summary_ratios(tmp_path):
