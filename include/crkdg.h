@@ -187,9 +187,9 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
 /* Schedule of crkdg_step / crkdg_step_dev.  The compact stencil of Section
  * 3.1 (a step reaches only the face neighbours of a cell, for any number of
  * stages, because the inner stages are element local) lets one kernel do
- * the whole step on a tile plus a one-cell ring: read u^n once, recompute
- * the ring's inner stages, evaluate the tile's faces, write u^{n+1}; no
- * stage state goes through memory.
+ * the whole step on a strip of cells plus a one-cell ring: read u^n once,
+ * recompute the ring's inner stages, evaluate the strip's faces, write
+ * u^{n+1}; no stage state goes through memory.
  *   CRKDG_SCHED_SPLIT  inner-stage pass, then final-stage pass (any case);
  *   CRKDG_SCHED_FUSED  the one-pass step, for 2D Euler in the FP32-bulk
  *                      form with k = 1 or 2, constant boundary data
@@ -207,7 +207,7 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
  * later crkdg_set_tableau can make a fused handle fall back to the split
  * schedule).  New handles start with CRKDG_SCHED_FUSED: every step that the
  * one-pass kernel can take runs there (on the 4096 x 1024 Q2 shock workload
- * it takes 0.77 ms against 0.93 ms for the two split passes). */
+ * it takes 0.68 ms against 0.93 ms for the two split passes). */
 #define CRKDG_SCHED_SPLIT 0
 #define CRKDG_SCHED_FUSED 1
 int crkdg_set_schedule(crkdg_state* st, int sched);

@@ -105,6 +105,7 @@ struct FusedArgs {
   double w_first, w_last;  // b_1 and b_s (s = 1: w_first only)
   double dt;
   const double* dt_ptr;
+  int strip;             // rows a workgroup marches over (set by the launcher)
 };
 
 // one inner stage of a full tableau (FP64 layout): L_{i-1} = loc(in), stored

@@ -54,9 +54,6 @@
 #ifndef FINAL_OCC_F64
 #define FINAL_OCC_F64 1
 #endif
-#ifndef FUSED_OCC
-#define FUSED_OCC 2
-#endif
 #ifndef FINAL_TX_F32
 #define FINAL_TX_F32 64
 #endif
@@ -910,335 +907,380 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 // ---------------------------------------------------------------------------
 // A cRKDG step reaches only the face neighbours of a cell, whatever the
 // number of stages: the inner stages are element local and only the final
-// stage couples neighbours (Section 3.1).  So a workgroup can read u^n of its
-// tile plus a one-cell ring, compute every inner stage of the ring cells
-// itself, evaluate the shared faces, and write u^{n+1} of the tile: one read
-// of u^n and one write of u^{n+1} per step, no stage state in memory.
+// stage couples neighbours (Section 3.1).  So a workgroup can read u^n of
+// its cells plus a one-cell ring, compute every inner stage of the ring cells
+// itself, evaluate the shared faces, and write u^{n+1}: one read of u^n and
+// one write of u^{n+1} per step, no stage state in memory.
 //
-// Workgroup: FX x FY lanes, one cell each: the owned OX x OY tile
-// (OX = FX - 2, OY = FY - 2) and its ring, corners unused.  A ring cell
-// outside the mesh has no lane work: with a non-periodic side its trace on
-// the boundary face is written by the owned cell next to it (transmissive:
-// its own trace; Dirichlet: the boundary state), as in the final-stage
-// kernel.  Every face of the tile is evaluated by one lane per quadrature
-// point in canonical (+x / +y) orientation; a face shared with a
-// neighbouring tile is evaluated by both with the same code on the same
-// traces (the ring cell's inner stages are computed by the same instructions
-// as by its owner), so both see the same bits and the cell averages stay
-// conservative.
-//
-// Schedule: the inner stages first (register chain as in k_inner), then the
-// final stage's terms one stage state at a time (u^(1) = u^n, u^(s)):
-// volume term into the update, traces to LDS, face fluxes accumulated into
-// the stage-weighted sum G = sum_i b_i F^(i) (equation (g)) of each face
-// point; finally G is lifted into both neighbours, the cell averages in FP64
-// (equation (avg)).  Tile: 64 x 12 lanes, 62 x 10 owned cells (taller
-// tiles recompute fewer ring cells; twelve waves at 168 registers still fit
-// a compute unit).  The
-// tableau must have nonzero weights b_i only on the first and last stages
-// (scheme (eq:2), scheme (eq:3), forward Euler), so that at most u^n and
-// u^(s) are live; the split kernels take the others.
-#ifndef FUSED_ROWS
-#define FUSED_ROWS 12
+// A workgroup of four wavefronts walks up a strip of 62 columns: wavefront w
+// holds row 4t + w in iteration t, one lane per cell of a 64-cell row (the 62
+// owned cells and the two ring cells).  Walking reuses each row's traces for
+// the face above it, so only the strip's two end rows and the two ring
+// columns are recomputed ((H + 2) / H x 64 / 62 of the work for a strip of H
+// rows).  A ring cell outside the mesh has no lane work: across a
+// non-periodic side the boundary face takes the boundary rule (transmissive:
+// the owned cell's own trace; Dirichlet: the boundary state).  Every face is
+// evaluated in canonical (+x / +y) orientation; a face shared with another
+// strip is evaluated by both with the same code on the same traces (a ring
+// cell's inner stages are computed by the same instructions as by its
+// owner), so both see the same bits and the FP64 cell averages stay
+// conservative (equation (avg)).  Per iteration:
+//   P1  (no barrier) u^n and the inner stages (register chain); the first
+//       inner stage and the first final-stage term share u^n's volume
+//       integral; the volume terms of u^n and u^(s); the x faces of the row:
+//       right traces pass to the next lane by a lane shift, a lane evaluates
+//       its left face and passes the stage-weighted flux G = sum_i b_i F^(i)
+//       (equation (g)) back for its left neighbour's right face; the row's
+//       top traces (of u^n and u^(s)) go to the row's LDS slot, its bottom
+//       traces stay in registers;
+//   P2  (after a barrier) the face below each row: the row's own bottom
+//       traces against the top traces of the row below; G lifts into the
+//       row's own update as its bottom face and goes to LDS, over the traces
+//       it has read, for the row below as its top face;
+//   P3  (after a barrier) rows 4t .. 4t + 2 take their top face and are
+//       stored; row 4t + 3 waits in LDS for the face the next iteration's
+//       first wavefront evaluates, and is stored then.
+// Slots: wavefronts 0 - 2 own slots 0 - 2; wavefront 3 alternates between
+// slots 3 and 4, so that its row's traces survive into the next iteration's
+// P2 while the next iteration's wavefront 3 writes its own.  While the inner
+// stages run, a wavefront's own next slot holds the update's share of the
+// volume integral.  The tableau must have nonzero weights b_i only on the
+// first and last stages (scheme (eq:2), scheme (eq:3), forward Euler), so
+// that at most u^n and u^(s) are live; the split kernels take the others.
+// Tuning (measured on the 4096 x 1024 Q2 shock workload): strips of 30 rows
+// (46 the same; 14 and 62 slower: more recomputed rows, or too few
+// workgroups for an even last wave), and two wavefronts per SIMD: the kernel
+// needs 221 registers, and forcing three (168 registers) spills 53 values and
+// ran 1.8x slower.
+#ifndef MARCH_H
+#define MARCH_H 30
 #endif
-constexpr int FUSED_FX = 64, FUSED_FY = FUSED_ROWS;
-constexpr int FUSED_OX = FUSED_FX - 2, FUSED_OY = FUSED_FY - 2;
+#ifndef MARCH_OCC
+#define MARCH_OCC 2
+#endif
 
-template <class R, int NV>
-struct FusedSmem {
-  // x faces: OY rows of OX + 1 faces; y faces: OY + 1 rows of OX faces
-  static constexpr int NXF = NV * FUSED_OY * (FUSED_OX + 1);
-  static constexpr int NYF = NV * (FUSED_OY + 1) * FUSED_OX;
-  static constexpr size_t BYTES = sizeof(R) * 2 * (NXF + NYF);
+template <class R, int NC, int Q>
+struct MarchSmem {
+  static constexpr int NB = Q * Q;
+  static constexpr int TRACES = 2 * NC * Q * 64;    // top traces of both states, [s][c][p][lane]
+  static constexpr int SHARE = NC * (NB - 1) * 64;  // the update's volume share, [c][mode][lane]
+  static constexpr int SLOTF = TRACES > SHARE ? TRACES : SHARE;
+  static constexpr int NSLOT = 5;
+  // the parked row: FP64 averages [c][lane], higher modes [c][mode][lane],
+  // the bottom-face G [c][p][lane]
+  static constexpr size_t PARK_BYTES = sizeof(double) * NC * 64 + sizeof(R) * (NC * (NB - 1) + NC * Q) * 64;
+  static constexpr size_t BYTES = PARK_BYTES + sizeof(R) * NSLOT * SLOTF;
 };
 
+__device__ __forceinline__ int march_slot(int ry) {
+  return (ry & 3) == 3 ? 3 + ((ry >> 2) & 1) : (ry & 3);
+}
+
 template <class EQ, int K>
-__global__ __launch_bounds__(FUSED_FX * FUSED_FY, FUSED_OCC) void k_fused2(PhysDev ph, Geo g, BCDev bc,
-                                                                   FusedArgs a) {
+__global__ __launch_bounds__(256, MARCH_OCC) void k_fused2(PhysDev ph, Geo g, BCDev bc, FusedArgs a) {
   using R = typename EQ::Real;
   constexpr int LAY = StepLayout<EQ>::value;
-  constexpr int FX = FUSED_FX, OX = FUSED_OX, OY = FUSED_OY, NT = FUSED_FX * FUSED_FY;
-  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q, NV = NC * Q;
-  using SM = FusedSmem<R, NV>;
-  constexpr int NXP = Q * (OX + 1) * OY, NFP = NXP + Q * OX * (OY + 1);
-  constexpr int NPASS = (NFP + NT - 1) / NT;
-  constexpr int CSX = Q * OY * (OX + 1), CSY = Q * (OY + 1) * OX;
+  constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q;
+  using SM = MarchSmem<R, NC, Q>;
   constexpr GTab<Q> T = Tab<Q>::t;
   __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
-  // tR[v][y][x]: right trace of cell x - 1 (x = 0: the left ring cell);
-  // tL: left trace of cell x; tT[v][y][x]: top trace of row y - 1;
-  // tB: bottom trace of row y (tile coordinates of the owned cells)
-  R(*tR)[OY][OX + 1] = reinterpret_cast<R(*)[OY][OX + 1]>(smem);
-  R(*tL)[OY][OX + 1] = reinterpret_cast<R(*)[OY][OX + 1]>(smem + sizeof(R) * SM::NXF);
-  R(*tT)[OY + 1][OX] = reinterpret_cast<R(*)[OY + 1][OX]>(smem + sizeof(R) * 2 * SM::NXF);
-  R(*tB)[OY + 1][OX] =
-      reinterpret_cast<R(*)[OY + 1][OX]>(smem + sizeof(R) * (2 * SM::NXF + SM::NYF));
-  R* tRf = &tR[0][0][0];
-  R* tLf = &tL[0][0][0];
-  R* tTf = &tT[0][0][0];
-  R* tBf = &tB[0][0][0];
+  double* pa0 = reinterpret_cast<double*>(smem);                  // [NC][64]
+  R* pfin = reinterpret_cast<R*>(smem + sizeof(double) * NC * 64);  // [NC * (NB - 1)][64]
+  R* pgb = pfin + NC * (NB - 1) * 64;                               // [NC * Q][64]
+  R* slots = reinterpret_cast<R*>(smem + SM::PARK_BYTES);           // [NSLOT][SLOTF]
 
-  const int tid = threadIdx.x, lx = tid % FX, ly = tid / FX;
-  const int i0 = blockIdx.x * OX, j0 = blockIdx.y * OY;
-  const int nax = min(OX, g.nx - i0), nay = min(OY, g.ny - j0);
-  const bool owned = lx >= 1 && lx <= nax && ly >= 1 && ly <= nay;
-  const bool ringx = (lx == 0 || lx == nax + 1) && ly >= 1 && ly <= nay;
-  const bool ringy = (ly == 0 || ly == nay + 1) && lx >= 1 && lx <= nax;
-  int i = i0 - 1 + lx, j = j0 - 1 + ly;
-  bool has = owned;
-  if (ringx || ringy) {
-    // a ring cell outside the mesh exists only across a periodic side
-    const bool outx = i < 0 || i >= g.nx, outy = j < 0 || j >= g.ny;
-    has = true;
-    if (outx) {
-      if (bc.type[i < 0 ? 0 : 1] == CRKDG_BC_PERIODIC) i = i < 0 ? i + g.nx : i - g.nx;
-      else has = false;
-    }
-    if (outy) {
-      if (bc.type[j < 0 ? 2 : 3] == CRKDG_BC_PERIODIC) j = j < 0 ? j + g.ny : j - g.ny;
-      else has = false;
-    }
-  }
-  const long long cell = (long long)j * g.nx + i;
+  const int lx = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 62, j0 = blockIdx.y * a.strip;
+  const int nax = min(62, g.nx - i0), nh = min(a.strip, g.ny - j0);
+  const int nrows = nh + 2, niter = (nrows + 3) / 4;
   const EQ eq = make_eq<EQ>(ph);
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
-  // boundary sides of an owned cell whose exterior traces it provides
-  const int bl = owned && i == 0 && bc.type[0] != CRKDG_BC_PERIODIC ? bc.type[0] : -1;
-  const int br = owned && i == g.nx - 1 && bc.type[1] != CRKDG_BC_PERIODIC ? bc.type[1] : -1;
-  const int bb = owned && j == 0 && bc.type[2] != CRKDG_BC_PERIODIC ? bc.type[2] : -1;
-  const int bt = owned && j == g.ny - 1 && bc.type[3] != CRKDG_BC_PERIODIC ? bc.type[3] : -1;
-
-  // u^n in the compute precision (kept: every inner stage starts from it),
-  // and the last stage state
-  R un[NC][NB], u[NC][NB];
-  if (has) load_state<R, NC, NB, LAY>(a.un, g.N, cell, un);
-  else {
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) un[c][b] = R(0);
-  }
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) u[c][b] = R(0);  // u^(s), set by the inner stages
-  // The first inner stage and the first final-stage term both need the
-  // volume integral of u^n: Z = (Vx / dx + Vy / dy)(u^n) is evaluated once;
-  // the inner stage takes 0.5 dt a_21 Z, the update 0.5 dt b_1 Z.  The
-  // update's share waits in LDS (free until the first term's traces) while
-  // the inner stages run.
   const bool share_vol = a.s > 1 && a.w_first != 0.0;
-  R(*park)[NT] = reinterpret_cast<R(*)[NT]>(smem);  // park[NC * (NB - 1)][NT]
-  static_assert(sizeof(R) * NC * (NB - 1) * NT <= SM::BYTES, "the update fits the trace buffer");
-  // inner stages: u^(i+1) = u^n - dt a_{i+1,i} loc(u^(i)); the first one
-  // reads u^(1) = u^n itself
-  if (has && a.s > 1) {
-    R acc[NC][NB];
-    if (share_vol) {
-      R Z[NC][NB];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) Z[c][b] = R(0);
-      volume_acc<EQ, K, R>(eq, un, R(g.inv_dx), R(g.inv_dy), Z);
-      const R ci = R(0.5 * dt * a.a_sub[1]), cf = R(0.5 * dt * a.w_first);
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[c][b] = un[c][b] + ci * Z[c][b];
-          if (b > 0) park[c * (NB - 1) + b - 1][tid] = un[c][b] + cf * Z[c][b];
-        }
-      loc_face_acc2<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
-    } else {
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
-      loc_acc<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
+  const R wf = R(a.w_first), wl = R(a.w_last);
+  const double lxs = -0.5 * dt * g.inv_dx, lys = -0.5 * dt * g.inv_dy;
+  const bool perx = bc.type[0] == CRKDG_BC_PERIODIC, pery = bc.type[2] == CRKDG_BC_PERIODIC;
+  // the lane's column: owned (1 .. nax), ring (0, nax + 1) or unused
+  const bool colown = lx >= 1 && lx <= nax;
+  int i = i0 - 1 + lx;
+  bool colhas = colown;  // a ring column holds cells inside the mesh or across a periodic side
+  if (lx == 0 || lx == nax + 1) {
+    colhas = (i >= 0 && i < g.nx) || perx;
+    if (i < 0) i += g.nx;
+    if (i >= g.nx) i -= g.nx;
+  }
+  // the left neighbour lane's column (for the lane's left face)
+  const bool lefthas = lx >= 2 ? true : (lx == 1 ? ((i0 - 1 >= 0) || perx) : false);
+  const bool bl = colown && i == 0 && !perx, br = colown && i == g.nx - 1 && !perx;
+
+#pragma unroll 1
+  for (int t = 0; t < niter; ++t) {
+    const int ry = 4 * t + w;
+    const bool rowvalid = ry < nrows;
+    const bool rowown = ry >= 1 && ry <= nh;
+    int j = j0 - 1 + ry;
+    bool rowhas = rowown;
+    if (rowvalid && !rowown) {
+      rowhas = (j >= 0 && j < g.ny) || pery;
+      if (j < 0) j += g.ny;
+      if (j >= g.ny) j -= g.ny;
     }
+    // ring rows hold only the owned columns; ring columns only owned rows
+    const bool has = rowvalid && ((rowown && colhas && (colown || lx == 0 || lx == nax + 1)) ||
+                                  (!rowown && rowhas && colown));
+    const bool owned = rowown && colown;
+    const long long cell = (long long)j * g.nx + i;
+    const bool bb = owned && j == 0 && !pery, bt = owned && j == g.ny - 1 && !pery;
+    R* slot = slots + march_slot(ry) * SM::SLOTF;
+
+    // ---- P1: inner stages, x faces, traces ----
+    R un[NC][NB], u[NC][NB];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
-#pragma unroll 1
-    for (int st = 2; st < a.s; ++st) {
+      for (int b = 0; b < NB; ++b) u[c][b] = R(0);
+    if (has) load_state<R, NC, NB, LAY>(a.un, g.N, cell, un);
+    else {
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
-      loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[st]), R(g.inv_dx), R(g.inv_dy), acc);
+        for (int b = 0; b < NB; ++b) un[c][b] = R(0);
+    }
+    if (has && a.s > 1) {
+      R acc[NC][NB];
+      if (share_vol) {
+        R Z[NC][NB];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) Z[c][b] = R(0);
+        volume_acc<EQ, K, R>(eq, un, R(g.inv_dx), R(g.inv_dy), Z);
+        const R ci = R(0.5 * dt * a.a_sub[1]), cf = R(0.5 * dt * a.w_first);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            acc[c][b] = un[c][b] + ci * Z[c][b];
+            if (b > 0) slot[(c * (NB - 1) + b - 1) * 64 + lx] = un[c][b] + cf * Z[c][b];
+          }
+        loc_face_acc2<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
+        loc_acc<EQ, K, R>(eq, un, R(-dt * a.a_sub[1]), R(g.inv_dx), R(g.inv_dy), acc);
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
-    }
-  }
-  // the update, started from u^n (higher modes in the compute precision,
-  // the averages in FP64 from memory), or from u^n plus the first term's
-  // volume share parked above
-  R fin[NC][NB];
-  double a0[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      fin[c][b] = share_vol && has && b > 0 ? park[c * (NB - 1) + b - 1][tid] : un[c][b];
-    a0[c] = owned ? load_avg<NC, NB, LAY>(a.un, g.N, c, cell) : 0.0;
-  }
-  if (share_vol) __syncthreads();  // every lane has its share before the traces overwrite it
-
-  // stage-weighted face fluxes G of this lane's face points (FP32: both
-  // cells of a face use the same value, so the FP64 averages stay
-  // conservative)
-  R Gp[NPASS][NC];
-#pragma unroll
-  for (int k = 0; k < NPASS; ++k)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) Gp[k][c] = R(0);
-  // one final-stage term: stage state U with weight w (volume term into the
-  // update, traces to LDS, the weighted fluxes into G)
-  auto final_term = [&](const R(&U)[NC][NB], const double w, const bool volume) {
-    if (owned && volume) {
-      const R vs = R(0.5 * dt * w);
-      volume_acc<EQ, K, R>(eq, U, vs * R(g.inv_dx), vs * R(g.inv_dy), fin);
-    }
-    if (has) {
-      R t[NC][Q];
-      // right trace: face lx of row ly - 1 (left side); also the exterior
-      // trace of a transmissive right boundary
-      if (ly >= 1 && ly <= nay && lx <= nax) {
-        trace_x<+1, EQ, K, R>(U, t);
+#pragma unroll 1
+      for (int st = 2; st < a.s; ++st) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int p = 0; p < Q; ++p) {
-            tR[c * Q + p][ly - 1][lx] = t[c][p];
-            if (br == CRKDG_BC_TRANSMISSIVE) tL[c * Q + p][ly - 1][lx] = t[c][p];
-          }
-      }
-      if (ly >= 1 && ly <= nay && lx >= 1) {
-        trace_x<-1, EQ, K, R>(U, t);
+          for (int b = 0; b < NB; ++b) acc[c][b] = un[c][b];
+        loc_acc<EQ, K, R>(eq, u, R(-dt * a.a_sub[st]), R(g.inv_dx), R(g.inv_dy), acc);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int p = 0; p < Q; ++p) {
-            tL[c * Q + p][ly - 1][lx - 1] = t[c][p];
-            if (bl == CRKDG_BC_TRANSMISSIVE) tR[c * Q + p][ly - 1][lx - 1] = t[c][p];
-          }
-      }
-      if (lx >= 1 && lx <= nax && ly <= nay) {
-        trace_y<+1, EQ, K, R>(U, t);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int p = 0; p < Q; ++p) {
-            tT[c * Q + p][ly][lx - 1] = t[c][p];
-            if (bt == CRKDG_BC_TRANSMISSIVE) tB[c * Q + p][ly][lx - 1] = t[c][p];
-          }
-      }
-      if (lx >= 1 && lx <= nax && ly >= 1) {
-        trace_y<-1, EQ, K, R>(U, t);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int p = 0; p < Q; ++p) {
-            tB[c * Q + p][ly - 1][lx - 1] = t[c][p];
-            if (bb == CRKDG_BC_TRANSMISSIVE) tT[c * Q + p][ly - 1][lx - 1] = t[c][p];
-          }
+          for (int b = 0; b < NB; ++b) u[c][b] = acc[c][b];
       }
     }
-    // constant Dirichlet data on the boundary faces of this tile
-    if (bl == CRKDG_BC_DIRICHLET || br == CRKDG_BC_DIRICHLET || bb == CRKDG_BC_DIRICHLET ||
-        bt == CRKDG_BC_DIRICHLET) {
+    // the update of an owned cell (higher modes in FP32, averages in FP64)
+    R fin[NC][NB];
+    double a0[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          if (bl == CRKDG_BC_DIRICHLET) tR[c * Q + p][ly - 1][lx - 1] = (R)bc.state[0][c];
-          if (br == CRKDG_BC_DIRICHLET) tL[c * Q + p][ly - 1][lx] = (R)bc.state[1][c];
-          if (bb == CRKDG_BC_DIRICHLET) tT[c * Q + p][ly - 1][lx - 1] = (R)bc.state[2][c];
-          if (bt == CRKDG_BC_DIRICHLET) tB[c * Q + p][ly][lx - 1] = (R)bc.state[3][c];
-        }
+      for (int b = 0; b < NB; ++b)
+        fin[c][b] = share_vol && has && b > 0 ? slot[(c * (NB - 1) + b - 1) * 64 + lx] : un[c][b];
+      a0[c] = owned ? load_avg<NC, NB, LAY>(a.un, g.N, c, cell) : 0.0;
     }
-    __syncthreads();
-    // every face point of the tile once: this lane's stage-weighted sum
-    // G = sum_i b_i F^(i) (equation (g)) gathers the point's flux
-    const bool full = nax == OX && nay == OY;
-    const R wr = R(w);
-#pragma unroll
-    for (int k = 0; k < NPASS; ++k) {
-      const int f = tid + k * NT;
-      if (f >= NFP) break;
-      const bool dy = f >= NXP;
-      const int e = dy ? f - NXP : f;
-      bool valid = full;
-      if (!full) {
-        int fx, fy, p;
-        face_point<OX, OY>(f, NXP, fx, fy, p);
-        valid = dy ? (fx < nax && fy <= nay) : (fx <= nax && fy < nay);
+    if (owned) {
+      if (!share_vol && a.w_first != 0.0) {
+        const R vs = R(0.5 * dt * a.w_first);
+        volume_acc<EQ, K, R>(eq, un, vs * R(g.inv_dx), vs * R(g.inv_dy), fin);
       }
-      if (valid) {
-        const R* A = dy ? tTf : tRf;
-        const R* B = dy ? tBf : tLf;
-        const int cs = dy ? CSY : CSX;
-        R qa[NC], qb[NC], F[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          qa[c] = A[c * cs + e];
-          qb[c] = B[c * cs + e];
-        }
-        eq.num_flux_d(qa, qb, dy, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Gp[k][c] = Gp[k][c] + wr * F[c];
+      if (a.w_last != 0.0) {
+        const R vs = R(0.5 * dt * a.w_last);
+        volume_acc<EQ, K, R>(eq, u, vs * R(g.inv_dx), vs * R(g.inv_dy), fin);
       }
     }
-    __syncthreads();  // the next term overwrites the traces
-  };
-  // (the weights are kernel arguments: the branches are uniform)
-  if (a.w_first != 0.0) final_term(un, a.w_first, !share_vol);
-  if (a.w_last != 0.0) final_term(u, a.w_last, true);
-  // G to LDS over the lower/left traces (each point belongs to one lane)
-#pragma unroll
-  for (int k = 0; k < NPASS; ++k) {
-    const int f = tid + k * NT;
-    if (f >= NFP) break;
-    const bool dy = f >= NXP;
-    const int e = dy ? f - NXP : f;
-    R* A = dy ? tTf : tRf;
-    const int cs = dy ? CSY : CSX;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) A[c * cs + e] = Gp[k][c];
-  }
-  __syncthreads();
-  if (owned) {
-    R FL[NC][Q], FR[NC][Q], GB[NC][Q], GT[NC][Q];
+    // x faces of an owned row: lane L evaluates the face between lanes L - 1
+    // and L (L = 1 .. nax + 1), both final-stage states
+    R Gx[NC][Q];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        FL[c][p] = tR[c * Q + p][ly - 1][lx - 1];
-        FR[c][p] = tR[c * Q + p][ly - 1][lx];
-        GB[c][p] = tT[c * Q + p][ly - 1][lx - 1];
-        GT[c][p] = tT[c * Q + p][ly][lx - 1];
-      }
-    // cell averages in FP64 (equation (avg)): each face's G converted
-    // exactly, so both cells of a face subtract / add the same value
-    const double lxs = -0.5 * dt * g.inv_dx, lys = -0.5 * dt * g.inv_dy;
+      for (int p = 0; p < Q; ++p) Gx[c][p] = R(0);
+    if (rowown) {
+      auto xface = [&](const R(&U)[NC][NB], const R wgt) {
+        R tr[NC][Q], tl[NC][Q];
+        trace_x<+1, EQ, K, R>(U, tr);
+        trace_x<-1, EQ, K, R>(U, tl);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double sx = 0.0, sy = 0.0;
+        for (int p = 0; p < Q; ++p) {
+          R A[NC], B[NC], F[NC];
 #pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        sx += T.W[p] * ((double)FR[c][p] - (double)FL[c][p]);
-        sy += T.W[p] * ((double)GT[c][p] - (double)GB[c][p]);
-      }
-      a0[c] += lxs * sx + lys * sy;
+          for (int c = 0; c < NC; ++c) A[c] = __shfl_up(tr[c][p], 1);
+          if (lx >= 1 && lx <= nax + 1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              if (!lefthas) A[c] = bc.type[0] == CRKDG_BC_TRANSMISSIVE ? tl[c][p] : (R)bc.state[0][c];
+              B[c] = has ? tl[c][p] : (bc.type[1] == CRKDG_BC_TRANSMISSIVE ? A[c] : (R)bc.state[1][c]);
+            }
+            eq.num_flux_d(A, B, false, F);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Gx[c][p] = Gx[c][p] + wgt * F[c];
+          }
+        }
+      };
+      if (a.w_first != 0.0) xface(un, wf);
+      if (a.w_last != 0.0) xface(u, wl);
     }
-    lift_x<EQ, K, R>(FR, FL, R(lxs), fin);
-    lift_y<EQ, K, R>(GT, GB, R(lys), fin);
+    {
+      // the right face's G is the right neighbour lane's left-face G
+      R GR[NC][Q];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) GR[c][p] = __shfl_down(Gx[c][p], 1);
+      if (owned) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          double sx = 0.0;
+#pragma unroll
+          for (int p = 0; p < Q; ++p) sx += T.W[p] * ((double)GR[c][p] - (double)Gx[c][p]);
+          a0[c] += lxs * sx;
+        }
+        lift_x<EQ, K, R>(GR, Gx, R(lxs), fin);
+      }
+    }
+    // top traces to the row's slot (the share read back above), bottom
+    // traces kept for P2
+    R tb[2][NC][Q];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) tb[s2][c][p] = R(0);
+    if (has && colown) {
+      R tt[NC][Q];
+      trace_y<+1, EQ, K, R>(un, tt);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) slot[((0 * NC + c) * Q + p) * 64 + lx] = tt[c][p];
+      trace_y<+1, EQ, K, R>(u, tt);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) slot[((1 * NC + c) * Q + p) * 64 + lx] = tt[c][p];
+      trace_y<-1, EQ, K, R>(un, tb[0]);
+      trace_y<-1, EQ, K, R>(u, tb[1]);
+    }
+    __syncthreads();  // B1: every row's top traces are in its slot
+
+    // ---- P2: the face below each row ----
+    R GB[NC][Q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int p = 0; p < Q; ++p) GB[c][p] = R(0);
+    if (rowvalid && ry >= 1 && colown) {
+      R* below = slots + march_slot(ry - 1) * SM::SLOTF;
+      const bool lowhas = ry - 1 >= 1 || ((j0 - 1 >= 0) || pery);  // row ry - 1 holds cells
+      const bool uphas = has;
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        R G[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) G[c] = R(0);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const R wgt = s2 == 0 ? wf : wl;
+          if (wgt == R(0)) continue;
+          R A[NC], B[NC], F[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            A[c] = lowhas ? below[((s2 * NC + c) * Q + p) * 64 + lx]
+                          : (bc.type[2] == CRKDG_BC_TRANSMISSIVE ? tb[s2][c][p] : (R)bc.state[2][c]);
+            B[c] = uphas ? tb[s2][c][p]
+                         : (bc.type[3] == CRKDG_BC_TRANSMISSIVE ? A[c] : (R)bc.state[3][c]);
+          }
+          eq.num_flux_d(A, B, true, F);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) G[c] = G[c] + wgt * F[c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) GB[c][p] = G[c];
+      }
+      // the lane has read the traces below; its G is the top face of that
+      // row (same lane column of the same slot)
+      if (ry - 1 >= 1) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int p = 0; p < Q; ++p) below[(c * Q + p) * 64 + lx] = GB[c][p];
+      }
+    }
+    __syncthreads();  // B2: every face's G is known
+
+    // ---- P3: rows whose top face is known are stored ----
+    auto finish = [&](R(&f)[NC][NB], double(&av)[NC], const R(&gb)[NC][Q], const R* gtop,
+                      long long cl) {
+      R GT[NC][Q];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int p = 0; p < Q; ++p) GT[c][p] = gtop[(c * Q + p) * 64 + lx];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double sy = 0.0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) sy += T.W[p] * ((double)GT[c][p] - (double)gb[c][p]);
+        av[c] += lys * sy;
+      }
+      lift_y<EQ, K, R>(GT, gb, R(lys), f);
+      store_state<R, NC, NB, LAY>(a.out, g.N, cl, f, av);
+    };
+    if (w == 3) {
+      // the row parked by the previous iteration's wavefront 3: its top face
+      // is the face this iteration's wavefront 0 evaluated
+      if (t > 0) {
+        const int rp = ry - 4;
+        if (rp >= 1 && rp <= nh && colown) {
+          R f[NC][NB], gb[NC][Q];
+          double av[NC];
+          int jp = j0 - 1 + rp;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            av[c] = pa0[c * 64 + lx];
+            f[c][0] = R(0);
+#pragma unroll
+            for (int b = 1; b < NB; ++b) f[c][b] = pfin[(c * (NB - 1) + b - 1) * 64 + lx];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) gb[c][p] = pgb[(c * Q + p) * 64 + lx];
+          }
+          finish(f, av, gb, slots + march_slot(rp) * SM::SLOTF, (long long)jp * g.nx + i);
+        }
+      }
+      if (owned) {  // park this row until the next iteration
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          pa0[c * 64 + lx] = a0[c];
+#pragma unroll
+          for (int b = 1; b < NB; ++b) pfin[(c * (NB - 1) + b - 1) * 64 + lx] = fin[c][b];
+#pragma unroll
+          for (int p = 0; p < Q; ++p) pgb[(c * Q + p) * 64 + lx] = GB[c][p];
+        }
+      }
+    } else if (owned) {
+      finish(fin, a0, GB, slot, cell);
+    }
   }
-  if (owned) store_state<R, NC, NB, LAY>(a.out, g.N, cell, fin, a0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2533,11 +2575,13 @@ bool fused_supported(int eq, int k, int prec, const BCDev& bc) {
 hipError_t launch_fused(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, const FusedArgs& a, hipStream_t s) {
   if (!fused_supported(eq, k, prec, bc) || a.s < 1 || a.s > MAXS) return hipErrorInvalidValue;
-  const dim3 grid(nblk(g.nx, FUSED_OX), nblk(g.ny, FUSED_OY)), blk(FUSED_FX * FUSED_FY);
+  FusedArgs am = a;
+  am.strip = MARCH_H;
+  const dim3 grid(nblk(g.nx, 62), nblk(g.ny, MARCH_H)), blk(256);
   if (k == 1)
-    hipLaunchKernelGGL((k_fused2<Euler2<float>, 1>), grid, blk, 0, s, ph, g, bc, a);
+    hipLaunchKernelGGL((k_fused2<Euler2<float>, 1>), grid, blk, 0, s, ph, g, bc, am);
   else
-    hipLaunchKernelGGL((k_fused2<Euler2<float>, 2>), grid, blk, 0, s, ph, g, bc, a);
+    hipLaunchKernelGGL((k_fused2<Euler2<float>, 2>), grid, blk, 0, s, ph, g, bc, am);
   return hipGetLastError();
 }
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,
