@@ -35,12 +35,16 @@ FN_TARGET = 0.005  # band: false negatives against TVB on validation (1% is the 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 4 SIMDs x 32 FMA lanes x 2 x 2.4 GHz)
-# FP32 vector flops one step needs per cell (Q2 Euler, scheme eq3): the
-# executed flops of the split schedule's inner and final kernels on the
-# 4096 x 1024 shock workload, which evaluate every cell's stages once
-# (profiles/shock_4096x1024_q2_flop_counters.txt: 1.546e10 + 1.612e10 per
-# launch over 4194304 cells)
-STEP_FLOP_PER_CELL = 7529.0
+# FP32 vector flops one step needs per cell (Q2 Euler, scheme eq3), every
+# cell's stages evaluated once and u^n's volume integral shared by the first
+# inner stage and the final stage: I + F, where I = 3686 is the inner-stage
+# kernel's count per cell (1.546e10 per launch over 4194304 lanes) and F = 2862
+# the one-pass kernel's final-stage part, from its 2.986e10 per launch over
+# 67 strips x 64 lanes x (1024 full rows x (I + F) + 70 strip-end rows x I)
+# (profiles/shock_4096x1024_q2_flop_counters.txt; the split schedule, which
+# evaluates u^n's volume integral twice and the halo's traces again, executes
+# 7529 per cell)
+STEP_FLOP_PER_CELL = 6548.0
 
 
 def algorithmic_bytes(cls, state_bytes, stage_bytes, ncells, stages_final, scheme="crkdg"):
@@ -174,9 +178,15 @@ def train_indicator(K, ML):
     Xva, yva = cat(va1[1:] + va2[1:])
     t1 = time.perf_counter()
     P, info = ML.train(Xtr, ytr, epochs=10, batch=4096, seed=0)
-    lo, hi = ML.choose_band(P, Xva, yva, fn_target=FN_TARGET)
-    rv = ML.rates(P, Xva, yva, lo, hi)
-    rv2 = ML.rates(P, *cat(va2[1:]), lo, hi)
+    lo0, hi0 = ML.choose_band(P, Xva, yva, fn_target=FN_TARGET)
+    # last round: the band on validation runs in the form of use (FP32 bulk)
+    # limited by this network with that band, where its states come from
+    va3 = [ML.generate(range(2200, 2202), n=4, family="shock", policy=(P, lo0, hi0),
+                       sample_seed=30, precision=K.FP32_MIXED)]
+    Xva3, yva3 = cat(va3)
+    lo, hi = ML.choose_band(P, Xva3, yva3, fn_target=FN_TARGET)
+    rv = ML.rates(P, Xva3, yva3, lo, hi)
+    rv2 = ML.rates(P, Xva, yva, lo, hi)
     rq = ML.rates(P, *cat([va1[0], va2[0]]), lo, hi)
     t2 = time.perf_counter()
     return P, lo, hi, {
@@ -185,15 +195,73 @@ def train_indicator(K, ML):
                  "T=0.25; seeds 2100-2103 at 4096x1024, 400 steps), limited by the TVB test; "
                  "pass 2: the same shock runs and quadrant seeds 0-15 limited by the pass-1 "
                  "indicator; labels always the FP64 TVB test, M=50",
-        "validation_sets": "band: shock seeds 2200-2201 at 1024x256 and 2200 at 4096x1024 "
-                           "(400 steps), both policies; quadrant seeds 64-71 reported with the "
-                           "same band",
+        "validation_sets": "band: shock seeds 2200-2201 at 1024x256 in FP32 bulk, limited by "
+                           "the trained network with a first band chosen on the FP64 shock "
+                           "validation runs (2200-2201 at 1024x256, 2200 at 4096x1024 for 400 "
+                           "steps, both policies); quadrant seeds 64-71 reported with the same "
+                           "band",
+        "band_round2": [lo0, hi0],
         "fn_target": FN_TARGET, "validation_quadrant": rq,
         "samples": int(len(ytr)), "positives": int(ytr.sum()),
         "runs_stopped_nonphysical": sorted(set(rep.get("stopped", []))),
         "adam_steps": info["steps"], "epochs": 10, "batch": 4096,
-        "tau_lo": lo, "tau_hi": hi, "validation": rv, "validation_on_policy": rv2,
+        "tau_lo": lo, "tau_hi": hi, "validation": rv, "validation_fp64_runs": rv2,
         "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)}
+
+
+def c4_study(K, ML, train_seeds=range(0, 64), val_seeds=range(64, 80), test_seeds=range(80, 96),
+             n_test=1024):
+    """the four-quadrant protocol of the learned indicator: training data from
+    FP64 TVB runs of seeds 0-63 at 256^2 and 512^2, the band chosen on
+    validation seeds 64-79 at 512^2 (runs limited by TVB, then by the network
+    with that band), and the held-out seeds 80-95 at 1024^2 run twice in FP64,
+    limited by TVB and by the network with the TVB fallback band; errors of
+    both against an FP64 TVB run at 2048^2."""
+    t0 = time.perf_counter()
+    rep = {}
+    X1, y1 = ML.generate(train_seeds, n=256, report=rep)
+    log(f"c4 study: training runs at 256^2 done, {time.perf_counter() - t0:.0f} s")
+    X2, y2 = ML.generate(train_seeds, n=512, sample_seed=1)
+    log(f"c4 study: training runs at 512^2 done, {time.perf_counter() - t0:.0f} s")
+    Xtr, ytr = np.concatenate([X1, X2]), np.concatenate([y1, y2])
+    P, info = ML.train(Xtr, ytr, epochs=10, batch=4096, seed=0)
+    log(f"c4 study: trained, {time.perf_counter() - t0:.0f} s")
+    Xva, yva = ML.generate(val_seeds, n=512, sample_seed=2)
+    lo0, hi0 = ML.choose_band(P, Xva, yva, fn_target=FN_TARGET)
+    log(f"c4 study: first band ({lo0:.4g}, {hi0:.4g}), {time.perf_counter() - t0:.0f} s")
+    Xvp, yvp = ML.generate(val_seeds, n=512, sample_seed=3, policy=(P, lo0, hi0))
+    lo, hi = ML.choose_band(P, Xvp, yvp, fn_target=FN_TARGET)
+    log(f"c4 study: {len(ytr)} training samples, band ({lo:.4g}, {hi:.4g}), "
+        f"{time.perf_counter() - t0:.0f} s")
+    rows, stopped = [], []
+    for seed in test_seeds:
+        r = ML.compare_with_tvb("quadrant", seed, n_test, P, lo, hi)
+        if "stopped" in r:
+            stopped.append(seed)
+            log(f"c4 seed {seed}: the {r['stopped']} run left the physical set")
+            continue
+        rows.append(r)
+        log(f"c4 seed {seed} ({time.perf_counter() - t0:.0f} s): "
+            f"{json.dumps({k: r[k] for k in ('tvb', 'learned')})}")
+    pos = sum(r["learned"]["tvb_positives_sampled"] for r in rows)
+    agg = {
+        "fn_rate_vs_tvb": sum(r["learned"]["fn_rate_vs_tvb"] * r["learned"]["tvb_positives_sampled"]
+                              for r in rows) / max(1, pos),
+        "fp_rate_vs_tvb_mean": float(np.mean([r["learned"]["fp_rate_vs_tvb"] for r in rows])),
+        "L1_ratio_mean": float(np.mean([r["learned"]["L1"] / r["tvb"]["L1"] for r in rows])),
+        "L2_ratio_mean": float(np.mean([r["learned"]["L2"] / r["tvb"]["L2"] for r in rows])),
+        "limit_ms_tvb": float(np.mean([r["tvb"]["limit_ms_per_step"] for r in rows])),
+        "limit_ms_learned": float(np.mean([r["learned"]["limit_ms_per_step"] for r in rows])),
+        "flagged_tvb": float(np.mean([r["tvb"]["flagged_fraction"] for r in rows])),
+        "flagged_learned": float(np.mean([r["learned"]["flagged_fraction"] for r in rows])),
+        "fallback": float(np.mean([r["learned"]["fallback_fraction"] for r in rows])),
+    }
+    return {"train": "quadrant seeds 0-63 at 256^2 and 512^2, FP64 TVB labels",
+            "samples": int(len(ytr)), "positives": int(ytr.sum()),
+            "band": [lo, hi], "band_tvb_limited_validation": [lo0, hi0],
+            "validation": ML.rates(P, Xvp, yvp, lo, hi), "test_mesh": f"{n_test}^2",
+            "tested_seeds": len(rows), "stopped_nonphysical": stopped, "aggregate": agg,
+            "per_seed": rows, "seconds": round(time.perf_counter() - t0, 1)}
 
 
 def dmr_run(K, k, nx, ny, precision, rkdg, T=0.2, M=50.0, cfl=0.1):
@@ -412,6 +480,9 @@ def main():
                     help="profiling runs: only the degree-4 Fehlberg runs (prints their JSON)")
     ap.add_argument("--dmr", action="store_true",
                     help="also run the double Mach reflection at 1920x480 (Q1, Q2) to t = 0.2")
+    ap.add_argument("--c4-study-only", action="store_true",
+                    help="the learned indicator's four-quadrant protocol (train 0-63, validate "
+                         "64-79, test 80-95 at 1024^2 against TVB; prints its JSON)")
     ap.add_argument("--dmr-only", action="store_true",
                     help="profiling runs: only the double Mach reflection study (prints its JSON)")
     ap.add_argument("--indicator", default=None,
@@ -434,6 +505,14 @@ def main():
 
     if args.dmr_only:
         print(json.dumps({"double_mach_reflection": dmr_study(K)}), flush=True)
+        return
+    if args.c4_study_only:
+        res = c4_study(K, ML)
+        try:
+            write_detail(res, args.detail)
+        except OSError as e:
+            log(f"could not write {args.detail}: {e}")
+        print(json.dumps({k: v for k, v in res.items() if k != "per_seed"}), flush=True)
         return
     if args.fehlberg_only:
         print(json.dumps({"fehlberg_k4": fehlberg_study(K)}), flush=True)
@@ -477,7 +556,7 @@ def main():
     # (not in counter runs: their one large copy is the traffic calibration)
     copy_gbs = None if args.calibrate_copy else round(stream_copy_gbs(), 1)
     plain = forms["fp64 + TVB"]
-    tvb32 = forms["fp32-bulk + TVB"]
+    tvb32 = forms["fp32-bulk fused + TVB"]
     other = forms[other_name]
     workload = (f"2D Euler Mach-3 shock into a smoothed density field, {head['nx']}x{head['ny']} "
                 f"Q2 cells on [0,4]x[0,1], cRKDG scheme eq3, Lax-Friedrichs flux, final-stage "
@@ -532,7 +611,9 @@ def main():
         "fp64_plain": {"value": plain["value"], "ms_per_step": round(plain["ms_per_step"], 5),
                        "roofline": {k: plain["roofline"][k] for k in ("kernel", "achieved", "frac")},
                        "kernels": short_kernels(plain["kernels"])},
-        "fp32_bulk_tvb": {"value": tvb32["value"], "ms_per_step": round(tvb32["ms_per_step"], 5)},
+        "fp32_bulk_fused_tvb": {"value": tvb32["value"],
+                                "ms_per_step": round(tvb32["ms_per_step"], 5),
+                                "limit_ms": round(tvb32["kernels"]["limit"]["ms_per_launch"], 5)},
         "split_schedule": {"form": other_name, "value": other["value"],
                            "ms_per_step": round(other["ms_per_step"], 5),
                            "kernels": short_kernels(other["kernels"]),

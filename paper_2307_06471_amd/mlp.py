@@ -52,7 +52,8 @@ def shock_solver(seed, scale, precision=K.FP64):
 
 
 def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample_seed=0,
-             report=None, family="quadrant", max_steps=None, max_pos=20000, policy=None):
+             report=None, family="quadrant", max_steps=None, max_pos=20000, policy=None,
+             precision=K.FP64):
     """features X (float32 [S, 12]) and TVB labels y (uint8 [S]) from FP64
     TVB runs with the given seeds, sampled at about `samples` evenly spaced
     steps.
@@ -70,6 +71,10 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
     Per sampled step at most max_pos positives are kept, and negatives are
     subsampled to neg_ratio per positive (at least 256).
 
+    precision: the form the runs step in (the limiter's tests are FP64 in
+    every form, so the labels are the FP64 TVB decisions on the run's own
+    states).
+
     Some random quadrant states (strong collisions of low-pressure gas) drive
     a cell average out of the physical set, which neither the TVB limiter nor
     the positivity safeguard can repair; such a run stops there and keeps the
@@ -81,14 +86,14 @@ def generate(seeds, n=128, samples=20, t_frac=0.25, M=50.0, neg_ratio=10, sample
     rng = np.random.default_rng(sample_seed)
     for seed in seeds:
         if family == "quadrant":
-            s, cfg = quadrant_solver(seed, n)
+            s, cfg = quadrant_solver(seed, n, precision=precision)
             s.crkdg_limit(M)  # the projected jumps overshoot
             smax = s.crkdg_max_wavespeed()          # sum over directions of speed / h
             h = (cfg["box"][1] - cfg["box"][0]) / n
             T = t_frac / (smax * h / 2.0)
             nsteps = int(math.ceil(T / (cfg["cfl"] / smax)))
         elif family == "shock":
-            s, cfg = shock_solver(seed, n)
+            s, cfg = shock_solver(seed, n, precision=precision)
             s.crkdg_limit(M)
             T = cfg["T"]
             nsteps = int(math.ceil(T / (cfg["cfl"] / s.crkdg_max_wavespeed())))
