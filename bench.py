@@ -83,9 +83,10 @@ def shock_mesh(K, W, cfg, theta, precision):
                        precision=precision)
 
 
-def make_solver(K, W, scale=1, precision=0, field_grid=None, seed=2000):
+def make_solver(K, W, scale=1, precision=0, field_grid=None, seed=2000, refine=1):
     import torch
     cfg = W.config("c5", scale=scale)
+    cfg["nx"], cfg["ny"] = cfg["nx"] * refine, cfg["ny"] * refine
     params, xi = W.shock_problem(seed, cfg["nx"], cfg["ny"], field_grid=field_grid)
     s = K.Solver(shock_mesh(K, W, cfg, params[0], precision), cfg["k"], K.FLUX_LLF, 3)
     s.crkdg_project(K.IC_SHOCK, params, aux=torch.from_numpy(xi).cuda())
@@ -483,6 +484,10 @@ def main():
     ap.add_argument("--c4-study-only", action="store_true",
                     help="the learned indicator's four-quadrant protocol (train 0-63, validate "
                          "64-79, test 80-95 at 1024^2 against TVB; prints its JSON)")
+    ap.add_argument("--full-size-study", action="store_true",
+                    help="the shock workload at full size (4096x1024) for seed 2000: FP64 + TVB, "
+                         "its 1e-7 control and the fused FP32-bulk forms against FP64 + TVB at "
+                         "8192x2048 (prints its JSON; needs --indicator or trains one)")
     ap.add_argument("--dmr-only", action="store_true",
                     help="profiling runs: only the double Mach reflection study (prints its JSON)")
     ap.add_argument("--indicator", default=None,
@@ -530,6 +535,19 @@ def main():
         log(f"indicator trained: {mlp_info['samples']} samples, band ({lo:.4g}, {hi:.4g}), "
             f"validation {mlp_info['validation']}")
         mlp = (P, lo, hi)
+
+    if args.full_size_study:
+        if mlp is None:
+            sys.exit("--full-size-study needs the learned indicator (drop --no-mlp)")
+        res = equal_error(K, W, 1, mlp, seeds=(2000,),
+                          forms=("fp64 + TVB", "fp64 + TVB, perturbed 1e-7",
+                                 "fp32-bulk fused + TVB", "fp32-bulk fused + MLP"))
+        try:
+            write_detail(res, args.detail)
+        except OSError as e:
+            log(f"could not write {args.detail}: {e}")
+        print(json.dumps({k: v for k, v in res.items() if k != "per_seed"}), flush=True)
+        return
 
     forms = {}
     F, S = K.SCHED_FUSED, K.SCHED_SPLIT
@@ -725,7 +743,7 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg", repeats=0, schedul
         roof["traffic_over_algorithmic"] = round(traffic / by, 3)
     if dom == "fused" and cfg["k"] == 2:
         # the one-pass step does all of a step's arithmetic for 2S bytes per
-        # cell (23.5 flop/B, above the FP32 ridge of 19.7 flop/B): ALU-bound
+        # cell (20.5 flop/B, above the FP32 ridge of 19.7 flop/B): ALU-bound
         fl = STEP_FLOP_PER_CELL * s.ncells
         tf = fl / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS,
@@ -741,7 +759,8 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg", repeats=0, schedul
             "cells": s.ncells, "dofs": dofs, "nx": cfg["nx"], "ny": cfg["ny"]}
 
 
-def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), samples=10):
+def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), samples=10,
+                seeds=None, forms=None):
     """the shock workload with cell counts divided by `scale`, run to T = 0.25
     by FP64 + TVB, the original RKDG (SSP-RK3, limiter every stage, FP64),
     FP32-inner + TVB, FP32-bulk + TVB, FP32-bulk + learned indicator and the
@@ -754,16 +773,18 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
     T.  A control run (FP64 + TVB from the initial state scaled by
     1 + 1e-7 noise, about the size of FP32 rounding) measures that spread.
     At about `samples` steps of the learned-indicator run its decisions are
-    compared with the FP64 TVB test on the same (pre-limiter) state."""
+    compared with the FP64 TVB test on the same (pre-limiter) state.
+    `seeds` and `forms` (names from the list below) narrow the study."""
     import torch
     P, lo, hi = mlp
     T = checkpoints[-1]
     coarse = W.config("c5", scale)
     grid = (coarse["nx"], coarse["ny"])  # the reference sees the same initial density field
 
-    def run(seed, scale_, precision, indicator, at_checkpoint, rates=False, perturb=False,
+    def run(seed, refine, precision, indicator, at_checkpoint, rates=False, perturb=False,
             scheme="crkdg"):
-        s, cfg, params, xi = make_solver(K, W, scale_, precision, field_grid=grid, seed=seed)
+        s, cfg, params, xi = make_solver(K, W, scale, precision, field_grid=grid, seed=seed,
+                                         refine=refine)
         s.crkdg_set_schedule(K.SCHED_FUSED if scheme == "crkdg-fused" else K.SCHED_SPLIT)
         if perturb:
             u = s.crkdg_get_state()
@@ -779,8 +800,11 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
         tot = {"flagged": 0, "fallback": 0, "cells": 0, "tvb_pos": 0, "fn": 0, "fp": 0,
                "sampled": 0}
         nsteps_est = None
-        t0 = time.perf_counter()
+        t0 = tlog = time.perf_counter()
         while ci < len(checkpoints):
+            if time.perf_counter() - tlog > 30.0:
+                tlog = time.perf_counter()
+                log(f"    {s.mesh.nx}x{s.mesh.ny} seed {seed}: step {n}, t = {t:.5f}")
             target = checkpoints[ci]
             dt = min(cfg["cfl"] / s.crkdg_max_wavespeed(), target - t)
             if nsteps_est is None:
@@ -817,7 +841,9 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
         torch.cuda.synchronize()
         return s, n, tot, time.perf_counter() - t0
 
-    seeds = (2000, 2001, 2002, 2003, 2004, 2005) if full else (2000, 2001, 2002)
+    if seeds is None:
+        seeds = (2000, 2001, 2002, 2003, 2004, 2005) if full else (2000, 2001, 2002)
+    only = forms
     forms = (("fp64 + TVB", K.FP64, None, False, "crkdg"),
              ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True, "crkdg"),
              ("fp32-bulk + TVB", K.FP32_MIXED, None, False, "crkdg"),
@@ -827,10 +853,13 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
                   ("fp32-inner + TVB", K.FP32_INNER, None, False, "crkdg"),
                   ("fp32-increments + TVB", K.FP32_INCREMENTS, None, False, "crkdg"),
                   ("fp32-increments + MLP", K.FP32_INCREMENTS, mlp, False, "crkdg"))
+    if only is not None:
+        forms = tuple(f for f in forms + (("fp32-bulk fused + TVB", K.FP32_MIXED, None, False,
+                                           "crkdg-fused"),) if f[0] in only)
     per_seed = {}
     for seed in seeds:
         snaps = []
-        ref, nref, _, tref = run(seed, max(1, scale // 2), K.FP64, None,
+        ref, nref, _, tref = run(seed, 2, K.FP64, None,
                                  lambda ci, s: snaps.append(s.crkdg_get_state()))
         log(f"equal-error seed {seed}: reference {ref.mesh.nx}x{ref.mesh.ny}, {nref} steps, "
             f"{tref:.1f} s")
@@ -849,7 +878,7 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
                 else:
                     ref.crkdg_set_state(snaps[ci])  # keep ref for the next checkpoint
 
-            s, n, tot, el = run(seed, scale, prec, ind, at_cp, rates=ind is not None,
+            s, n, tot, el = run(seed, 1, prec, ind, at_cp, rates=ind is not None,
                                 perturb=pert, scheme=sch)
             r = {"L1": [e[0] for e in errs], "L2": [e[1] for e in errs], "steps": n,
                  "flagged_fraction": None if sch == "rkdg3" else tot["flagged"] / tot["cells"],
