@@ -553,7 +553,8 @@ def main():
     F, S = K.SCHED_FUSED, K.SCHED_SPLIT
     plan = [("fp32-bulk fused + MLP", K.FP32_MIXED, mlp, F),
             ("fp32-bulk + MLP", K.FP32_MIXED, mlp, S)] if mlp is not None else []
-    plan += [("fp64 + TVB", K.FP64, None, S), ("fp32-bulk fused + TVB", K.FP32_MIXED, None, F),
+    plan += [("fp64 + TVB", K.FP64, None, F), ("fp64 split + TVB", K.FP64, None, S),
+             ("fp32-bulk fused + TVB", K.FP32_MIXED, None, F),
              ("fp32-bulk + TVB", K.FP32_MIXED, None, S)]
     if args.all_forms:
         plan += [("fp32-inner + TVB", K.FP32_INNER, None, S)]
@@ -627,8 +628,10 @@ def main():
         "kernels": short_kernels(head["kernels"]),
         "repeats_ms_per_step": [round(v, 5) for v in head["repeat_ms_per_step"]],
         "fp64_plain": {"value": plain["value"], "ms_per_step": round(plain["ms_per_step"], 5),
-                       "roofline": {k: plain["roofline"][k] for k in ("kernel", "achieved", "frac")},
-                       "kernels": short_kernels(plain["kernels"])},
+                       "roofline": {k: plain["roofline"][k]
+                                    for k in ("kernel", "bound", "achieved", "unit", "frac")},
+                       "kernels": short_kernels(plain["kernels"]),
+                       "split_ms_per_step": round(forms["fp64 split + TVB"]["ms_per_step"], 5)},
         "fp32_bulk_fused_tvb": {"value": tvb32["value"],
                                 "ms_per_step": round(tvb32["ms_per_step"], 5),
                                 "limit_ms": round(tvb32["kernels"]["limit"]["ms_per_launch"], 5)},
@@ -743,11 +746,13 @@ def run_form(K, W, args, precision, mlp=None, scheme="crkdg", repeats=0, schedul
         roof["traffic_over_algorithmic"] = round(traffic / by, 3)
     if dom == "fused" and cfg["k"] == 2:
         # the one-pass step does all of a step's arithmetic for 2S bytes per
-        # cell (20.5 flop/B, above the FP32 ridge of 19.7 flop/B): ALU-bound
+        # cell: 20.5 flop/B in the FP32-bulk form (the FP32 ridge is 19.7
+        # flop/B), 11.4 flop/B in FP64 (ridge 9.8 flop/B): ALU-bound
         fl = STEP_FLOP_PER_CELL * s.ncells
+        peak = FP64_PEAK_TFLOPS if precision == K.FP64 else FP32_PEAK_TFLOPS
         tf = fl / (prof[dom][0] / prof[dom][1] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+        roof = {"bound": "alu", "achieved": round(tf, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": traffic,
                 "kernel": dom, "flop_per_launch": fl, "bytes_per_launch": by,
                 "hbm_achieved_GBs": round(achieved, 1),
                 "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
@@ -844,8 +849,8 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
     if seeds is None:
         seeds = (2000, 2001, 2002, 2003, 2004, 2005) if full else (2000, 2001, 2002)
     only = forms
-    forms = (("fp64 + TVB", K.FP64, None, False, "crkdg"),
-             ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True, "crkdg"),
+    forms = (("fp64 + TVB", K.FP64, None, False, "crkdg-fused"),
+             ("fp64 + TVB, perturbed 1e-7", K.FP64, None, True, "crkdg-fused"),
              ("fp32-bulk + TVB", K.FP32_MIXED, None, False, "crkdg"),
              ("fp32-bulk fused + MLP", K.FP32_MIXED, mlp, False, "crkdg-fused"))
     if full:
@@ -860,7 +865,8 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
     for seed in seeds:
         snaps = []
         ref, nref, _, tref = run(seed, 2, K.FP64, None,
-                                 lambda ci, s: snaps.append(s.crkdg_get_state()))
+                                 lambda ci, s: snaps.append(s.crkdg_get_state()),
+                                 scheme="crkdg-fused")
         log(f"equal-error seed {seed}: reference {ref.mesh.nx}x{ref.mesh.ny}, {nref} steps, "
             f"{tref:.1f} s")
         res = {}

@@ -192,22 +192,24 @@ int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
  * u^{n+1}; no stage state goes through memory.
  *   CRKDG_SCHED_SPLIT  inner-stage pass, then final-stage pass (any case);
  *   CRKDG_SCHED_FUSED  the one-pass step, for 2D Euler in the FP32-bulk
- *                      form with k = 1 or 2, constant boundary data
+ *                      or the FP64 form with k = 1 or 2, constant boundary
+ *                      data
  *                      (periodic, transmissive, time-independent Dirichlet)
  *                      and a subdiagonal tableau whose weights are nonzero
  *                      only on the first and last stages (schemes (eq:2),
  *                      (eq:3), forward Euler).
- * The results of the two schedules agree to the rounding of FP32 arithmetic
- * (the fused step sums the stage-weighted face fluxes in FP32, the split
- * final stage in FP64; both convert each face's sum exactly into the FP64
- * cell-average update, so both conserve).
+ * The results of the two schedules agree to the rounding of the form's
+ * arithmetic (in the FP32-bulk form the fused step sums the stage-weighted
+ * face fluxes in FP32, the split final stage in FP64; both convert each
+ * face's sum exactly into the FP64 cell-average update, so both conserve).
  * crkdg_set_schedule returns CRKDG_EUNSUPPORTED for CRKDG_SCHED_FUSED on a
  * handle that does not meet these conditions, CRKDG_EINVAL for an unknown
  * value.  crkdg_get_schedule returns the schedule the next step takes (a
  * later crkdg_set_tableau can make a fused handle fall back to the split
  * schedule).  New handles start with CRKDG_SCHED_FUSED: every step that the
  * one-pass kernel can take runs there (on the 4096 x 1024 Q2 shock workload
- * it takes 0.68 ms against 0.93 ms for the two split passes). */
+ * it takes 0.65 ms against 0.92 ms for the two split passes in the FP32-bulk
+ * form, 1.66 ms against 2.26 ms in FP64). */
 #define CRKDG_SCHED_SPLIT 0
 #define CRKDG_SCHED_FUSED 1
 int crkdg_set_schedule(crkdg_state* st, int sched);

@@ -951,12 +951,22 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 // (46 the same; 14 and 62 slower: more recomputed rows, or too few
 // workgroups for an even last wave), and two wavefronts per SIMD: the kernel
 // needs 221 registers, and forcing three (168 registers) spills 53 values and
-// ran 1.8x slower.
+// ran 1.8x slower.  The FP64 form (Real = double, the same code) needs 419
+// registers (256 VGPRs and 163 AGPRs) and 104 KB of LDS: one wavefront per
+// SIMD, and still 27% faster than the split FP64 kernels.  Strip order: workgroups reach the eight XCDs in turn, so
+// in launch order neighbouring strips land in different L2s and each fetches
+// the 128-byte lines at their shared edge (a 64-cell row of FP32 modes starts
+// one cell before a line): u^n was read 1.63 times.  Runs of 16 neighbouring
+// strips per XCD read it 1.12 times and run 1% faster; one contiguous block
+// per XCD read it 1.09 times but ran 4% slower.
 #ifndef MARCH_H
 #define MARCH_H 30
 #endif
 #ifndef MARCH_OCC
 #define MARCH_OCC 2
+#endif
+#ifndef MARCH_XCD
+#define MARCH_XCD 16
 #endif
 
 template <class R, int NC, int Q>
@@ -977,7 +987,8 @@ __device__ __forceinline__ int march_slot(int ry) {
 }
 
 template <class EQ, int K>
-__global__ __launch_bounds__(256, MARCH_OCC) void k_fused2(PhysDev ph, Geo g, BCDev bc, FusedArgs a) {
+__global__ __launch_bounds__(256, sizeof(typename EQ::Real) == 8 ? 1 : MARCH_OCC) void k_fused2(
+    PhysDev ph, Geo g, BCDev bc, FusedArgs a) {
   using R = typename EQ::Real;
   constexpr int LAY = StepLayout<EQ>::value;
   constexpr int Q = K + 1, NC = EQ::NC, NB = Q * Q;
@@ -990,7 +1001,23 @@ __global__ __launch_bounds__(256, MARCH_OCC) void k_fused2(PhysDev ph, Geo g, BC
   R* slots = reinterpret_cast<R*>(smem + SM::PARK_BYTES);           // [NSLOT][SLOTF]
 
   const int lx = threadIdx.x & 63, w = threadIdx.x >> 6;
+#if MARCH_XCD
+  // workgroups go to the eight XCDs in turn; give each XCD runs of
+  // MARCH_XCD neighbouring strips, so that the lines at their shared edges
+  // and ring columns meet in the same L2
+  int bxs, bys;
+  {
+    const unsigned gx = gridDim.x, tot = gx * gridDim.y;
+    const unsigned w = blockIdx.x + blockIdx.y * gx;
+    constexpr unsigned L = MARCH_XCD, BLK = 8u * L;
+    const unsigned lg = w < (tot / BLK) * BLK ? (w / BLK) * BLK + (w & 7u) * L + (w >> 3) % L : w;
+    bxs = (int)(lg % gx);
+    bys = (int)(lg / gx);
+  }
+  const int i0 = bxs * 62, j0 = bys * a.strip;
+#else
   const int i0 = blockIdx.x * 62, j0 = blockIdx.y * a.strip;
+#endif
   const int nax = min(62, g.nx - i0), nh = min(a.strip, g.ny - j0);
   const int nrows = nh + 2, niter = (nrows + 3) / 4;
   const EQ eq = make_eq<EQ>(ph);
@@ -2570,7 +2597,8 @@ hipError_t launch_final(int eq, int k, int prec, const PhysDev& ph, const Geo& g
   }
 }
 bool fused_supported(int eq, int k, int prec, const BCDev& bc) {
-  return eq == EQ_EULER2 && prec == PBULK && (k == 1 || k == 2) && bc.exact <= 0;
+  return eq == EQ_EULER2 && (prec == PBULK || prec == P64) && (k == 1 || k == 2) &&
+         bc.exact <= 0;
 }
 hipError_t launch_fused(int eq, int k, int prec, const PhysDev& ph, const Geo& g,
                         const BCDev& bc, const FusedArgs& a, hipStream_t s) {
@@ -2578,10 +2606,16 @@ hipError_t launch_fused(int eq, int k, int prec, const PhysDev& ph, const Geo& g
   FusedArgs am = a;
   am.strip = MARCH_H;
   const dim3 grid(nblk(g.nx, 62), nblk(g.ny, MARCH_H)), blk(256);
-  if (k == 1)
+  if (prec == P64) {
+    if (k == 1)
+      hipLaunchKernelGGL((k_fused2<Euler2<double>, 1>), grid, blk, 0, s, ph, g, bc, am);
+    else
+      hipLaunchKernelGGL((k_fused2<Euler2<double>, 2>), grid, blk, 0, s, ph, g, bc, am);
+  } else if (k == 1) {
     hipLaunchKernelGGL((k_fused2<Euler2<float>, 1>), grid, blk, 0, s, ph, g, bc, am);
-  else
+  } else {
     hipLaunchKernelGGL((k_fused2<Euler2<float>, 2>), grid, blk, 0, s, ph, g, bc, am);
+  }
   return hipGetLastError();
 }
 hipError_t launch_loc(int eq, int k, const PhysDev& ph, const Geo& g, const double* in,

@@ -280,8 +280,8 @@ def test_noalloc_gradient_argument_checks():
 
 def test_schedule_selection_is_host_logic():
     """the fused schedule is accepted only where the fused kernel applies
-    (2D Euler, FP32-bulk, k = 1 or 2, constant boundary data, weights on the
-    first and last stage only); no GPU needed"""
+    (2D Euler, FP32-bulk or FP64, k = 1 or 2, constant boundary data, weights
+    on the first and last stage only); no GPU needed"""
     L = K.lib()
 
     def handle(k=2, stages=3, precision=K.FP32_MIXED, bc=(1, 1, 1, 1), bc_exact=0, dim=2):
@@ -297,14 +297,15 @@ def test_schedule_selection_is_host_logic():
     assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_OK
     assert L.crkdg_get_schedule(h) == K.SCHED_FUSED
     L.crkdg_destroy(h)
-    for kw in (dict(precision=K.FP64), dict(k=3), dict(stages=4),
-               dict(precision=K.FP32_INNER), dict(bc=(2, 1, 2, 2), bc_exact=K.IC_DMR)):
+    for kw in (dict(k=3), dict(stages=4), dict(precision=K.FP32_INNER),
+               dict(precision=K.FP32_INCREMENTS), dict(bc=(2, 1, 2, 2), bc_exact=K.IC_DMR)):
         h = handle(**kw)
         assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT, kw      # falls back by itself
         assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_EUNSUPPORTED, kw
         assert L.crkdg_get_schedule(h) == K.SCHED_SPLIT
         L.crkdg_destroy(h)
-    for kw in (dict(k=1, stages=2), dict(stages=1), dict(bc=(0, 0, 0, 0)), dict(bc=(2, 2, 2, 2))):
+    for kw in (dict(k=1, stages=2), dict(stages=1), dict(bc=(0, 0, 0, 0)), dict(bc=(2, 2, 2, 2)),
+               dict(precision=K.FP64), dict(precision=K.FP64, k=1, stages=2)):
         h = handle(**kw)
         assert L.crkdg_set_schedule(h, K.SCHED_FUSED) == K.CRKDG_OK, kw
         L.crkdg_destroy(h)
