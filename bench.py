@@ -486,8 +486,9 @@ def main():
                          "64-79, test 80-95 at 1024^2 against TVB; prints its JSON)")
     ap.add_argument("--full-size-study", action="store_true",
                     help="the shock workload at full size (4096x1024) for seed 2000: FP64 + TVB, "
-                         "its 1e-7 control and the fused FP32-bulk forms against FP64 + TVB at "
-                         "8192x2048 (prints its JSON; needs --indicator or trains one)")
+                         "its 1e-7 control, the fused FP32-bulk forms and FP32-inner + TVB "
+                         "against FP64 + TVB at 8192x2048 (prints its JSON; needs --indicator "
+                         "or trains one)")
     ap.add_argument("--dmr-only", action="store_true",
                     help="profiling runs: only the double Mach reflection study (prints its JSON)")
     ap.add_argument("--indicator", default=None,
@@ -539,9 +540,10 @@ def main():
     if args.full_size_study:
         if mlp is None:
             sys.exit("--full-size-study needs the learned indicator (drop --no-mlp)")
-        res = equal_error(K, W, 1, mlp, seeds=(2000,),
+        res = equal_error(K, W, 1, mlp, seeds=(2000,), full=True,
                           forms=("fp64 + TVB", "fp64 + TVB, perturbed 1e-7",
-                                 "fp32-bulk fused + TVB", "fp32-bulk fused + MLP"))
+                                 "fp32-bulk fused + TVB", "fp32-bulk fused + MLP",
+                                 "fp32-inner + TVB"))
         try:
             write_detail(res, args.detail)
         except OSError as e:
@@ -925,7 +927,10 @@ def equal_error(K, W, scale, mlp, full=False, checkpoints=(0.05, 0.1, 0.25), sam
             "criterion": "mean over seeds of the density-error ratio to FP64 + TVB at most 1.05",
             "mean_error_ratio_vs_fp64_tvb": ratios, "per_seed": per_seed,
             "verdict": verdict("fp32-bulk fused + MLP"),
-            "verdict_fp32_increments_mlp": verdict("fp32-increments + MLP") if full else None}
+            "verdict_fp32_increments_mlp": (verdict("fp32-increments + MLP")
+                                            if "fp32-increments + MLP" in ratios else None),
+            "verdict_fp32_inner": (verdict("fp32-inner + TVB")
+                                   if "fp32-inner + TVB" in ratios else None)}
 
 
 if __name__ == "__main__":
