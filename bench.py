@@ -265,6 +265,43 @@ def c4_study(K, ML, train_seeds=range(0, 64), val_seeds=range(64, 80), test_seed
             "per_seed": rows, "seconds": round(time.perf_counter() - t0, 1)}
 
 
+def c3_rates(K, W, steps=100, warmup=20):
+    """DOF-updates/s of the scaled density-wave workload (Section 4.1.2's
+    example at 1024^2, Q^3, classical RK4, periodic, no limiter) in FP64 and
+    in the FP32-bulk form: fixed dt (CFL 0.05) from the initial state, 100
+    steps timed with HIP events after 20 warm-up steps"""
+    import torch
+    cfg = W.config("c3")
+    x0, x1, y0, y1 = cfg["box"]
+    out = {}
+    for name, prec in (("fp64", K.FP64), ("fp32_bulk", K.FP32_MIXED)):
+        mesh = K.make_mesh(2, cfg["nx"], cfg["ny"], x0=x0, x1=x1, y0=y0, y1=y1,
+                           equation=K.EQ_EULER, gamma=W.GAMMA, precision=prec)
+        s = K.Solver(mesh, cfg["k"], K.FLUX_LLF, W.RK_STAGES[cfg["tableau"]])
+        s.crkdg_project(K.IC_EULER_WAVE, cfg["ic_params"])
+        dt = torch.full((1,), cfg["cfl"] / s.crkdg_max_wavespeed(), dtype=torch.float64,
+                        device="cuda")
+        for _ in range(warmup):
+            s.crkdg_step_dev(dt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s.stream):
+            e0.record(s.stream)
+            for _ in range(steps):
+                s.crkdg_step_dev(dt)
+            e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        dofs = s.ncells * s.nmodes * s.ncomp
+        out[name] = {"value": dofs / (ms * 1e-3), "ms_per_step": round(ms, 5)}
+        del s
+        torch.cuda.empty_cache()
+    out["workload"] = (f"2D Euler density wave, {cfg['nx']}x{cfg['ny']} Q3, RK4, periodic, "
+                       f"fixed dt (CFL {cfg['cfl']}), no limiter")
+    return out
+
+
 def dmr_run(K, k, nx, ny, precision, rkdg, T=0.2, M=50.0, cfl=0.1):
     """the paper's double Mach reflection (Section 4): projection, one limiter
     pass on the projected jump, then steps to T with dt = cfl / s_max; the
@@ -472,6 +509,8 @@ def main():
                     help="profiling runs only: skip the learned indicator (training and form)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (traffic counter calibration)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the density-wave workload's rates (1024^2 Q3 RK4, FP64 and FP32 bulk)")
     ap.add_argument("--no-rkdg", action="store_true",
                     help="profiling runs only: skip the original-RKDG form")
     ap.add_argument("--fehlberg", action="store_true",
@@ -573,6 +612,10 @@ def main():
     if not args.no_rkdg:
         rk = run_form(K, W, args, K.FP64, None, scheme="rkdg3")
         log(f"fp64 RKDG SSP3 + TVB every stage: {rk['ms_per_step']:.3f} ms/step")
+    c3 = None
+    if not args.no_c3:
+        c3 = c3_rates(K, W)
+        log(f"c3 density wave: {json.dumps(c3)}")
     head = forms[head_name]
     # (not in counter runs: their one large copy is the traffic calibration)
     copy_gbs = None if args.calibrate_copy else round(stream_copy_gbs(), 1)
@@ -590,6 +633,8 @@ def main():
               "warmup": args.warmup, "forms": forms, "stream_copy_GBs": copy_gbs}
     if rk is not None:
         detail["fp64_rkdg_ssp3"] = rk
+    if c3 is not None:
+        detail["c3_density_wave"] = c3
     if mlp is not None:
         detail["mlp"] = mlp_info
     ee = None
@@ -646,6 +691,10 @@ def main():
         "stream_copy_GBs": copy_gbs,
         "detail": args.detail,
     }
+    if c3 is not None:
+        line["c3_density_wave"] = {k: ({"value": v["value"], "ms_per_step": v["ms_per_step"]}
+                                       if isinstance(v, dict) else v) for k, v in c3.items()
+                                   if k != "workload"}
     if rk is not None:
         line["fp64_rkdg_ssp3"] = {"value": rk["value"], "ms_per_step": round(rk["ms_per_step"], 5),
                                   "crkdg_over_rkdg_fp64": round(plain["value"] / rk["value"], 4)}
