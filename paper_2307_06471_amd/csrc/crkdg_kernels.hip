@@ -953,12 +953,13 @@ __global__ __launch_bounds__(FinalTile<typename EQ::Real>::TX * FinalTile<typena
 // needs 221 registers, and forcing three (168 registers) spills 53 values and
 // ran 1.8x slower.  The FP64 form (Real = double, the same code) needs 419
 // registers (256 VGPRs and 163 AGPRs) and 104 KB of LDS: one wavefront per
-// SIMD, and still 27% faster than the split FP64 kernels.  Strip order: workgroups reach the eight XCDs in turn, so
-// in launch order neighbouring strips land in different L2s and each fetches
-// the 128-byte lines at their shared edge (a 64-cell row of FP32 modes starts
-// one cell before a line): u^n was read 1.63 times.  Runs of 16 neighbouring
-// strips per XCD read it 1.12 times and run 1% faster; one contiguous block
-// per XCD read it 1.09 times but ran 4% slower.
+// SIMD, and still 27% faster than the split FP64 kernels.
+// Strip order: workgroups reach the eight XCDs in turn, so in launch order
+// neighbouring strips land in different L2s and each fetches the 128-byte
+// lines at their shared edge (a 64-cell row of FP32 modes starts one cell
+// before a line): u^n was read 1.63 times.  Runs of 16 neighbouring strips
+// per XCD read it 1.12 times and run 1% faster; one contiguous block per XCD
+// read it 1.09 times but ran 4% slower.
 #ifndef MARCH_H
 #define MARCH_H 30
 #endif
