@@ -119,6 +119,36 @@ def test_fused_equals_split_on_the_same_state(K, form):
     assert err < (1e-13 if fp64 else TOL)
 
 
+@pytest.mark.parametrize("form", ["fp32-bulk", "fp64"])
+def test_fused_equals_split_with_remapped_strips(K, form):
+    """1240 x 240 cells: 20 strips x 8 row blocks = 160 workgroups, more than
+    one run of 16 strips per XCD, so the strip order is remapped (and 32
+    workgroups past the last full group of 128 keep launch order); every
+    cell of the one-pass step must equal the split schedule's"""
+    import torch
+    nx, ny = 1240, 240
+    fp64 = form == "fp64"
+    rng = np.random.default_rng(11)
+    u = W.random_euler_modes(rng, 9, nx * ny)
+    if not fp64:
+        u = fp32_modes(u)
+    out = {}
+    for sched in (K.SCHED_SPLIT, K.SCHED_FUSED):
+        s, om = pair(K, nx, ny, (2, 1, 0, 0), 2, 3, K.FP64 if fp64 else None)
+        s.crkdg_set_schedule(sched)
+        s.crkdg_set_state(u)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.crkdg_compute_dt(0.1, dt_dev)
+        for _ in range(2):
+            s.crkdg_step_dev(dt_dev)
+        out[sched] = s.crkdg_get_state()
+    d = np.abs(out[K.SCHED_FUSED] - out[K.SCHED_SPLIT]).max(axis=(0, 1))
+    scale = np.abs(out[K.SCHED_SPLIT]).max()
+    worst = int(np.argmax(d))
+    print(f"[fused] {form} {nx}x{ny}: max rel diff {d.max() / scale:.2e} at cell {worst}", flush=True)
+    assert d.max() / scale < (1e-13 if fp64 else TOL)
+
+
 def test_fused_density_wave_run_and_conservation(K):
     """the density-wave workload (Section 4.1.2 example) on 130 x 20 cells,
     60 steps: within 1e-5 relative L2 of the FP64 oracle, and the FP64 cell
