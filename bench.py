@@ -524,10 +524,13 @@ def main():
                     help="the learned indicator's four-quadrant protocol (train 0-63, validate "
                          "64-79, test 80-95 at 1024^2 against TVB; prints its JSON)")
     ap.add_argument("--full-size-study", action="store_true",
-                    help="the shock workload at full size (4096x1024) for seed 2000: FP64 + TVB, "
+                    help="the shock workload at full size (4096x1024), seed 2000 unless "
+                         "--full-size-seeds says otherwise: FP64 + TVB, "
                          "its 1e-7 control, the fused FP32-bulk forms and FP32-inner + TVB "
                          "against FP64 + TVB at 8192x2048 (prints its JSON; needs --indicator "
                          "or trains one)")
+    ap.add_argument("--full-size-seeds", type=int, nargs="+", default=[2000],
+                    help="seeds of --full-size-study (default 2000)")
     ap.add_argument("--dmr-only", action="store_true",
                     help="profiling runs: only the double Mach reflection study (prints its JSON)")
     ap.add_argument("--indicator", default=None,
@@ -579,7 +582,7 @@ def main():
     if args.full_size_study:
         if mlp is None:
             sys.exit("--full-size-study needs the learned indicator (drop --no-mlp)")
-        res = equal_error(K, W, 1, mlp, seeds=(2000,), full=True,
+        res = equal_error(K, W, 1, mlp, seeds=tuple(args.full_size_seeds), full=True,
                           forms=("fp64 + TVB", "fp64 + TVB, perturbed 1e-7",
                                  "fp32-bulk fused + TVB", "fp32-bulk fused + MLP",
                                  "fp32-inner + TVB"))

@@ -11,6 +11,10 @@
 //              neighbours with opposite signs, so the cell-average update
 //              (equation (avg)) is conservative and done in FP64.
 //   k_final1   the same for 1D meshes.
+//   k_fused2   the whole step in one pass (Section 3.1's compact stencil):
+//              a workgroup walks a strip of 62 columns, recomputes its
+//              one-cell ring's inner stages, evaluates the strip's faces and
+//              writes u^{n+1}; 2D Euler, FP32 bulk or FP64, k = 1, 2.
 //   k_loc      one application of the local operator (materialised path).
 //   k_combine  RK stage combination, out = base + sum_j coef_j X_j (streaming).
 //   k_wave*    dt selection from the cell averages (max reduction).
@@ -21,8 +25,10 @@
 //
 // Precision: the step kernels are templated on the compute type R.  R =
 // double is the plain FP64 method; R = float is the FP32-bulk form, in which
-// the cell averages stay FP64 in memory and in the final update, the stage
-// states of the inner stages are FP32, and the face-flux sums G are FP64.
+// the cell averages stay FP64 in memory and in the final update and the
+// stage states of the inner stages are FP32; the face-flux sums G are FP64
+// in k_final2 and FP32 in k_fused2, each converted exactly into the FP64
+// average update.
 #include <math.h>
 
 #include "crkdg_internal.hpp"
