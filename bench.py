@@ -23,6 +23,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -540,7 +541,8 @@ def main():
     ap.add_argument("--indicator", default=None,
                     help="profiling runs: .npz of a trained indicator, loaded if the file "
                          "exists, else written after training")
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail",
+                    default=os.path.join(tempfile.gettempdir(), "crkdg_bench_detail.json"),
                     help="where the full report goes (the compact line is printed on stdout)")
     args = ap.parse_args()
     if args.equal_error_scale < 2:
