@@ -181,7 +181,12 @@ int crkdg_step(crkdg_state* st, double dt);
  * data the internal time is not advanced.  With them (bc_exact), the time is
  * kept in device memory (the library's workspace): the stages take their
  * boundary data at t + c_i * (*dt_dev), the limiter's ghost averages at the
- * advanced time, and crkdg_get_time reads it back (syncs). */
+ * advanced time, and crkdg_get_time reads it back (syncs).
+ * crkdg_step_dev and crkdg_limit_dt only launch kernels on the bound stream
+ * (no allocation, memset, copy or synchronisation), so a run of them can be
+ * captured in a HIP graph and replayed; the handle alternates between two
+ * state buffers on the host side, so a captured run must hold an even
+ * number of steps. */
 int crkdg_step_dev(crkdg_state* st, const double* dt_dev);
 
 /* Schedule of crkdg_step / crkdg_step_dev.  The compact stencil of Section
